@@ -1,0 +1,712 @@
+"""Plain FP64 CPU oracle of the high-order isothermal GKS step with ALM and IBM body forces.
+
+TEST INFRASTRUCTURE ONLY -- never imported by the product path (see the package docstring).
+
+Everything is written from the paper (arXiv 2603.11102) in its order and notation, whole-array, in
+torch.float64 on the CPU, with no blocking or fusion:
+
+* kinetic model and equilibrium state: Section 2, Eq. (bgk-3d) and the isothermal Maxwellian,
+  lambda = Ma^2 / (2 U_inf^2);
+* finite-volume form: Section 2, Eqs. (semi), (finite), (x_example): 2x2 Gauss points per face;
+* interface distribution f = g0 (1 - tau (a1 u + a2 v + a3 w + A) + A t): Section 2, Eq. (flux),
+  tau = mu / p; microscopic coefficients from the moment system of the Appendix;
+* fifth-order WENO-JS reconstruction, dimension by dimension, to the Gauss points: Section 2;
+* two-stage fourth-order (S2O4) time stepping and the CFL time step: Section 2;
+* actuator line model: Section 3.1, Eqs. (axial-tangential), (Gaussian); truncation at 3 eps and
+  the eps guidance of Section 4.3.1;
+* direct-forcing immersed boundary: Section 3.2, Eqs. (ibm-1), (force-ibm);
+* body-force update after the S2O4 step: Section 3.3;
+* power and thrust coefficients: Section 4.4.1.
+
+Readings where the paper is silent or garbled (implemented identically by the HIP path):
+
+R1  Reconstruction is component-wise on the conservative variables (rho, rho U, rho V, rho W).
+R2  WENO-JS with epsilon = 1e-6 and power 2; the smoothness indicators are the Jiang-Shu integrals
+    of the squared first and second derivatives of each quadratic over the cell.
+R3  Normal direction: WENO face values q^L (left cell) and q^R (right cell); the normal derivative is
+    the face derivative of the cubic matching the four nearest cell averages; C = (q^L + q^R)/2.
+R4  Tangential sweeps: x-faces y then z, y-faces x then z, z-faces x then y. q^L and q^R are taken to
+    the Gauss points by WENO-JS (linear weights re-derived for the Gauss point); the normal
+    derivative and the tangential derivatives of the equilibrium state use the linear quartic
+    (value or derivative) on D and on C.
+R5  g0's macroscopic state Q0 is the kinetic (half-space) average of the left and right Maxwellians.
+R6  The Appendix system is normalised by rho: d = (dQ0/dx)/rho0, and a^1 = d1 - U a^2 - V a^3 - W a^4.
+R7  S2O4: Q* = Q + dt/2 L + dt^2/8 L_t; Q^{n+1} = Q + dt L + dt^2/6 (L_t + 2 L_t(Q*)).
+R8  Body force after the step: (rho U) += dt (G + f_ALM + F_IBM / |Omega|): the printed divisor V-bar is
+    read as the cell volume for the IBM force and f_ALM (already per volume) is added as dt f.
+    Order: G, then ALM, then IBM; the rotor sits at t^{n+1}.
+R9  ALM: force on the fluid is minus the blade force; phi = atan2(U_x, omega r - U_theta); free-stream
+    correction applied once with C_D at the uncorrected angle; rho in L, D is rho_ref; synthetic polar
+    C_L = cl_slope * clamp(alpha, +-clip), C_D = cd0 + cd2 alpha^2 (radians).
+R10 IBM: Peskin 4-point delta, tensor product, in both directions; fixed iteration count; stationary
+    points (v_p = 0); residual reported after the last iteration.
+R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
+    momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
+    U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).
+"""
+from __future__ import annotations
+
+import math
+from functools import lru_cache
+
+import numpy as np
+import torch
+
+F64 = torch.float64
+NG = 3  # ghost layers
+
+__all__ = [
+    "poly_weights", "weno_linear_weights", "smoothness_rules", "WenoControl", "weno_point",
+    "linear_point", "constants", "ghost_fill", "kinetic_average", "maxwellian_moment",
+    "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
+    "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
+]
+
+GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
+
+
+# ================================================================================================
+# polynomial reconstruction from cell averages (definitions)
+# ================================================================================================
+
+def _cell_avg_monomials(offsets, degree):
+    """A[r, p] = average of xi^p over the cell [o_r - 1/2, o_r + 1/2] (unit cell width)."""
+    A = np.zeros((len(offsets), degree + 1))
+    for r, o in enumerate(offsets):
+        for p in range(degree + 1):
+            A[r, p] = ((o + 0.5) ** (p + 1) - (o - 0.5) ** (p + 1)) / (p + 1)
+    return A
+
+
+def poly_weights(offsets, xi, deriv=0):
+    """Weights w such that p^(deriv)(xi) = sum_r w_r qbar_r, where p is the polynomial of degree
+    len(offsets)-1 whose cell averages over the cells at ``offsets`` are qbar (unit cell width)."""
+    offsets = tuple(offsets)
+    deg = len(offsets) - 1
+    A = _cell_avg_monomials(offsets, deg)
+    v = np.zeros(deg + 1)
+    for p in range(deriv, deg + 1):
+        v[p] = math.factorial(p) / math.factorial(p - deriv) * xi ** (p - deriv)
+    return np.linalg.solve(A.T, v)
+
+
+_SUB = ((-2, -1, 0), (-1, 0, 1), (0, 1, 2))
+_QUARTIC = (-2, -1, 0, 1, 2)
+
+
+@lru_cache(maxsize=None)
+def weno_linear_weights(xi):
+    """Sub-stencil weights c_k and linear weights gamma_k with sum_k gamma_k p_k(xi) = quartic(xi)."""
+    c = [poly_weights(s, xi) for s in _SUB]
+    c5 = poly_weights(_QUARTIC, xi)
+    E = np.zeros((5, 3))
+    for k in range(3):
+        E[k:k + 3, k] = c[k]
+    gamma, *_ = np.linalg.lstsq(E, c5, rcond=None)
+    if not np.allclose(E @ gamma, c5, atol=1e-13):
+        raise RuntimeError("no linear weights reproduce the quartic at this point")
+    return tuple(tuple(ck) for ck in c), tuple(gamma)
+
+
+@lru_cache(maxsize=None)
+def smoothness_rules(k):
+    """Jiang-Shu indicator of sub-stencil k as exact quadrature of sum_{l=1,2} int (p^(l))^2 over the
+    cell: a list of (quadrature weight, weights giving p^(l) at the quadrature node)."""
+    xg, wg = np.polynomial.legendre.leggauss(3)
+    rules = []
+    for l in (1, 2):
+        for x, w in zip(xg / 2.0, wg / 2.0):
+            rules.append((float(w), tuple(poly_weights(_SUB[k], float(x), deriv=l))))
+    return tuple(rules)
+
+
+class WenoControl:
+    """How nonlinear weights are treated: 'live' (normal), 'detach' (frozen for differentiation),
+    'record' (store them) or 'replay' (use stored weights in call order)."""
+
+    def __init__(self, mode="live", store=None):
+        self.mode = mode
+        self.store = [] if store is None else store
+        self.i = 0
+
+    def apply(self, om):
+        if self.mode == "live":
+            return om
+        if self.mode == "detach":
+            return [o.detach() for o in om]
+        if self.mode == "record":
+            self.store.append([o.detach().clone() for o in om])
+            return om
+        if self.mode == "replay":
+            w = self.store[self.i]
+            self.i += 1
+            return w
+        raise ValueError(self.mode)
+
+
+_LIVE = WenoControl("live")
+
+
+def weno_point(q5, xi, eps, ctl=None):
+    """Fifth-order WENO-JS value at cell-relative point xi from five cell averages q5 = [q_-2..q_2]."""
+    ctl = ctl or _LIVE
+    c, gamma = weno_linear_weights(float(xi))
+    vals, alphas = [], []
+    for k in range(3):
+        sub = q5[k:k + 3]
+        vals.append(c[k][0] * sub[0] + c[k][1] * sub[1] + c[k][2] * sub[2])
+        beta = 0.0
+        for w, d in smoothness_rules(k):
+            beta = beta + w * (d[0] * sub[0] + d[1] * sub[1] + d[2] * sub[2]) ** 2
+        alphas.append(gamma[k] / (eps + beta) ** 2)
+    s = alphas[0] + alphas[1] + alphas[2]
+    om = ctl.apply([a / s for a in alphas])
+    return om[0] * vals[0] + om[1] * vals[1] + om[2] * vals[2]
+
+
+def linear_point(q5, xi, deriv=0):
+    """Value (deriv=0) or derivative (deriv=1, per unit cell width) of the quartic through q5."""
+    w = poly_weights(_QUARTIC, float(xi), deriv)
+    return sum(float(w[r]) * q5[r] for r in range(5))
+
+
+# ================================================================================================
+# constants, boundary ghost cells, time step
+# ================================================================================================
+
+def constants(cfg):
+    """lambda = Ma^2/(2 U_inf^2); sound speed C = sqrt(1/(2 lambda)) (Section 2)."""
+    lam = cfg.ma ** 2 / (2.0 * cfg.u_ref ** 2)
+    return {"lam": lam, "c2": 1.0 / (2.0 * lam), "c": math.sqrt(1.0 / (2.0 * lam))}
+
+
+def _ghost_slab(A, dim, side, kind, axis, cfg, c):
+    n = A.shape[dim]
+    if kind == "periodic":
+        return A.narrow(dim, n - NG, NG) if side == 0 else A.narrow(dim, 0, NG)
+    if kind in ("noslip", "slip"):
+        src = A.narrow(dim, 0, NG) if side == 0 else A.narrow(dim, n - NG, NG)
+        src = torch.flip(src, dims=(dim,))
+        sign = torch.ones(4, dtype=A.dtype)
+        if kind == "noslip":
+            sign[1:] = -1.0
+        else:
+            sign[1 + axis] = -1.0
+        return src * sign.view(4, 1, 1, 1)
+    if kind == "outflow":
+        src = A.narrow(dim, 0, 1) if side == 0 else A.narrow(dim, n - 1, 1)
+        return torch.cat([src] * NG, dim)
+    if kind == "inflow":
+        src = A.narrow(dim, 0, 1) if side == 0 else A.narrow(dim, n - 1, 1)
+        rho_i = src[0:1]
+        un_i = src[1 + axis:2 + axis] / rho_i
+        u_in = float(cfg.u_in[axis])
+        # outgoing invariant: U - C ln rho at the low side, U + C ln rho at the high side
+        expo = (u_in - un_i) / c if side == 0 else (un_i - u_in) / c
+        rho_g = rho_i * torch.exp(expo)
+        g = torch.cat([rho_g, rho_g * float(cfg.u_in[0]), rho_g * float(cfg.u_in[1]),
+                       rho_g * float(cfg.u_in[2])], 0)
+        return torch.cat([g] * NG, dim)
+    raise ValueError(kind)
+
+
+def ghost_fill(Q, cfg):
+    """Return the field padded with 3 ghost layers per side, axes filled x, y, z (reading R11)."""
+    c = constants(cfg)["c"]
+    A = Q
+    for axis, dim in ((0, 3), (1, 2), (2, 1)):
+        lo = _ghost_slab(A, dim, 0, cfg.bc[2 * axis], axis, cfg, c)
+        hi = _ghost_slab(A, dim, 1, cfg.bc[2 * axis + 1], axis, cfg, c)
+        A = torch.cat([lo, A, hi], dim)
+    return A
+
+
+def cfl_dt(Q, cfg):
+    """dt = CFL min(dx,dy,dz) / (|U|_max + C), |U|_max over the cells (Section 2); or the fixed dt."""
+    if cfg.cfl <= 0:
+        return float(cfg.dt_fixed)
+    c = constants(cfg)["c"]
+    u = Q[1:] / Q[0:1]
+    umax = float(torch.sqrt((u * u).sum(0)).max())
+    return cfg.cfl * min(cfg.dx, cfg.dy, cfg.dz) / (umax + c)
+
+
+# ================================================================================================
+# gas-kinetic flux at one Gauss point
+# ================================================================================================
+
+def kinetic_average(qL, qR, normal, lam):
+    """Q0 = int_{u_n>0} psi g^L + int_{u_n<0} psi g^R (reading R5), with the closed-form half-space
+    moments of the isothermal Maxwellians (variance 1/(2 lambda) per component)."""
+    s = math.sqrt(lam)
+    kk = 1.0 / (2.0 * math.sqrt(math.pi * lam))
+    rL, rR = qL[0], qR[0]
+    uL, uR = qL[1 + normal] / rL, qR[1 + normal] / rR
+    hL = 0.5 * torch.special.erfc(-s * uL)
+    hR = 0.5 * torch.special.erfc(s * uR)
+    eL = torch.exp(-lam * uL * uL)
+    eR = torch.exp(-lam * uR * uR)
+    out = [rL * hL + rR * hR]
+    for j in range(3):
+        v = qL[1 + j] * hL + qR[1 + j] * hR
+        if j == normal:
+            v = v + kk * (rL * eL - rR * eR)
+        out.append(v)
+    return torch.stack(out, 0)
+
+
+def _moment_1d(U, n, lam, cache):
+    """<u^n> of the normalised 1D Maxwellian: <u^0>=1, <u>=U, <u^{n+2}> = (n+1)/(2 lam) <u^n> + U <u^{n+1}>
+    (Appendix)."""
+    if n in cache:
+        return cache[n]
+    if n == 0:
+        r = torch.ones_like(U)
+    elif n == 1:
+        r = U
+    else:
+        r = (n - 1) / (2.0 * lam) * _moment_1d(U, n - 2, lam, cache) + U * _moment_1d(U, n - 1, lam, cache)
+    cache[n] = r
+    return r
+
+
+def maxwellian_moment(U3, lam, powers, caches=None):
+    """<u^a v^b w^c> = <u^a><v^b><w^c> (Appendix)."""
+    if caches is None:
+        caches = ({}, {}, {})
+    r = None
+    for i in range(3):
+        m = _moment_1d(U3[i], powers[i], lam, caches[i])
+        r = m if r is None else r * m
+    return r
+
+
+_PSI = ((0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1))  # exponents of psi = (1, u, v, w)
+
+
+def _addp(*ps):
+    return tuple(sum(p[i] for p in ps) for i in range(3))
+
+
+_UNIT = ((1, 0, 0), (0, 1, 0), (0, 0, 1))
+
+
+def micro_coefficients(Q0, grads, lam):
+    """Microscopic coefficients of g0 (Appendix): M a_k = (dQ0/dx_k)/rho0 for k = x, y, z, with
+    M = <psi psi^T>, then A from the compatibility condition <(a_x u + a_y v + a_z w + A) psi> = 0
+    (reading R6). Returns (a, A, mom): a[k] and A are [4, ...]; mom evaluates Maxwellian moments."""
+    rho0 = Q0[0]
+    U3 = [Q0[1] / rho0, Q0[2] / rho0, Q0[3] / rho0]
+    caches = ({}, {}, {})
+
+    def mom(*ps):
+        return maxwellian_moment(U3, lam, _addp(*ps), caches)
+
+    shape = rho0.shape
+    M = torch.stack([torch.stack([mom(_PSI[i], _PSI[l]) for l in range(4)], -1) for i in range(4)], -2)
+    M = M.reshape(-1, 4, 4)
+
+    def solve(rhs):  # rhs [4, ...] -> [4, ...]
+        x = torch.linalg.solve(M, rhs.reshape(4, -1).T.unsqueeze(-1)).squeeze(-1)
+        return x.T.reshape((4,) + shape)
+
+    a = [solve(grads[k] / rho0) for k in range(3)]
+    b = []
+    for i in range(4):
+        acc = 0.0
+        for k in range(3):
+            for l in range(4):
+                acc = acc + a[k][l] * mom(_UNIT[k], _PSI[l], _PSI[i])
+        b.append(-acc)
+    A = solve(torch.stack(b, 0))
+    return a, A, mom
+
+
+def gks_point_flux(Q0, grads, normal, lam, mu, need_f0=True):
+    """F0 = rho0 <u_n psi> - tau rho0 <u_n (a.u + A) psi> and F1 = rho0 <u_n A psi> at one Gauss point
+    for f = g0 (1 - tau (a1 u + a2 v + a3 w + A) + A t) (Section 2, Eq. (flux)), tau = mu/p0,
+    p0 = rho0/(2 lambda). grads[k] = dQ0/dx_k (k = x, y, z). Returns (F0, F1), each [4, ...]."""
+    rho0 = Q0[0]
+    a, A, mom = micro_coefficients(Q0, grads, lam)
+    un = _UNIT[normal]
+    F1 = []
+    F0 = []
+    for i in range(4):
+        t_a = 0.0
+        for l in range(4):
+            t_a = t_a + A[l] * mom(un, _PSI[l], _PSI[i])
+        F1.append(rho0 * t_a)
+        if need_f0:
+            t_u = 0.0
+            for k in range(3):
+                for l in range(4):
+                    t_u = t_u + a[k][l] * mom(un, _UNIT[k], _PSI[l], _PSI[i])
+            tau = mu / (rho0 / (2.0 * lam))
+            F0.append(rho0 * (mom(un, _PSI[i]) - tau * (t_u + t_a)))
+    return (torch.stack(F0, 0) if need_f0 else None), torch.stack(F1, 0)
+
+
+# ================================================================================================
+# the operator L(Q) and its time derivative, dimension by dimension
+# ================================================================================================
+
+def _local(P, d):
+    """Padded [4, Z, Y, X] viewed as [4, t2, t1, n] with the face normal last."""
+    if d == 0:
+        return P
+    if d == 1:
+        return P.permute(0, 1, 3, 2)  # (z, x, y)
+    return P.permute(0, 2, 3, 1)      # (y, x, z)
+
+
+def _global(A, d):
+    if d == 0:
+        return A
+    if d == 1:
+        return A.permute(0, 1, 3, 2)
+    return A.permute(0, 3, 1, 2)
+
+
+def _spacings(cfg, d):
+    dx, dy, dz = cfg.dx, cfg.dy, cfg.dz
+    return ((dx, dy, dz), (dy, dx, dz), (dz, dx, dy))[d]
+
+
+def _grads_global(d, dn, dt1, dt2):
+    return ((dn, dt1, dt2), (dt1, dn, dt2), (dt1, dt2, dn))[d]
+
+
+def _direction(P, d, cfg, lam, need_f0, ctl, chunk):
+    """Face fluxes in direction d and their divergence contributions (per unit volume)."""
+    hn, h1, h2 = _spacings(cfg, d)
+    A = _local(P, d)
+    T2, T1, N = A.shape[1] - 2 * NG, A.shape[2] - 2 * NG, A.shape[3] - 2 * NG
+    eps = cfg.weno_eps
+    # normal derivative: face derivative of the cubic through cells f-2..f+1 (reading R3)
+    wd = poly_weights((-1, 0, 1, 2), 0.5, deriv=1)
+    L0 = [] if need_f0 else None
+    L1 = []
+    k0 = 0
+    while k0 < T2:
+        k1 = min(T2, k0 + chunk)
+        B = A[:, k0 + 1:k1 + 5, 1:T1 + 5, :]  # cells k0-2..k1+1 (t2), -2..T1+1 (t1), all normal
+
+        def cell(rel):
+            return B[..., NG + rel: NG + rel + N + 1]
+
+        qL = weno_point([cell(-3), cell(-2), cell(-1), cell(0), cell(1)], 0.5, eps, ctl)
+        qR = weno_point([cell(-2), cell(-1), cell(0), cell(1), cell(2)], -0.5, eps, ctl)
+        D = sum(float(wd[r]) * cell(r - 2) for r in range(4)) / hn
+        C = 0.5 * (qL + qR)
+
+        def sl1(X, r):
+            return X[:, :, r:r + T1, :]
+
+        def sl2(X, r):
+            return X[:, r:r + (k1 - k0), :, :]
+
+        t1 = []
+        for xm in GAUSS_XI:
+            t1.append({
+                "L": weno_point([sl1(qL, r) for r in range(5)], xm, eps, ctl),
+                "R": weno_point([sl1(qR, r) for r in range(5)], xm, eps, ctl),
+                "D": linear_point([sl1(D, r) for r in range(5)], xm),
+                "C": linear_point([sl1(C, r) for r in range(5)], xm),
+                "Ct1": linear_point([sl1(C, r) for r in range(5)], xm, 1) / h1,
+            })
+        F0s, F1s = 0.0, 0.0
+        for m in range(2):
+            for xn in GAUSS_XI:
+                gL = weno_point([sl2(t1[m]["L"], r) for r in range(5)], xn, eps, ctl)
+                gR = weno_point([sl2(t1[m]["R"], r) for r in range(5)], xn, eps, ctl)
+                dn = linear_point([sl2(t1[m]["D"], r) for r in range(5)], xn)
+                dt1 = linear_point([sl2(t1[m]["Ct1"], r) for r in range(5)], xn)
+                dt2 = linear_point([sl2(t1[m]["C"], r) for r in range(5)], xn, 1) / h2
+                Q0 = kinetic_average(gL, gR, d, lam)
+                F0, F1 = gks_point_flux(Q0, _grads_global(d, dn, dt1, dt2), d, lam, cfg.mu, need_f0)
+                F1s = F1s + 0.25 * F1
+                if need_f0:
+                    F0s = F0s + 0.25 * F0
+        L1.append(-(F1s[..., 1:] - F1s[..., :-1]) / hn)
+        if need_f0:
+            L0.append(-(F0s[..., 1:] - F0s[..., :-1]) / hn)
+        k0 = k1
+    L1 = _global(torch.cat(L1, 1), d)
+    L0 = _global(torch.cat(L0, 1), d) if need_f0 else None
+    return L0, L1
+
+
+def operator(Q, cfg, need_f0=True, ctl=None, chunk=64):
+    """L(Q) = -(1/|Omega|) sum over the six faces of the face flux at t (Eq. (finite)) and its time
+    derivative; with f linear in t these are the face averages of F0 and F1."""
+    lam = constants(cfg)["lam"]
+    P = ghost_fill(Q, cfg)
+    L0 = 0.0 if need_f0 else None
+    L1 = 0.0
+    for d in range(3):
+        a, b = _direction(P, d, cfg, lam, need_f0, ctl, chunk)
+        L1 = L1 + b
+        if need_f0:
+            L0 = L0 + a
+    return L0, L1
+
+
+def s2o4_stage1(Q, L, Lt, dt):
+    """Intermediate state of the two-stage fourth-order method: Q* = Q + dt/2 L + dt^2/8 L_t (reading R7)."""
+    return Q + 0.5 * dt * L + dt * dt / 8.0 * Lt
+
+
+def s2o4_final(Q, L, Lt, Lt_star, dt):
+    """Q^{n+1} = Q + dt L + dt^2/6 (L_t + 2 L_t(Q*)) (reading R7)."""
+    return Q + dt * L + dt * dt / 6.0 * (Lt + 2.0 * Lt_star)
+
+
+# ================================================================================================
+# actuator line model (Section 3.1)
+# ================================================================================================
+
+def rotor_points(rotor, t):
+    """Actuator point positions and blade-motion directions at time t. Blade b sits at angle
+    theta0 + omega t + 2 pi b / N_b about the +x axis; e_theta = (0, -sin, cos)."""
+    nb, npb = rotor.n_blades, rotor.n_per_blade
+    th = rotor.theta0 + rotor.omega * t + 2 * math.pi * np.arange(nb) / nb
+    r = np.asarray(rotor.r, dtype=np.float64)
+    X = np.zeros((nb, npb, 3))
+    et = np.zeros((nb, npb, 3))
+    for b in range(nb):
+        X[b, :, 0] = rotor.hub[0]
+        X[b, :, 1] = rotor.hub[1] + r * math.cos(th[b])
+        X[b, :, 2] = rotor.hub[2] + r * math.sin(th[b])
+        et[b, :, 1] = -math.sin(th[b])
+        et[b, :, 2] = math.cos(th[b])
+    return X.reshape(-1, 3), et.reshape(-1, 3)
+
+
+def _trilinear(Q, cfg, X):
+    """Velocity U = (rho U)/rho at points X by trilinear interpolation of cell-centre values."""
+    out = []
+    org = (cfg.x0, cfg.y0, cfg.z0)
+    h = (cfg.dx, cfg.dy, cfg.dz)
+    for p in range(X.shape[0]):
+        f = [(X[p, a] - org[a]) / h[a] - 0.5 for a in range(3)]
+        i0 = [int(math.floor(v)) for v in f]
+        tt = [f[a] - i0[a] for a in range(3)]
+        acc = 0.0
+        for dz_ in (0, 1):
+            for dy_ in (0, 1):
+                for dx_ in (0, 1):
+                    w = ((tt[0] if dx_ else 1 - tt[0]) * (tt[1] if dy_ else 1 - tt[1]) *
+                         (tt[2] if dz_ else 1 - tt[2]))
+                    cellv = Q[:, i0[2] + dz_, i0[1] + dy_, i0[0] + dx_]
+                    acc = acc + w * (cellv[1:] / cellv[0])
+        out.append(acc)
+    return torch.stack(out, 0)  # [n, 3]
+
+
+def alm_apply(Q, t, dt, cfg, rotor, scales=None):
+    """Sample, blade-element forces, Gaussian projection truncated at 3 eps, momentum update
+    (Section 3.1, Eqs. (axial-tangential), (Gaussian); Section 3.3; reading R9).
+    Returns (Q_new, outputs)."""
+    X, et = rotor_points(rotor, t)
+    n = X.shape[0]
+    if scales is None:
+        scales = torch.ones(n, dtype=F64)
+    npb = rotor.n_per_blade
+    r = torch.tensor(np.tile(rotor.r, rotor.n_blades), dtype=F64)
+    chord = torch.tensor(np.tile(rotor.chord, rotor.n_blades), dtype=F64)
+    twist = torch.tensor(np.tile(rotor.twist, rotor.n_blades), dtype=F64)
+    width = torch.tensor(np.tile(rotor.width, rotor.n_blades), dtype=F64)
+    U = _trilinear(Q, cfg, X)
+    ett = torch.tensor(et, dtype=F64)
+    ux = U[:, 0]
+    ut = (U * ett).sum(1)
+    om = rotor.omega
+
+    def cd(alpha):
+        return rotor.cd0 + rotor.cd2 * alpha * alpha
+
+    if rotor.u_inf_correction:
+        phi0 = torch.atan2(ux, om * r - ut)
+        alpha0 = phi0 - twist
+        fac = 1.0 / (1.0 - cd(alpha0) * chord / (4.0 * math.sqrt(math.pi) * rotor.eps))
+        ux = ux * fac
+        ut = ut * fac
+    phi = torch.atan2(ux, om * r - ut)
+    alpha = phi - twist
+    urel2 = ux * ux + (ut - om * r) ** 2
+    cl = rotor.cl_slope * torch.clamp(alpha, -rotor.alpha_clip, rotor.alpha_clip)
+    lift = 0.5 * cfg.rho_ref * chord * width * cl * urel2
+    drag = 0.5 * cfg.rho_ref * chord * width * cd(alpha) * urel2
+    fx = scales * (lift * torch.cos(phi) + drag * torch.sin(phi))
+    ft = scales * (lift * torch.sin(phi) - drag * torch.cos(phi))
+    thrust = fx.sum()
+    torque = (r * ft).sum()
+    power = om * torque
+    area = math.pi * rotor.radius ** 2
+    cp = power / (0.5 * cfg.rho_ref * area * rotor.u_inf ** 3)
+    ct = thrust / (0.5 * cfg.rho_ref * area * rotor.u_inf ** 2)
+    # Gaussian projection of minus the blade force, truncated at r = 3 eps, point values at cell centres
+    eps = rotor.eps
+    norm = 1.0 / (eps ** 3 * math.pi ** 1.5)
+    org = (cfg.x0, cfg.y0, cfg.z0)
+    h = (cfg.dx, cfg.dy, cfg.dz)
+    nn = (cfg.nx, cfg.ny, cfg.nz)
+    force = torch.zeros((3,) + tuple(Q.shape[1:]), dtype=F64)
+    for p in range(n):
+        lo, hi = [], []
+        for a in range(3):
+            lo.append(max(0, int(math.ceil((X[p, a] - 3 * eps - org[a]) / h[a] - 0.5))))
+            hi.append(min(nn[a] - 1, int(math.floor((X[p, a] + 3 * eps - org[a]) / h[a] - 0.5))))
+        xs = [org[a] + (np.arange(lo[a], hi[a] + 1) + 0.5) * h[a] for a in range(3)]
+        ZZ, YY, XX = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+        r2 = (XX - X[p, 0]) ** 2 + (YY - X[p, 1]) ** 2 + (ZZ - X[p, 2]) ** 2
+        g = np.where(r2 <= 9.0 * eps * eps, norm * np.exp(-r2 / (eps * eps)), 0.0)
+        gt = torch.tensor(g, dtype=F64)
+        fvec = [-fx[p], -ft[p] * float(et[p, 1]), -ft[p] * float(et[p, 2])]
+        for comp in range(3):
+            force[comp, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] = (
+                force[comp, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] + fvec[comp] * gt)
+    Qn = torch.cat([Q[0:1], Q[1:] + dt * force], 0)
+    out = {"X": X, "alpha": alpha, "phi": phi, "fx": fx, "ftheta": ft, "urel": torch.sqrt(urel2),
+           "thrust": thrust, "torque": torque, "power": power, "cp": cp, "ct": ct, "force": force}
+    return Qn, out
+
+
+# ================================================================================================
+# immersed boundary method (Section 3.2)
+# ================================================================================================
+
+def phi4(r):
+    """Peskin's 4-point regularised delta function (per unit cell width)."""
+    r = np.abs(np.asarray(r, dtype=np.float64))
+    out = np.zeros_like(r)
+    a = r <= 1.0
+    b = (r > 1.0) & (r < 2.0)
+    out[a] = (3.0 - 2.0 * r[a] + np.sqrt(1.0 + 4.0 * r[a] - 4.0 * r[a] ** 2)) / 8.0
+    out[b] = (5.0 - 2.0 * r[b] - np.sqrt(-7.0 + 12.0 * r[b] - 4.0 * r[b] ** 2)) / 8.0
+    return out
+
+
+class IbmCache:
+    """Static data of stationary Lagrangian points: per point the 4x4x4 support cells and weights,
+    and per cell the interpolated volume V-bar (with v-bar = 0)."""
+
+    def __init__(self, cells, weights, vbar_index, vbar):
+        self.cells = cells        # [n, 64, 3] integer (i, j, k)
+        self.weights = weights    # [n, 64]
+        self.vbar_index = vbar_index  # [m, 3] cells with V-bar > 0
+        self.vbar = vbar          # [m]
+
+
+def ibm_setup(cfg, ibm):
+    """W_{p->ijk} = phi4((x_i-X)/dx) phi4((y_j-Y)/dy) phi4((z_k-Z)/dz); V_p = dx dS_p;
+    V-bar_ijk = sum_p W V_p (Section 3.2)."""
+    X = np.asarray(ibm.xyz, dtype=np.float64)
+    n = X.shape[0]
+    org = np.array([cfg.x0, cfg.y0, cfg.z0])
+    h = np.array([cfg.dx, cfg.dy, cfg.dz])
+    f = (X - org) / h - 0.5
+    i0 = np.floor(f).astype(np.int64)
+    offs = np.arange(-1, 3)
+    cells = np.zeros((n, 64, 3), dtype=np.int64)
+    weights = np.zeros((n, 64))
+    q = 0
+    for dk in offs:
+        for dj in offs:
+            for di in offs:
+                idx = i0 + np.array([di, dj, dk])
+                cells[:, q] = idx
+                rr = f - idx
+                weights[:, q] = phi4(rr[:, 0]) * phi4(rr[:, 1]) * phi4(rr[:, 2])
+                q += 1
+    nn = np.array([cfg.nx, cfg.ny, cfg.nz])
+    if (cells < 0).any() or (cells >= nn).any():
+        raise ValueError("IBM support leaves the interior cells")
+    vp = cfg.dx * np.asarray(ibm.dS, dtype=np.float64)
+    flat = (cells[..., 2] * cfg.ny + cells[..., 1]) * cfg.nx + cells[..., 0]
+    vb = np.zeros(cfg.nx * cfg.ny * cfg.nz)
+    np.add.at(vb, flat.reshape(-1), (weights * vp[:, None]).reshape(-1))
+    nz_idx = np.nonzero(vb > 0)[0]
+    vbar_index = np.stack([nz_idx % cfg.nx, (nz_idx // cfg.nx) % cfg.ny, nz_idx // (cfg.nx * cfg.ny)], 1)
+    return IbmCache(cells, weights, vbar_index, vb[nz_idx])
+
+
+def ibm_apply(Q, dt, cfg, cache, iters):
+    """Direct-forcing iterations at the cells with V-bar > 0 (Eq. (ibm-1) and the velocity update of
+    Section 3.2, reading R8 for the divisor): F^s = rho V-bar (v-bar - U^s)/dt, (rho U)^{s+1} =
+    (rho U)^s + dt F^s / |Omega|; f_IBM = sum_s F^s (Eq. (force-ibm)). Returns (Q_new, outputs)."""
+    vol = cfg.dx * cfg.dy * cfg.dz
+    vi = cache.vbar_index
+    i, j, k = vi[:, 0], vi[:, 1], vi[:, 2]
+    rho = Q[0, k, j, i]
+    m = Q[1:, k, j, i]
+    vbar = torch.tensor(cache.vbar, dtype=F64)
+    facc = torch.zeros_like(m)
+    for _ in range(iters):
+        U = m / rho
+        F = rho * vbar * (0.0 - U) / dt
+        m = m + dt * F / vol
+        facc = facc + F
+    mom = Q[1:].clone()
+    mom[:, k, j, i] = m
+    Qn = torch.cat([Q[0:1], mom], 0)
+    # residual: |v_p - sum_ijk W_{ijk->p} U_ijk| after the last iteration
+    c = cache.cells
+    Uc = Qn[1:, c[..., 2], c[..., 1], c[..., 0]] / Qn[0, c[..., 2], c[..., 1], c[..., 0]]  # [3, n, 64]
+    w = torch.tensor(cache.weights, dtype=F64)
+    Up = (Uc * w).sum(-1)
+    res = torch.sqrt((Up * Up).sum(0)).max() if Up.shape[1] > 0 else torch.tensor(0.0, dtype=F64)
+    total = facc.sum(1)
+    return Qn, {"force_on_fluid": total, "body_force": -total, "residual": res, "facc": facc}
+
+
+# ================================================================================================
+# step driver
+# ================================================================================================
+
+def conservation_sums(Q):
+    """Mass and momentum totals over the interior cells (per unit cell volume), exactly summed."""
+    a = Q.detach().numpy()
+    return [math.fsum(a[v].reshape(-1).tolist()) for v in range(4)]
+
+
+class Oracle:
+    """State holder: interior cell averages Q [4, nz, ny, nx] (rho, rho U, rho V, rho W) in float64."""
+
+    def __init__(self, cfg, q0=None, scales=None, weno_ctl=None, chunk=64):
+        self.cfg = cfg
+        q = cfg.q0 if q0 is None else q0
+        self.Q = q.clone() if isinstance(q, torch.Tensor) else torch.tensor(np.asarray(q), dtype=F64)
+        self.t = 0.0
+        self.n = 0
+        self.scales = scales
+        self.ctl = weno_ctl
+        self.chunk = chunk
+        self.ibm_cache = ibm_setup(cfg, cfg.ibm) if cfg.ibm is not None else None
+        self.history = []
+
+    def step(self, dt=None):
+        cfg = self.cfg
+        Q = self.Q
+        if dt is None:
+            dt = cfl_dt(Q.detach(), cfg)
+        L0, L1 = operator(Q, cfg, True, self.ctl, self.chunk)
+        Qs = s2o4_stage1(Q, L0, L1, dt)
+        _, L1s = operator(Qs, cfg, False, self.ctl, self.chunk)
+        Qn = s2o4_final(Q, L0, L1, L1s, dt)
+        G = cfg.body_force
+        if any(g != 0.0 for g in G):
+            Qn = torch.cat([Qn[0:1], Qn[1:] + dt * torch.tensor(G, dtype=F64).view(3, 1, 1, 1)], 0)
+        t_new = self.t + dt
+        out = {"dt": dt, "t": t_new}
+        if cfg.rotor is not None:
+            Qn, alm = alm_apply(Qn, t_new, dt, cfg, cfg.rotor, self.scales)
+            out["alm"] = alm
+        if self.ibm_cache is not None:
+            Qn, ib = ibm_apply(Qn, dt, cfg, self.ibm_cache, cfg.ibm_iters)
+            out["ibm"] = ib
+        self.Q = Qn
+        self.t = t_new
+        self.n += 1
+        self.history.append(out)
+        return out
