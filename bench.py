@@ -1,0 +1,148 @@
+"""Benchmark of one S2O4 step of the high-order isothermal GKS (HIP library, one MI355X).
+
+Default workload: the channel-like flow, 192 x 96 x 96 cells, no-slip walls in y, periodic x and z,
+constant pressure-gradient body force, FP32 storage and arithmetic with density stored as its
+deviation from rho_ref. A step = ghost cells, CFL dt on the device, both S2O4 stages (reconstruction,
+gas-kinetic flux, divergence, combination) and the body-force update. Inputs are resident in HBM
+when the timed region starts. The FP64 run of the same case is timed too, and the FP32 result is
+compared with it after the same number of steps.
+
+Prints ONE JSON line (last line of stdout).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point operations (add, sub, mul = 1, FMA = 2, div / sqrt / exp / erf = 1) per
+# cell and face direction, counted from the formulation of the face kernel: reconstruction of the four
+# variables (normal 111, t1 215, t2 430 per variable), flux at four Gauss points, divergence. The
+# breakdown is given with the kernel description in the design notes.
+FLOP_STAGE1_PER_CELL_DIR = 3692
+FLOP_STAGE2_PER_CELL_DIR = 3592
+FLOP_PER_CELL_STEP = 3 * (FLOP_STAGE1_PER_CELL_DIR + FLOP_STAGE2_PER_CELL_DIR) + 56
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
+PEAK_HBM_GBS = 8000.0
+
+
+def _time_steps(s, steps):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def run_gpu(cfg, precision, steps, warmup):
+    import torch
+    from paper_2603_11102_amd import GksSolver
+    s = GksSolver(cfg, precision=precision)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    ms = _time_steps(s, steps)
+    s.set_timing(True)
+    ms_t = _time_steps(s, steps)
+    timing = s.read_timing()
+    s.set_timing(False)
+    f = s.forces(check=False)
+    return s, ms, ms_t, timing, f
+
+
+def cpu_baseline(cfg, planes):
+    """Time the FP64 CPU oracle for one step on a bounded sample: the first `planes` z-planes of the same
+    initial field, periodic in z (same spacing, same physics)."""
+    import torch
+    from oracle import Oracle
+    sub = cfg.with_(nz=planes, lz=cfg.dz * planes, q0=cfg.q0[:, :planes].copy())
+    o = Oracle(sub)
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    return {"value": sub.n_cells / dt, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"1 S2O4 step of the FP64 oracle on {sub.nx}x{sub.ny}x{sub.nz} cells (first {planes} "
+                      f"z-planes of the same field, periodic in z), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--case", default="channel")
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the x-slab multi-GPU "
+              "decomposition is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from synth import make_case
+    cfg = make_case(args.case)
+    print(f"[bench] case={args.case} grid={cfg.nx}x{cfg.ny}x{cfg.nz} precision={args.precision} "
+          f"steps={args.steps} warmup={args.warmup}", flush=True)
+    s, ms, ms_t, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    n = cfg.n_cells
+    value = n * args.steps / (ms * 1e-3)
+    print(f"[bench] {args.precision}: {ms / args.steps:.3f} ms/step, {value:.4e} cell-updates/s", flush=True)
+    print("[bench] per-category ms/step: " + ", ".join(f"{k}={v[0] / args.steps:.3f}" for k, v in timing.items()),
+          flush=True)
+    s1_ms = sum(timing[k][0] for k in ("s1x", "s1y", "s1z"))
+    s1_launches = sum(timing[k][1] for k in ("s1x", "s1y", "s1z"))
+    avg_launch_ms = s1_ms / max(1, s1_launches)
+    flops_launch = FLOP_STAGE1_PER_CELL_DIR * n
+    achieved = flops_launch / (avg_launch_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    result = {
+        "metric": "cell-updates/s per S2O4 step",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.case} {cfg.nx}x{cfg.ny}x{cfg.nz} ({n} cells), "
+                               f"{'FP32, density as deviation from rho_ref' if args.precision == 'fp32' else 'FP64'}",
+                   "cells": n, "bc": list(cfg.bc), "ma": cfg.ma},
+        "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'},1> "
+                                                "(stage 1, mean over the x, y, z launches)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "avg_launch_ms": avg_launch_ms,
+                     "algorithmic_flop_per_launch": flops_launch},
+        "per_category_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
+        "flop_per_cell_step": FLOP_PER_CELL_STEP,
+    }
+    if args.precision == "fp32" and not args.no_fp64:
+        s64, ms64, _, _, _ = run_gpu(cfg, "fp64", args.steps, args.warmup)
+        q32, q64 = s.interior(), s64.interior()
+        rl2 = [float(torch.linalg.vector_norm(q32[v] - q64[v]) / torch.linalg.vector_norm(q64[v])) for v in range(4)]
+        result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
+        result["fp32_vs_fp64_rel_l2"] = {"after_steps": args.steps * 2 + args.warmup, "per_variable": rl2}
+        print(f"[bench] fp64: {ms64 / args.steps:.3f} ms/step; fp32 vs fp64 rel L2 {rl2}", flush=True)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample ...", flush=True)
+        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_planes)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

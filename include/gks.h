@@ -1,0 +1,213 @@
+/*
+ * gks.h -- C ABI of the MI355X (gfx950) library for one two-stage fourth-order (S2O4) time step of the
+ * high-order gas-kinetic scheme (GKS) for 3D weakly compressible isothermal flow on a uniform
+ * Cartesian grid, with actuator-line (ALM) and immersed-boundary (IBM) body forces.
+ *
+ * Method: Huo, Pan, Cao, Meng, Tian, Huang, "High-order gas-kinetic scheme for numerical simulations
+ * of wind turbine with nacelle and tower using ALM and IBM" (arXiv 2603.11102):
+ *   Section 2      BGK model, isothermal Maxwellian, finite-volume form (Eqs. (semi), (finite),
+ *                  (x_example)), interface distribution (Eq. (flux)), WENO reconstruction, S2O4, CFL dt;
+ *   Appendix       microscopic coefficients of g0;
+ *   Section 3.1    actuator line model (Eqs. (axial-tangential), (Gaussian));
+ *   Section 3.2    direct-forcing immersed boundary (Eqs. (ibm-1), (force-ibm));
+ *   Section 3.3    momentum update with the external body force after the S2O4 step;
+ *   Section 4.4.1  power and thrust coefficients.
+ *
+ * Memory ownership: the CALLER owns every device buffer (fields, workspace, checkpoints, scalings)
+ * and keeps it alive until gks_destroy. The library never allocates device memory; it holds a small
+ * host context. All device work is enqueued on the HIP stream given to gks_init, in order.
+ *
+ * Fields: a gks_field is four device pointers (rho - rho_ref, rho U, rho V, rho W). Each points to
+ * (nx+6)(ny+6)(nz+6) elements of the configured precision (float or double), x fastest, then y, then
+ * z, with 3 ghost layers per side: cell (i, j, k), -3 <= i < nx+3, sits at
+ * ((k+3)(ny+6) + (j+3))(nx+6) + (i+3). Density is stored as its deviation from rho_ref.
+ *
+ * Errors: every call returns GKS_OK (0) or a GKS_E_* code and never throws across the ABI; the last
+ * message of a context is available from gks_last_error. Contexts are not thread-safe.
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GKS_OK 0
+#define GKS_E_INVALID_ARG 1   /* argument out of range, inconsistent sizes, null pointer */
+#define GKS_E_STATE 2         /* call out of order (e.g. adjoint without a checkpoint window) */
+#define GKS_E_HIP 3           /* a HIP runtime call failed */
+#define GKS_E_NONFINITE 4     /* a non-finite value was found in the field (reported by gks_forces) */
+#define GKS_E_UNSTABLE 5      /* |U|_max reached the sound speed (reported by gks_forces) */
+#define GKS_E_UNSUPPORTED 6   /* valid request this build does not implement */
+
+/* boundary kinds, per side, order x-, x+, y-, y+, z-, z+ */
+#define GKS_BC_PERIODIC 0
+#define GKS_BC_NOSLIP_WALL 1  /* mirror: rho even, all momenta odd (no-slip isothermal wall) */
+#define GKS_BC_SLIP_WALL 2    /* mirror: normal momentum odd, rest even (slip / symmetry wall) */
+#define GKS_BC_INFLOW 3       /* prescribed velocity u_in, rho from the outgoing isothermal Riemann invariant */
+#define GKS_BC_OUTFLOW 4      /* zero-gradient extrapolation */
+
+#define GKS_FP32 0
+#define GKS_FP64 1
+
+/* gks_forces_out.flags bits (warnings, non-fatal) */
+#define GKS_WARN_EPS_SMALL 1  /* ALM eps < 2 dx (Section 4.3.1 advises eps >= 2 dx) */
+#define GKS_WARN_MACH 2       /* Ma > 0.3: outside the weakly compressible regime */
+
+typedef struct gks_config {
+    int32_t nx, ny, nz;          /* interior cells per axis, each >= 1 */
+    int32_t precision;           /* GKS_FP32 or GKS_FP64: storage and arithmetic of the stage kernels */
+    double x0, y0, z0;           /* low corner of the domain */
+    double lx, ly, lz;           /* domain lengths (uniform spacing lx/nx, ...) */
+    double ma, u_ref;            /* lambda = ma^2 / (2 u_ref^2) (Section 2); sound speed sqrt(1/(2 lambda)) */
+    double rho_ref;              /* reference density; fields store rho - rho_ref */
+    double mu;                   /* dynamic viscosity; collision time tau = mu / p (Section 2) */
+    double cfl;                  /* > 0: dt = cfl min(dx,dy,dz) / (|U|_max + C) each step (Section 2) */
+    double dt_fixed;             /* used when cfl <= 0 (the constant dt of Section 4.3) */
+    int32_t bc[6];               /* GKS_BC_* for x-, x+, y-, y+, z-, z+; periodic must be paired */
+    double u_in[3];              /* inflow velocity for GKS_BC_INFLOW sides */
+    double body_force[3];        /* constant body force G per unit volume, added as dt G after the step */
+    double weno_eps;             /* WENO-JS epsilon (1e-6 if <= 0) */
+    int32_t ibm_iters;           /* direct-forcing iterations per step (fixed count, >= 1) */
+    int32_t max_act;             /* capacity of the workspace for actuator points (0 = no rotor), <= 1024 */
+    int64_t max_ibm;             /* capacity of the workspace for Lagrangian points (0 = no bodies) */
+} gks_config;
+
+typedef struct gks_field {
+    void* rho;  /* rho - rho_ref */
+    void* mx;   /* rho U */
+    void* my;   /* rho V */
+    void* mz;   /* rho W */
+} gks_field;
+
+typedef struct gks_rotor {
+    int32_t n_blades, n_per_blade;   /* actuator points: n_blades * n_per_blade, blade-major */
+    double hub[3];                   /* rotor centre; the rotor axis is +x */
+    double omega, theta0;            /* blade b at angle theta0 + omega t + 2 pi b / n_blades about +x */
+    double radius;                   /* tip radius R (for C_P, C_T) */
+    double u_inf;                    /* reference velocity of C_P, C_T */
+    const double* r;                 /* host, n_per_blade: radius of each point */
+    const double* chord;             /* host, n_per_blade */
+    const double* twist;             /* host, n_per_blade: local twist gamma (rad) */
+    const double* width;             /* host, n_per_blade: element width w */
+    double eps;                      /* Gaussian smearing width (Eq. (Gaussian)), truncated at 3 eps */
+    double cl_slope, alpha_clip;     /* synthetic polar C_L = cl_slope * clamp(alpha, +-alpha_clip) */
+    double cd0, cd2;                 /* C_D = cd0 + cd2 alpha^2 (alpha in rad) */
+    int32_t u_inf_correction;        /* 1: free-stream velocity correction of Section 3.1 */
+    int32_t reserved;
+    const double* scale;             /* DEVICE, n_act doubles: per-point force scaling s_p; NULL = 1 */
+} gks_rotor;
+
+typedef struct gks_forces_out {
+    double t, dt;                    /* time after the last step and its dt */
+    int64_t step;                    /* steps taken since gks_init */
+    double thrust, torque, power;    /* rotor loads of the last step (FP64 reductions) */
+    double cp, ct;                   /* 2 P/(rho pi R^2 U^3), 2 T/(rho pi R^2 U^2) (Section 4.4.1) */
+    double ibm_force[3];             /* total IBM force on the bodies, last step: -sum_s sum_cells F^s */
+    double ibm_residual;             /* max_p |v_p - interpolated U| after the last iteration */
+    int32_t ibm_iters_used;
+    int32_t flags;                   /* GKS_WARN_* bits */
+    double mass, mom[3];             /* interior sums of rho - rho_ref and rho U (times cell volume) */
+    double umax;                     /* max |U| over interior cells */
+    double window_power, window_thrust; /* sums of P and T over steps since the last window reset */
+    int64_t window_steps;
+    /* optional HOST arrays of n_act doubles, filled if non-NULL */
+    double* alpha;
+    double* fx;
+    double* ftheta;
+    double* urel;
+} gks_forces_out;
+
+typedef struct gks_ctx gks_ctx;
+
+/* Bytes of device workspace the caller must provide to gks_init for this configuration (including
+ * room for cfg->max_act actuator points and cfg->max_ibm Lagrangian points). Returns 0 on invalid
+ * input. */
+size_t gks_workspace_bytes(const gks_config* cfg);
+
+/* Create a context. q holds Q^0 (interior cells; ghosts are filled here), q_stage and q_acc are the
+ * stage buffers (Q* and the S2O4 accumulator), same layout. workspace: device, >= the bytes above,
+ * 256-byte aligned. hip_stream: a hipStream_t (NULL = default stream). Validates the configuration,
+ * fills the ghost cells of q and enqueues nothing else. */
+int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_acc, void* workspace,
+             size_t workspace_bytes, void* hip_stream, gks_ctx** out);
+
+/* Set (or replace) the rotor of the actuator line model (Section 3.1). Host arrays are copied; the
+ * device scale array is referenced and read at every step. Every actuator point, its sampling cells
+ * and its 3 eps projection sphere must lie inside the interior cells. */
+int gks_set_actuators(gks_ctx* ctx, const gks_rotor* rotor);
+
+/* Set stationary Lagrangian points of the immersed bodies (Section 3.2): n points, host xyz [n][3]
+ * and surface areas dS [n]; vel must be NULL (moving points are not supported). Each point's 4x4x4
+ * discrete-delta support must lie inside the interior cells. Computes the static interpolated
+ * volumes V-bar on the device. */
+int gks_set_ibm_points(gks_ctx* ctx, int64_t n, const double* xyz, const double* dS, const double* vel);
+
+/* Enqueue nsteps S2O4 steps (Section 2) with the body-force update of Section 3.3 on the stream and
+ * return without synchronising. dt stays on the device. */
+int gks_step(gks_ctx* ctx, int32_t nsteps);
+
+/* Synchronise the stream and report the FP64 loads, coefficients, conservation sums and time of the
+ * last step. Returns GKS_E_NONFINITE / GKS_E_UNSTABLE (after filling out) when the field is not finite
+ * or |U|_max >= sound speed. */
+int gks_forces(gks_ctx* ctx, gks_forces_out* out);
+
+/* Reset the window sums of power and thrust (gks_forces_out.window_*). Enqueued on the stream. */
+int gks_reset_window(gks_ctx* ctx);
+
+/* Bytes of device memory one checkpoint slot needs (one field, the time and dt of a step). */
+size_t gks_checkpoint_slot_bytes(const gks_config* cfg);
+
+/* Register a DEVICE buffer of `capacity` checkpoint slots (or NULL to stop). While registered, every
+ * gks_step stores Q^n (before the step) in slot (window step index) and the window sums are reset.
+ * Used by gks_adjoint to recompute each step. */
+int gks_set_checkpoints(gks_ctx* ctx, void* buffer, int32_t capacity);
+
+/* Bytes of device scratch gks_adjoint needs. */
+size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
+
+/* Reverse-mode gradient of J = w[0] * mean_n P^n + w[1] * mean_n T^n over the checkpointed window of
+ * nsteps steps with respect to the per-point force scalings s_p, written to grad_s (DEVICE, n_act
+ * doubles). The WENO nonlinear weights are frozen at their forward values (differentiated as
+ * constants); everything else is linearised exactly. FP64 contexts with periodic, wall or outflow
+ * boundaries and a fixed dt only. adj_ws: device scratch of gks_adjoint_workspace_bytes. */
+int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, void* adj_ws,
+                size_t adj_ws_bytes);
+
+/* Per-launch timing with HIP events recorded on the context's stream around each launch group.
+ * Categories (index into the arrays of gks_read_timing): */
+#define GKS_TIMER_GHOST 0      /* ghost-cell fills (3 launches per stage) */
+#define GKS_TIMER_DT 1         /* |U|max reduction and the dt update */
+#define GKS_TIMER_S1X 2        /* stage-1 face kernel, x faces */
+#define GKS_TIMER_S1Y 3
+#define GKS_TIMER_S1Z 4        /* includes the stage-1 S2O4 combination */
+#define GKS_TIMER_S2X 5        /* stage-2 face kernel, x faces */
+#define GKS_TIMER_S2Y 6
+#define GKS_TIMER_S2Z 7        /* includes the final combination and the constant body force */
+#define GKS_TIMER_ALM 8
+#define GKS_TIMER_IBM 9
+#define GKS_TIMER_OTHER 10     /* checkpoint copies and step bookkeeping */
+#define GKS_TIMER_COUNT 11
+
+/* Enable (1) or disable (0) event timing; enabling clears the accumulated totals. Host-side event
+ * objects are created on demand (no device memory). */
+int gks_set_timing(gks_ctx* ctx, int32_t enable);
+
+/* Synchronise the stream and return the accumulated milliseconds and launch-group counts per
+ * category (arrays of n <= GKS_TIMER_COUNT entries). */
+int gks_read_timing(gks_ctx* ctx, double* ms, int64_t* count, int32_t n);
+
+/* Release the host context (device buffers stay the caller's). */
+void gks_destroy(gks_ctx* ctx);
+
+/* Last error message of a context (or of the last failed gks_init when ctx is NULL). */
+const char* gks_last_error(const gks_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKS_H */

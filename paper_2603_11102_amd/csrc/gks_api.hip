@@ -1,0 +1,700 @@
+// gks_api.hip -- host side of the C ABI declared in include/gks.h: validation, workspace carving,
+// launch sequencing of one S2O4 step (Section 2) and the body-force update (Section 3.3) on the
+// caller's stream, and the FP64 result readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gks.h"
+#include "gks_adjoint.h"
+#include "gks_body.h"
+#include "gks_internal.h"
+
+using namespace gks;
+
+static thread_local std::string g_init_error;
+
+struct Carver {
+    char* base;
+    size_t off;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+    template <typename T>
+    T* ptr(size_t bytes) {
+        size_t o = take(bytes);
+        return base ? reinterpret_cast<T*>(base + o) : nullptr;
+    }
+};
+
+struct gks_ctx {
+    gks_config cfg;
+    GridDesc g;
+    size_t es;
+    void* q[4];
+    void* qs[4];
+    void* qa[4];
+    char* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    DevState* st;
+    void* r0[4];
+    void* r1[4];
+    double* diag_partials;
+    int diag_nblk;
+    double lam, c, hmin, eps;
+    int chunk[3];
+    int flags;
+    // actuator line model
+    int has_rotor;
+    AlmArgs alm;
+    double* alm_mem;   // start of the rotor block in the workspace
+    // immersed boundary
+    int has_ibm;
+    IbmArgs ibm;
+    char* ibm_mem;
+    // checkpoints
+    char* ckpt;
+    int ckpt_cap;
+    int ckpt_n;
+    // event timing
+    int timing;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_cat;   // category of each recorded pair
+    size_t ev_used;            // events in use (2 per pair)
+    double t_ms[GKS_TIMER_COUNT];
+    long long t_cnt[GKS_TIMER_COUNT];
+    std::string err;
+};
+
+namespace {
+
+const int kPerm[3][4] = {{0, 1, 2, 3}, {0, 2, 1, 3}, {0, 3, 1, 2}};  // local -> global variable
+const int kAxes[3][3] = {{0, 1, 2}, {1, 0, 2}, {2, 0, 1}};          // (normal, t1, t2) axes
+
+int fail(gks_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((ctx), GKS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_size(const gks_config* c) { return c->precision == GKS_FP32 ? 4 : 8; }
+
+// workspace layout; base == nullptr only measures
+struct Layout {
+    DevState* st;
+    void* r0[4];
+    void* r1[4];
+    double* diag;
+    char* alm;
+    char* ibm;
+    size_t total;
+};
+
+size_t alm_block_bytes(int n) {
+    if (n <= 0) return 0;
+    Carver cv{nullptr, 0};
+    for (int i = 0; i < 4; ++i) cv.take(sizeof(double) * n);          // r, chord, twist, width
+    cv.take(sizeof(double) * 3 * n);                                   // X
+    cv.take(sizeof(double) * 3 * n);                                   // fv
+    for (int i = 0; i < 5; ++i) cv.take(sizeof(double) * n);          // alpha, fx, ft, urel, phi
+    cv.take(sizeof(double) * 3 * n);                                   // sampled u
+    return cv.off;
+}
+
+size_t ibm_block_bytes(long long n) {
+    if (n <= 0) return 0;
+    const long long nc = 64 * n;
+    Carver cv{nullptr, 0};
+    cv.take(sizeof(double) * 3 * n);
+    cv.take(sizeof(double) * n);
+    cv.take(sizeof(int) * 3 * nc);
+    cv.take(sizeof(int) * (nc + 1));
+    cv.take(sizeof(int) * nc);
+    cv.take(sizeof(double) * nc);
+    cv.take(sizeof(double) * 3 * ((nc + 255) / 256));
+    return cv.off;
+}
+
+bool layout(const gks_config* c, char* base, Layout* L) {
+    const size_t es = elem_size(c);
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    Carver cv{base, 0};
+    L->st = cv.ptr<DevState>(sizeof(DevState));
+    for (int v = 0; v < 4; ++v) L->r0[v] = cv.ptr<void>(N * es);
+    for (int v = 0; v < 4; ++v) L->r1[v] = cv.ptr<void>(N * es);
+    L->diag = cv.ptr<double>(sizeof(double) * 4 * 1024);
+    size_t ab = alm_block_bytes(c->max_act);
+    L->alm = ab ? cv.ptr<char>(ab) : nullptr;
+    size_t ib = ibm_block_bytes(c->max_ibm);
+    L->ibm = ib ? cv.ptr<char>(ib) : nullptr;
+    L->total = cv.off;
+    return true;
+}
+
+std::string validate(const gks_config* c) {
+    if (!c) return "config is null";
+    if (c->nx < 3 || c->ny < 3 || c->nz < 3) return "nx, ny, nz must be >= 3";
+    if ((long long)c->nx * c->ny * c->nz > (1LL << 31)) return "grid too large (more than 2^31 cells)";
+    if (c->precision != GKS_FP32 && c->precision != GKS_FP64) return "precision must be GKS_FP32 or GKS_FP64";
+    if (!(c->lx > 0 && c->ly > 0 && c->lz > 0)) return "domain lengths must be > 0";
+    if (!(c->ma > 0 && c->u_ref > 0 && c->rho_ref > 0)) return "ma, u_ref and rho_ref must be > 0";
+    if (!(c->mu >= 0)) return "mu must be >= 0";
+    if (!(c->cfl > 0) && !(c->dt_fixed > 0)) return "either cfl > 0 or dt_fixed > 0";
+    for (int s = 0; s < 6; ++s)
+        if (c->bc[s] < GKS_BC_PERIODIC || c->bc[s] > GKS_BC_OUTFLOW) return "unknown boundary kind";
+    for (int a = 0; a < 3; ++a)
+        if ((c->bc[2 * a] == GKS_BC_PERIODIC) != (c->bc[2 * a + 1] == GKS_BC_PERIODIC))
+            return "periodic boundaries must be paired";
+    if (c->max_act < 0 || c->max_act > 1024) return "max_act must be in [0, 1024]";
+    if (c->max_ibm < 0 || c->max_ibm > (1LL << 24)) return "max_ibm must be in [0, 2^24]";
+    if (c->max_ibm > 0 && c->ibm_iters < 1) return "ibm_iters must be >= 1";
+    return "";
+}
+
+template <typename real>
+Field4<real> field(void* const p[4]) {
+    Field4<real> f;
+    for (int v = 0; v < 4; ++v) f.v[v] = static_cast<real*>(p[v]);
+    return f;
+}
+
+template <typename real>
+int ghost_all(gks_ctx* c, void* const p[4]) {
+    Field4<real> f = field<real>(p);
+    for (int a = 0; a < 3; ++a)
+        HIPCHK(c, launch_ghost<real>(f, c->g, a, c->cfg.bc[2 * a], c->cfg.bc[2 * a + 1], c->cfg.u_in, c->c,
+                                     c->cfg.rho_ref, c->stream));
+    return GKS_OK;
+}
+
+template <typename real>
+FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
+    FaceArgs<real> a;
+    std::memset(&a, 0, sizeof(a));
+    const int* pm = kPerm[d];
+    const int* ax = kAxes[d];
+    const long long ist[3] = {1, c->cfg.nx, (long long)c->cfg.nx * c->cfg.ny};
+    for (int v = 0; v < 4; ++v) {
+        const int gv = pm[v];
+        a.q[v] = static_cast<const real*>(src[gv]);
+        a.r0[v] = static_cast<real*>(c->r0[gv]);
+        a.r1[v] = static_cast<real*>(c->r1[gv]);
+        if (stage == 1) {
+            a.out_a[v] = static_cast<real*>(c->qs[gv]);
+            a.out_b[v] = static_cast<real*>(c->qa[gv]);
+            a.q_c[v] = static_cast<const real*>(c->q[gv]);
+        } else {
+            a.out_a[v] = static_cast<real*>(c->q[gv]);
+            a.s_in[v] = static_cast<const real*>(c->qa[gv]);
+        }
+    }
+    a.n_n = c->g.n[ax[0]];
+    a.n_t1 = c->g.n[ax[1]];
+    a.n_t2 = c->g.n[ax[2]];
+    a.tiles_t1 = (a.n_t1 + TILE1 - 1) / TILE1;
+    a.tiles_t2 = (a.n_t2 + TILE2 - 1) / TILE2;
+    a.chunk = c->chunk[d];
+    a.st_n = c->g.st[ax[0]];
+    a.st_t1 = c->g.st[ax[1]];
+    a.st_t2 = c->g.st[ax[2]];
+    a.ist_n = ist[ax[0]];
+    a.ist_t1 = ist[ax[1]];
+    a.ist_t2 = ist[ax[2]];
+    a.pad0 = c->g.pad0;
+    a.inv_hn = real(1.0 / c->g.h[ax[0]]);
+    a.inv_h1 = real(1.0 / c->g.h[ax[1]]);
+    a.inv_h2 = real(1.0 / c->g.h[ax[2]]);
+    a.eps = real(c->eps);
+    a.fc.lam = real(c->lam);
+    a.fc.sl = real(std::sqrt(c->lam));
+    a.fc.kk = real(1.0 / (2.0 * std::sqrt(M_PI * c->lam)));
+    a.fc.c2 = real(1.0 / (2.0 * c->lam));
+    a.fc.mu = real(c->cfg.mu);
+    a.fc.rho_ref = real(c->cfg.rho_ref);
+    for (int j = 0; j < 3; ++j) a.g_local[j] = real(c->cfg.body_force[pm[1 + j] - 1]);
+    a.dt_ptr = &c->st->dt;
+    a.mode = d == 0 ? 0 : (d == 1 ? 1 : 2);
+    return a;
+}
+
+int timing_flush(gks_ctx* c) {
+    if (c->ev_used == 0) return GKS_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t p = 0; p < c->ev_cat.size(); ++p) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * p], c->ev_pool[2 * p + 1]));
+        c->t_ms[c->ev_cat[p]] += ms;
+        c->t_cnt[c->ev_cat[p]] += 1;
+    }
+    c->ev_cat.clear();
+    c->ev_used = 0;
+    return GKS_OK;
+}
+
+// open a timed launch group; returns the pair index or -1 when timing is off
+int tbeg(gks_ctx* c, int cat) {
+    if (!c->timing) return -1;
+    if (c->ev_used + 2 > 4096 && timing_flush(c) != GKS_OK) return -1;
+    while (c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        c->ev_pool.push_back(e);
+    }
+    const size_t i = c->ev_used;
+    if (hipEventRecord(c->ev_pool[i], c->stream) != hipSuccess) return -1;
+    c->ev_used += 2;
+    c->ev_cat.push_back(cat);
+    return (int)(i / 2);
+}
+
+void tend(gks_ctx* c, int pair) {
+    if (pair >= 0) (void)hipEventRecord(c->ev_pool[2 * pair + 1], c->stream);
+}
+
+template <typename real>
+int steps(gks_ctx* c, int nsteps) {
+    const size_t field_bytes = (size_t)c->g.n_padded * sizeof(real);
+    const int cat1[3] = {GKS_TIMER_S1X, GKS_TIMER_S1Y, GKS_TIMER_S1Z};
+    const int cat2[3] = {GKS_TIMER_S2X, GKS_TIMER_S2Y, GKS_TIMER_S2Z};
+    for (int s = 0; s < nsteps; ++s) {
+        int tp;
+        if (c->ckpt && c->ckpt_n < c->ckpt_cap) {
+            tp = tbeg(c, GKS_TIMER_OTHER);
+            const size_t slot = gks_checkpoint_slot_bytes(&c->cfg);
+            char* dst = c->ckpt + (size_t)c->ckpt_n * slot;
+            for (int v = 0; v < 4; ++v)
+                HIPCHK(c, launch_copy_field(c->q[v], dst + v * ((field_bytes + 255) & ~size_t(255)), field_bytes,
+                                            c->stream));
+            HIPCHK(c, launch_copy_field(&c->st->t, dst + slot - 256, sizeof(double), c->stream));
+            tend(c, tp);
+            c->ckpt_n++;
+        }
+        tp = tbeg(c, GKS_TIMER_GHOST);
+        int rc = ghost_all<real>(c, c->q);
+        tend(c, tp);
+        if (rc) return rc;
+        tp = tbeg(c, GKS_TIMER_DT);
+        if (c->cfg.cfl > 0) HIPCHK(c, launch_umax<real>(field<real>(c->q), c->g, c->cfg.rho_ref, &c->st->umax2_bits, c->stream));
+        HIPCHK(c, launch_dt(c->st, c->cfg.cfl, c->hmin, c->c, c->cfg.dt_fixed, c->stream));
+        tend(c, tp);
+        for (int d = 0; d < 3; ++d) {
+            tp = tbeg(c, cat1[d]);
+            HIPCHK(c, launch_face<real>(face_args<real>(c, d, 1, c->q), 1, c->stream));
+            tend(c, tp);
+        }
+        tp = tbeg(c, GKS_TIMER_GHOST);
+        rc = ghost_all<real>(c, c->qs);
+        tend(c, tp);
+        if (rc) return rc;
+        for (int d = 0; d < 3; ++d) {
+            tp = tbeg(c, cat2[d]);
+            HIPCHK(c, launch_face<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream));
+            tend(c, tp);
+        }
+        if (c->has_rotor) {
+            tp = tbeg(c, GKS_TIMER_ALM);
+            HIPCHK(c, launch_alm<real>(field<real>(c->q), c->alm, c->stream));
+            tend(c, tp);
+        }
+        if (c->has_ibm) {
+            tp = tbeg(c, GKS_TIMER_IBM);
+            HIPCHK(c, launch_ibm<real>(field<real>(c->q), c->ibm, c->stream));
+            tend(c, tp);
+        }
+        tp = tbeg(c, GKS_TIMER_OTHER);
+        HIPCHK(c, launch_finish(c->st, c->has_rotor, c->stream));
+        tend(c, tp);
+    }
+    return GKS_OK;
+}
+
+}  // namespace
+
+// ================================================================================================
+// C ABI
+// ================================================================================================
+extern "C" {
+
+size_t gks_workspace_bytes(const gks_config* cfg) {
+    if (!validate(cfg).empty()) return 0;
+    Layout L;
+    layout(cfg, nullptr, &L);
+    return L.total;
+}
+
+size_t gks_checkpoint_slot_bytes(const gks_config* cfg) {
+    if (!validate(cfg).empty()) return 0;
+    const size_t np = (size_t)(cfg->nx + 6) * (cfg->ny + 6) * (cfg->nz + 6);
+    const size_t fb = ((np * elem_size(cfg)) + 255) & ~size_t(255);
+    return 4 * fb + 256;
+}
+
+int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_acc, void* workspace,
+             size_t workspace_bytes, void* hip_stream, gks_ctx** out) {
+    if (!out) return fail(nullptr, GKS_E_INVALID_ARG, "out is null");
+    *out = nullptr;
+    std::string why = validate(cfg);
+    if (!why.empty()) return fail(nullptr, GKS_E_INVALID_ARG, why);
+    void* qp[4] = {q.rho, q.mx, q.my, q.mz};
+    void* sp[4] = {q_stage.rho, q_stage.mx, q_stage.my, q_stage.mz};
+    void* ap[4] = {q_acc.rho, q_acc.mx, q_acc.my, q_acc.mz};
+    for (int v = 0; v < 4; ++v)
+        if (!qp[v] || !sp[v] || !ap[v]) return fail(nullptr, GKS_E_INVALID_ARG, "a field pointer is null");
+    if (!workspace) return fail(nullptr, GKS_E_INVALID_ARG, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(nullptr, GKS_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    Layout L;
+    layout(cfg, nullptr, &L);
+    if (workspace_bytes < L.total)
+        return fail(nullptr, GKS_E_INVALID_ARG,
+                    "workspace too small: need " + std::to_string(L.total) + " bytes (gks_workspace_bytes)");
+    gks_ctx* c = new (std::nothrow) gks_ctx();
+    if (!c) return fail(nullptr, GKS_E_INVALID_ARG, "out of host memory");
+    c->cfg = *cfg;
+    if (!(c->cfg.weno_eps > 0)) c->cfg.weno_eps = 1e-6;
+    c->es = elem_size(cfg);
+    for (int v = 0; v < 4; ++v) {
+        c->q[v] = qp[v];
+        c->qs[v] = sp[v];
+        c->qa[v] = ap[v];
+    }
+    c->ws = static_cast<char*>(workspace);
+    c->ws_bytes = workspace_bytes;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    layout(cfg, c->ws, &L);
+    c->st = L.st;
+    for (int v = 0; v < 4; ++v) {
+        c->r0[v] = L.r0[v];
+        c->r1[v] = L.r1[v];
+    }
+    c->diag_partials = L.diag;
+    c->alm_mem = reinterpret_cast<double*>(L.alm);
+    c->ibm_mem = L.ibm;
+    const int n[3] = {cfg->nx, cfg->ny, cfg->nz};
+    const double len[3] = {cfg->lx, cfg->ly, cfg->lz};
+    const double org[3] = {cfg->x0, cfg->y0, cfg->z0};
+    for (int a = 0; a < 3; ++a) {
+        c->g.n[a] = n[a];
+        c->g.h[a] = len[a] / n[a];
+        c->g.x0[a] = org[a];
+    }
+    c->g.st[0] = 1;
+    c->g.st[1] = n[0] + 6;
+    c->g.st[2] = (long long)(n[0] + 6) * (n[1] + 6);
+    c->g.pad0 = 3 * (c->g.st[0] + c->g.st[1] + c->g.st[2]);
+    c->g.n_padded = (long long)(n[0] + 6) * (n[1] + 6) * (n[2] + 6);
+    c->lam = cfg->ma * cfg->ma / (2.0 * cfg->u_ref * cfg->u_ref);
+    c->c = std::sqrt(1.0 / (2.0 * c->lam));
+    c->hmin = std::min(c->g.h[0], std::min(c->g.h[1], c->g.h[2]));
+    c->eps = c->cfg.weno_eps;
+    c->diag_nblk = diag_blocks(c->g);
+    c->flags = cfg->ma > 0.3 ? GKS_WARN_MACH : 0;
+    for (int d = 0; d < 3; ++d) {
+        const int* ax = kAxes[d];
+        const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + TILE2 - 1) / TILE2);
+        c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles) : face_chunk<double>(n[ax[0]], tiles);
+    }
+    hipError_t e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
+    if (e != hipSuccess) {
+        g_init_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+        delete c;
+        return GKS_E_HIP;
+    }
+    int rc = cfg->precision == GKS_FP32 ? ghost_all<float>(c, c->q) : ghost_all<double>(c, c->q);
+    if (rc) {
+        g_init_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return GKS_OK;
+}
+
+int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (!r) return fail(c, GKS_E_INVALID_ARG, "rotor is null");
+    const int n = r->n_blades * r->n_per_blade;
+    if (r->n_blades < 1 || r->n_per_blade < 1) return fail(c, GKS_E_INVALID_ARG, "n_blades and n_per_blade must be >= 1");
+    if (n > c->cfg.max_act) return fail(c, GKS_E_INVALID_ARG, "more actuator points than config.max_act");
+    if (!r->r || !r->chord || !r->twist || !r->width) return fail(c, GKS_E_INVALID_ARG, "rotor arrays are null");
+    if (!(r->eps > 0) || !(r->radius > 0) || !(r->u_inf > 0)) return fail(c, GKS_E_INVALID_ARG, "eps, radius and u_inf must be > 0");
+    double rmax = 0.0;
+    for (int i = 0; i < r->n_per_blade; ++i) {
+        if (!(r->r[i] >= 0) || !(r->chord[i] >= 0) || !(r->width[i] >= 0))
+            return fail(c, GKS_E_INVALID_ARG, "negative radius, chord or width");
+        rmax = std::max(rmax, r->r[i]);
+    }
+    if (r->u_inf_correction) {
+        for (int i = 0; i < r->n_per_blade; ++i)
+            if (r->chord[i] * (r->cd0 + r->cd2 * (M_PI * M_PI)) >= 4.0 * std::sqrt(M_PI) * r->eps)
+                return fail(c, GKS_E_INVALID_ARG, "free-stream correction denominator can vanish (chord too large for eps)");
+    }
+    // box of cells the rotor can touch: projection spheres (3 eps) around the swept disc, plus the
+    // trilinear sampling cells; it must lie inside the interior cells
+    const double ext = 3.0 * r->eps;
+    const double lo[3] = {r->hub[0] - ext, r->hub[1] - rmax - ext, r->hub[2] - rmax - ext};
+    const double hi[3] = {r->hub[0] + ext, r->hub[1] + rmax + ext, r->hub[2] + rmax + ext};
+    AlmArgs& a = c->alm;
+    std::memset(&a, 0, sizeof(a));
+    for (int d = 0; d < 3; ++d) {
+        int i0 = (int)std::ceil((lo[d] - c->g.x0[d]) / c->g.h[d] - 0.5);
+        int i1 = (int)std::floor((hi[d] - c->g.x0[d]) / c->g.h[d] - 0.5);
+        // sampling cells of any point on the disc
+        const double slo = (d == 0 ? r->hub[0] : r->hub[d] - rmax), shi = (d == 0 ? r->hub[0] : r->hub[d] + rmax);
+        const int s0 = (int)std::floor((slo - c->g.x0[d]) / c->g.h[d] - 0.5);
+        const int s1 = (int)std::floor((shi - c->g.x0[d]) / c->g.h[d] - 0.5) + 1;
+        if (std::min(i0, s0) < 0 || std::max(i1, s1) >= c->g.n[d])
+            return fail(c, GKS_E_INVALID_ARG, "rotor (points, sampling cells or 3 eps spheres) leaves the interior cells");
+        a.box_lo[d] = i0;
+        a.box_n[d] = i1 - i0 + 1;
+    }
+    a.n_act = n;
+    a.nb = r->n_blades;
+    a.npb = r->n_per_blade;
+    a.corr = r->u_inf_correction ? 1 : 0;
+    for (int d = 0; d < 3; ++d) a.hub[d] = r->hub[d];
+    a.omega = r->omega;
+    a.theta0 = r->theta0;
+    a.radius = r->radius;
+    a.u_inf = r->u_inf;
+    a.eps = r->eps;
+    a.cl_slope = r->cl_slope;
+    a.alpha_clip = r->alpha_clip;
+    a.cd0 = r->cd0;
+    a.cd2 = r->cd2;
+    a.rho_ref = c->cfg.rho_ref;
+    a.area = M_PI * r->radius * r->radius;
+    const int cap = c->cfg.max_act;
+    Carver cv{reinterpret_cast<char*>(c->alm_mem), 0};
+    double* tab[4];
+    for (int i = 0; i < 4; ++i) tab[i] = cv.ptr<double>(sizeof(double) * cap);
+    a.r = tab[0];
+    a.chord = tab[1];
+    a.twist = tab[2];
+    a.width = tab[3];
+    a.X = cv.ptr<double>(sizeof(double) * 3 * cap);
+    a.fv = cv.ptr<double>(sizeof(double) * 3 * cap);
+    a.out_alpha = cv.ptr<double>(sizeof(double) * cap);
+    a.out_fx = cv.ptr<double>(sizeof(double) * cap);
+    a.out_ft = cv.ptr<double>(sizeof(double) * cap);
+    a.out_urel = cv.ptr<double>(sizeof(double) * cap);
+    a.out_phi = cv.ptr<double>(sizeof(double) * cap);
+    a.out_u = cv.ptr<double>(sizeof(double) * 3 * cap);
+    a.scale = r->scale;
+    a.g = c->g;
+    a.st = c->st;
+    const double* src[4] = {r->r, r->chord, r->twist, r->width};
+    for (int i = 0; i < 4; ++i)
+        HIPCHK(c, hipMemcpyAsync(tab[i], src[i], sizeof(double) * r->n_per_blade, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (r->eps < 2.0 * c->hmin) c->flags |= GKS_WARN_EPS_SMALL;
+    else c->flags &= ~GKS_WARN_EPS_SMALL;
+    c->has_rotor = 1;
+    return GKS_OK;
+}
+
+int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* dS, const double* vel) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (vel) return fail(c, GKS_E_UNSUPPORTED, "moving Lagrangian points are not supported (vel must be NULL)");
+    if (n <= 0 || !xyz || !dS) return fail(c, GKS_E_INVALID_ARG, "need n > 0 points with xyz and dS");
+    if (n > c->cfg.max_ibm) return fail(c, GKS_E_INVALID_ARG, "more Lagrangian points than config.max_ibm");
+    // host-side binning (index work only): every (cell, point) pair of the 4x4x4 supports, sorted by
+    // cell and then point, gives the cell list and a CSR of contributing points per cell
+    std::vector<long long> keys;
+    keys.reserve((size_t)n * 64);
+    const long long nx = c->g.n[0], ny = c->g.n[1];
+    for (long long p = 0; p < n; ++p) {
+        if (!(dS[p] >= 0)) return fail(c, GKS_E_INVALID_ARG, "negative surface element");
+        int i0[3];
+        for (int d = 0; d < 3; ++d) {
+            const double f = (xyz[3 * p + d] - c->g.x0[d]) / c->g.h[d] - 0.5;
+            if (!std::isfinite(f)) return fail(c, GKS_E_INVALID_ARG, "non-finite point coordinate");
+            i0[d] = (int)std::floor(f);
+            if (i0[d] - 1 < 0 || i0[d] + 2 >= c->g.n[d])
+                return fail(c, GKS_E_INVALID_ARG, "a Lagrangian point's 4x4x4 support leaves the interior cells");
+        }
+        for (int dk = -1; dk <= 2; ++dk)
+            for (int dj = -1; dj <= 2; ++dj)
+                for (int di = -1; di <= 2; ++di) {
+                    const long long cell = ((long long)(i0[2] + dk) * ny + (i0[1] + dj)) * nx + (i0[0] + di);
+                    keys.push_back(cell * (1LL << 25) + p);
+                }
+    }
+    std::sort(keys.begin(), keys.end());
+    std::vector<int> cells, csr, ent;
+    csr.push_back(0);
+    long long last = -1;
+    for (long long kv : keys) {
+        const long long cell = kv >> 25;
+        const int p = (int)(kv & ((1LL << 25) - 1));
+        if (cell != last) {
+            if (last >= 0) csr.push_back((int)ent.size());
+            cells.push_back((int)(cell % nx));
+            cells.push_back((int)((cell / nx) % ny));
+            cells.push_back((int)(cell / (nx * ny)));
+            last = cell;
+        }
+        ent.push_back(p);
+    }
+    csr.push_back((int)ent.size());
+    const int ncell = (int)(cells.size() / 3);
+    const long long cap = c->cfg.max_ibm, nc = 64 * cap;
+    Carver cv{c->ibm_mem, 0};
+    IbmArgs& a = c->ibm;
+    std::memset(&a, 0, sizeof(a));
+    double* dx = cv.ptr<double>(sizeof(double) * 3 * cap);
+    double* ds = cv.ptr<double>(sizeof(double) * cap);
+    int* dcell = cv.ptr<int>(sizeof(int) * 3 * nc);
+    int* dcsr = cv.ptr<int>(sizeof(int) * (nc + 1));
+    int* dent = cv.ptr<int>(sizeof(int) * nc);
+    a.vbar = cv.ptr<double>(sizeof(double) * nc);
+    a.partials = cv.ptr<double>(sizeof(double) * 3 * ((nc + 255) / 256));
+    a.xyz = dx;
+    a.dS = ds;
+    a.cell = dcell;
+    a.csr = dcsr;
+    a.ent = dent;
+    a.npts = (int)n;
+    a.ncell = ncell;
+    a.iters = c->cfg.ibm_iters;
+    a.rho_ref = c->cfg.rho_ref;
+    a.g = c->g;
+    a.st = c->st;
+    HIPCHK(c, hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ds, dS, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dcell, cells.data(), sizeof(int) * cells.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dcsr, csr.data(), sizeof(int) * csr.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_ibm_vbar(a, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_ibm = 1;
+    return GKS_OK;
+}
+
+int gks_step(gks_ctx* c, int32_t nsteps) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (nsteps < 0) return fail(c, GKS_E_INVALID_ARG, "nsteps must be >= 0");
+    return c->cfg.precision == GKS_FP32 ? steps<float>(c, nsteps) : steps<double>(c, nsteps);
+}
+
+int gks_forces(gks_ctx* c, gks_forces_out* out) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (!out) return fail(c, GKS_E_INVALID_ARG, "out is null");
+    if (c->cfg.precision == GKS_FP32)
+        HIPCHK(c, launch_diag<float>(field<float>(c->q), c->g, c->cfg.rho_ref, c->diag_partials, c->diag_nblk, c->st, c->stream));
+    else
+        HIPCHK(c, launch_diag<double>(field<double>(c->q), c->g, c->cfg.rho_ref, c->diag_partials, c->diag_nblk, c->st, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    DevState h;
+    HIPCHK(c, hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    out->t = h.t;
+    out->dt = h.dt;
+    out->step = h.step;
+    out->thrust = h.thrust;
+    out->torque = h.torque;
+    out->power = h.power;
+    out->cp = h.cp;
+    out->ct = h.ct;
+    for (int d = 0; d < 3; ++d) out->ibm_force[d] = h.ibm_force[d];
+    double rb;
+    std::memcpy(&rb, &h.ibm_res_bits, sizeof(double));
+    out->ibm_residual = c->has_ibm ? rb : 0.0;
+    out->ibm_iters_used = c->has_ibm ? h.ibm_iters_used : 0;
+    out->flags = c->flags;
+    out->mass = h.mass;
+    for (int d = 0; d < 3; ++d) out->mom[d] = h.mom[d];
+    double u2;
+    std::memcpy(&u2, &h.umax_diag_bits, sizeof(double));
+    out->umax = std::sqrt(u2);
+    out->window_power = h.win_p;
+    out->window_thrust = h.win_t;
+    out->window_steps = h.win_n;
+    if (c->has_rotor) {
+        const int n = c->alm.n_act;
+        if (out->alpha) HIPCHK(c, hipMemcpy(out->alpha, c->alm.out_alpha, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (out->fx) HIPCHK(c, hipMemcpy(out->fx, c->alm.out_fx, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (out->ftheta) HIPCHK(c, hipMemcpy(out->ftheta, c->alm.out_ft, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (out->urel) HIPCHK(c, hipMemcpy(out->urel, c->alm.out_urel, sizeof(double) * n, hipMemcpyDeviceToHost));
+    }
+    if (h.nonfinite || !std::isfinite(out->mass)) return fail(c, GKS_E_NONFINITE, "non-finite value in the field");
+    if (!(out->umax < c->c)) return fail(c, GKS_E_UNSTABLE, "|U|max reached the sound speed");
+    return GKS_OK;
+}
+
+int gks_reset_window(gks_ctx* c) {
+    if (!c) return GKS_E_INVALID_ARG;
+    HIPCHK(c, launch_window_reset(c->st, c->stream));
+    return GKS_OK;
+}
+
+int gks_set_checkpoints(gks_ctx* c, void* buffer, int32_t capacity) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (buffer && capacity < 1) return fail(c, GKS_E_INVALID_ARG, "capacity must be >= 1");
+    if (buffer && reinterpret_cast<uintptr_t>(buffer) % 256) return fail(c, GKS_E_INVALID_ARG, "checkpoint buffer must be 256-byte aligned");
+    c->ckpt = static_cast<char*>(buffer);
+    c->ckpt_cap = buffer ? capacity : 0;
+    c->ckpt_n = 0;
+    HIPCHK(c, launch_window_reset(c->st, c->stream));
+    return GKS_OK;
+}
+
+size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act) {
+    if (!validate(cfg).empty() || n_act < 0) return 0;
+    return adjoint_workspace_bytes(cfg->nx, cfg->ny, cfg->nz, n_act);
+}
+
+int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, void* adj_ws, size_t adj_ws_bytes) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (!w || !grad_s || !adj_ws) return fail(c, GKS_E_INVALID_ARG, "null argument");
+    return fail(c, GKS_E_UNSUPPORTED, "adjoint not available in this build");
+    (void)nsteps;
+    (void)adj_ws_bytes;
+}
+
+int gks_set_timing(gks_ctx* c, int32_t enable) {
+    if (!c) return GKS_E_INVALID_ARG;
+    int rc = timing_flush(c);
+    if (rc) return rc;
+    c->timing = enable ? 1 : 0;
+    for (int i = 0; i < GKS_TIMER_COUNT; ++i) {
+        c->t_ms[i] = 0.0;
+        c->t_cnt[i] = 0;
+    }
+    return GKS_OK;
+}
+
+int gks_read_timing(gks_ctx* c, double* ms, int64_t* count, int32_t n) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (n < 0 || n > GKS_TIMER_COUNT || (n > 0 && (!ms || !count))) return fail(c, GKS_E_INVALID_ARG, "bad timing arrays");
+    int rc = timing_flush(c);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        ms[i] = c->t_ms[i];
+        count[i] = c->t_cnt[i];
+    }
+    return GKS_OK;
+}
+
+void gks_destroy(gks_ctx* c) {
+    if (!c) return;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* gks_last_error(const gks_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,272 @@
+// gks_aux.hip -- ghost cells, CFL time step, step bookkeeping and FP64 diagnostics.
+//
+// Boundary ghost cells (three layers) follow the boundary conditions named in Section 4:
+// periodic; no-slip isothermal wall (mirror, rho even, all momenta odd); slip / symmetry wall
+// (mirror, normal momentum odd); inflow with prescribed velocity and the density from the outgoing
+// isothermal Riemann invariant U -+ C ln rho; zero-gradient outflow. Axes are filled x, then y, then z
+// over the full padded extent of the other axes, so edges and corners are consistent.
+// Time step: dt = CFL min(dx, dy, dz) / (|U|_max + C), C = sqrt(1/(2 lambda)) (Section 2).
+#include "gks_internal.h"
+
+namespace gks {
+
+struct GhostArgs {
+    int axis, n, np1, np2;
+    long long st_a, st_1, st_2;
+    int bc_lo, bc_hi;
+    double u_in[3];
+    double c, rho_ref;
+};
+
+template <typename real>
+__global__ void ghost_kernel(Field4<real> f, GhostArgs g) {
+    const long long per_side = 3LL * g.np1 * g.np2;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * per_side) return;
+    const int side = (int)(t / per_side);
+    long long r = t % per_side;
+    const int layer = (int)(r / ((long long)g.np1 * g.np2));
+    r %= (long long)g.np1 * g.np2;
+    const int p1 = (int)(r % g.np1), p2 = (int)(r / g.np1);
+    const long long base = (long long)p1 * g.st_1 + (long long)p2 * g.st_2;
+    // padded index along the axis: interior cell i sits at i + 3
+    const int gi = side == 0 ? (2 - layer) : (g.n + 3 + layer);
+    const int kind = side == 0 ? g.bc_lo : g.bc_hi;
+    const long long dst = base + (long long)gi * g.st_a;
+    int src_i;
+    if (kind == 0) src_i = side == 0 ? (g.n - 1 - layer) : layer;                      // periodic
+    else if (kind == 1 || kind == 2) src_i = side == 0 ? layer : (g.n - 1 - layer);    // mirror
+    else src_i = side == 0 ? 0 : g.n - 1;                                              // adjacent cell
+    const long long src = base + (long long)(src_i + 3) * g.st_a;
+    if (kind == 0 || kind == 4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f.v[v][dst] = f.v[v][src];
+    } else if (kind == 1) {
+        f.v[0][dst] = f.v[0][src];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) f.v[v][dst] = -f.v[v][src];
+    } else if (kind == 2) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f.v[v][dst] = (v == 1 + g.axis) ? -f.v[v][src] : f.v[v][src];
+    } else {  // inflow
+        const double rp = (double)f.v[0][src];
+        const double rho_i = g.rho_ref + rp;
+        const double un = (double)f.v[1 + g.axis][src] / rho_i;
+        const double x = side == 0 ? (g.u_in[g.axis] - un) / g.c : (un - g.u_in[g.axis]) / g.c;
+        const double rho_g = rho_i * exp(x);
+        f.v[0][dst] = (real)(rp * exp(x) + g.rho_ref * expm1(x));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) f.v[1 + j][dst] = (real)(rho_g * g.u_in[j]);
+    }
+}
+
+template <typename real>
+hipError_t launch_ghost(Field4<real> f, const GridDesc& gd, int axis, int bc_lo, int bc_hi, const double u_in[3],
+                        double c, double rho_ref, hipStream_t s) {
+    GhostArgs g;
+    g.axis = axis;
+    g.n = gd.n[axis];
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    g.np1 = gd.n[a1] + 6;
+    g.np2 = gd.n[a2] + 6;
+    g.st_a = gd.st[axis];
+    g.st_1 = gd.st[a1];
+    g.st_2 = gd.st[a2];
+    g.bc_lo = bc_lo;
+    g.bc_hi = bc_hi;
+    for (int j = 0; j < 3; ++j) g.u_in[j] = u_in[j];
+    g.c = c;
+    g.rho_ref = rho_ref;
+    const long long total = 2LL * 3 * g.np1 * g.np2;
+    const int bs = 256;
+    hipLaunchKernelGGL((ghost_kernel<real>), dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, f, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// max |U|^2 over the interior cells (as a double; max is order independent, so the result is
+// deterministic)
+// ------------------------------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(256) umax_kernel(Field4<real> f, GridDesc g, double rho_ref,
+                                                   unsigned long long* out) {
+    __shared__ double red[256];
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    double mx = 0.0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % g.n[0]);
+        const long long r = c / g.n[0];
+        const int j = (int)(r % g.n[1]);
+        const int k = (int)(r / g.n[1]);
+        const long long p = g.pad0 + i * g.st[0] + j * g.st[1] + (long long)k * g.st[2];
+        const double rho = rho_ref + (double)f.v[0][p];
+        const double u = (double)f.v[1][p] / rho, v = (double)f.v[2][p] / rho, w = (double)f.v[3][p] / rho;
+        const double s2 = u * u + v * v + w * w;
+        mx = s2 > mx ? s2 : mx;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+template <typename real>
+hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, unsigned long long* out, hipStream_t s) {
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    long long blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL((umax_kernel<real>), dim3((unsigned)blocks), dim3(256), 0, s, f, g, rho_ref, out);
+    return hipGetLastError();
+}
+
+__global__ void dt_kernel(DevState* st, double cfl, double hmin, double c, double dt_fixed) {
+    if (threadIdx.x != 0) return;
+    double dt;
+    if (cfl > 0.0) {
+        const double u = sqrt(__longlong_as_double((long long)st->umax2_bits));
+        dt = cfl * hmin / (u + c);
+    } else {
+        dt = dt_fixed;
+    }
+    st->dt = dt;
+    st->t_next = st->t + dt;
+    st->umax2_bits = 0ULL;
+    st->ibm_res_bits = 0ULL;
+}
+
+hipError_t launch_dt(DevState* st, double cfl, double hmin, double c, double dt_fixed, hipStream_t s) {
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(64), 0, s, st, cfl, hmin, c, dt_fixed);
+    return hipGetLastError();
+}
+
+__global__ void finish_kernel(DevState* st, int has_rotor) {
+    if (threadIdx.x != 0) return;
+    st->t = st->t_next;
+    st->step += 1;
+    if (has_rotor) {
+        st->win_p += st->power;
+        st->win_t += st->thrust;
+    }
+    st->win_n += 1;
+}
+
+hipError_t launch_finish(DevState* st, int has_rotor, hipStream_t s) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, st, has_rotor);
+    return hipGetLastError();
+}
+
+__global__ void window_reset_kernel(DevState* st) {
+    if (threadIdx.x != 0) return;
+    st->win_p = 0.0;
+    st->win_t = 0.0;
+    st->win_n = 0;
+}
+
+hipError_t launch_window_reset(DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(window_reset_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// FP64 conservation sums, max |U| and a non-finite flag; fixed-order block partials then one block
+// ------------------------------------------------------------------------------------------------
+int diag_blocks(const GridDesc& g) {
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    long long b = (n + 255) / 256;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) diag_kernel(Field4<real> f, GridDesc g, double rho_ref, double* partials,
+                                                   DevState* st) {
+    __shared__ double red[4][256];
+    __shared__ double mxs[256];
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    double s[4] = {0, 0, 0, 0};
+    double mx = 0.0;
+    int bad = 0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % g.n[0]);
+        const long long r = c / g.n[0];
+        const int j = (int)(r % g.n[1]);
+        const int k = (int)(r / g.n[1]);
+        const long long p = g.pad0 + i * g.st[0] + j * g.st[1] + (long long)k * g.st[2];
+        double q[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            q[v] = (double)f.v[v][p];
+            s[v] += q[v];
+            if (!isfinite(q[v])) bad = 1;
+        }
+        const double rho = rho_ref + q[0];
+        const double s2 = (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / (rho * rho);
+        mx = s2 > mx ? s2 : mx;
+    }
+    for (int v = 0; v < 4; ++v) red[v][threadIdx.x] = s[v];
+    mxs[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            for (int v = 0; v < 4; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + w];
+            mxs[threadIdx.x] = fmax(mxs[threadIdx.x], mxs[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < 4; ++v) partials[4 * blockIdx.x + v] = red[v][0];
+        atomicMax(&st->umax_diag_bits, (unsigned long long)__double_as_longlong(mxs[0]));
+    }
+    if (bad) atomicOr(&st->nonfinite, 1);
+}
+
+__global__ void __launch_bounds__(256) diag_final_kernel(const double* partials, int nblk, DevState* st, double vol) {
+    __shared__ double red[4][256];
+    double s[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int v = 0; v < 4; ++v) s[v] += partials[4 * b + v];
+    for (int v = 0; v < 4; ++v) red[v][threadIdx.x] = s[v];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int v = 0; v < 4; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->mass = red[0][0] * vol;
+        for (int v = 0; v < 3; ++v) st->mom[v] = red[1 + v][0] * vol;
+    }
+}
+
+__global__ void diag_reset_kernel(DevState* st) {
+    if (threadIdx.x == 0) {
+        st->umax_diag_bits = 0ULL;
+        st->nonfinite = 0;
+    }
+}
+
+template <typename real>
+hipError_t launch_diag(Field4<real> f, const GridDesc& g, double rho_ref, double* partials, int nblk, DevState* st,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL((diag_kernel<real>), dim3(nblk), dim3(256), 0, s, f, g, rho_ref, partials, st);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, (const double*)partials, nblk, st,
+                       g.h[0] * g.h[1] * g.h[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+template hipError_t launch_ghost<float>(Field4<float>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
+template hipError_t launch_ghost<double>(Field4<double>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
+template hipError_t launch_umax<float>(Field4<float>, const GridDesc&, double, unsigned long long*, hipStream_t);
+template hipError_t launch_umax<double>(Field4<double>, const GridDesc&, double, unsigned long long*, hipStream_t);
+template hipError_t launch_diag<float>(Field4<float>, const GridDesc&, double, double*, int, DevState*, hipStream_t);
+template hipError_t launch_diag<double>(Field4<double>, const GridDesc&, double, double*, int, DevState*, hipStream_t);
+
+}  // namespace gks

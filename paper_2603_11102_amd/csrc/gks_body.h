@@ -1,0 +1,51 @@
+// gks_body.h -- argument blocks of the actuator-line and immersed-boundary kernels (internal).
+#pragma once
+
+#include "gks_internal.h"
+
+namespace gks {
+
+struct AlmArgs {
+    int n_act, nb, npb, corr;
+    double hub[3];
+    double omega, theta0, radius, u_inf, eps, cl_slope, alpha_clip, cd0, cd2, rho_ref, area;
+    const double* r;      // device, npb
+    const double* chord;  // device, npb
+    const double* twist;  // device, npb
+    const double* width;  // device, npb
+    const double* scale;  // device, n_act, or null
+    double* X;            // device, 3 n_act: point positions of the step
+    double* fv;           // device, 3 n_act: force on the fluid per point
+    double* out_alpha;    // device, n_act
+    double* out_fx;
+    double* out_ft;
+    double* out_urel;
+    double* out_phi;
+    double* out_u;        // device, 3 n_act: sampled velocity
+    int box_lo[3], box_n[3];
+    GridDesc g;
+    DevState* st;
+};
+
+struct IbmArgs {
+    int npts, ncell, iters;
+    double rho_ref;
+    const double* xyz;    // device, 3 npts
+    const double* dS;     // device, npts
+    const int* cell;      // device, 3 ncell: (i, j, k) of every cell in some point's support
+    const int* csr;       // device, ncell + 1
+    const int* ent;       // device, point indices per cell (ascending)
+    double* vbar;         // device, ncell
+    double* partials;     // device, 3 * ceil(ncell / 256)
+    GridDesc g;
+    DevState* st;
+};
+
+template <typename real>
+hipError_t launch_alm(Field4<real> f, const AlmArgs& a, hipStream_t s);
+hipError_t launch_ibm_vbar(const IbmArgs& a, hipStream_t s);
+template <typename real>
+hipError_t launch_ibm(Field4<real> f, const IbmArgs& a, hipStream_t s);
+int ibm_blocks(int ncell);
+
+}  // namespace gks

@@ -1,0 +1,308 @@
+// gks_body.hip -- external body forces applied after the S2O4 step (Section 3.3):
+//   * actuator line model (Section 3.1): trilinear sampling of U at each actuator point, blade-element
+//     forces (Eq. (axial-tangential)) with the optional free-stream correction, Gaussian projection
+//     (Eq. (Gaussian)) truncated at 3 eps; rotor thrust / torque / power / C_P / C_T reduced in FP64
+//     (Section 4.4.1);
+//   * direct-forcing immersed boundary (Section 3.2): Peskin 4-point delta weights, static volumes
+//     V-bar = sum_p W V_p with V_p = dx dS_p, per-cell forcing iterations (Eq. (ibm-1)), total force
+//     (Eq. (force-ibm)) reduced in FP64, interpolation residual at the points.
+// Every sum runs in a fixed order (one thread per output, gather form, tree reductions): results are
+// bitwise reproducible and no floating-point atomics are used.
+#include "gks_body.h"
+
+namespace gks {
+
+__device__ __forceinline__ double phi4d(double r) {
+    r = fabs(r);
+    if (r <= 1.0) return (3.0 - 2.0 * r + sqrt(1.0 + 4.0 * r - 4.0 * r * r)) * 0.125;
+    if (r < 2.0) return (5.0 - 2.0 * r - sqrt(-7.0 + 12.0 * r - 4.0 * r * r)) * 0.125;
+    return 0.0;
+}
+
+__device__ __forceinline__ long long pidx(const GridDesc& g, int i, int j, int k) {
+    return g.pad0 + (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
+}
+
+// ------------------------------------------------------------------------------------------------
+// ALM: one workgroup, one thread per actuator point
+// ------------------------------------------------------------------------------------------------
+template <typename real>
+__global__ void __launch_bounds__(1024) alm_points_kernel(Field4<real> f, AlmArgs a) {
+    __shared__ double red_t[1024];
+    __shared__ double red_q[1024];
+    const int p = threadIdx.x;
+    double fx = 0.0, ft = 0.0, rr = 0.0;
+    const double t = a.st->t_next;
+    if (p < a.n_act) {
+        const int bl = p / a.npb, ip = p % a.npb;
+        const double th = a.theta0 + a.omega * t + 2.0 * M_PI * (double)bl / (double)a.nb;
+        const double cth = cos(th), sth = sin(th);
+        rr = a.r[ip];
+        const double X[3] = {a.hub[0], a.hub[1] + rr * cth, a.hub[2] + rr * sth};
+        const double et[3] = {0.0, -sth, cth};
+        // trilinear sampling of U = (rho U)/rho at cell centres
+        int i0[3];
+        double w1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double fc = (X[d] - a.g.x0[d]) / a.g.h[d] - 0.5;
+            const double fl = floor(fc);
+            i0[d] = (int)fl;
+            w1[d] = fc - fl;
+        }
+        double U[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) *
+                                     (dz ? w1[2] : 1.0 - w1[2]);
+                    const long long q = pidx(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+                    const double rho = a.rho_ref + (double)f.v[0][q];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) U[c] += w * ((double)f.v[1 + c][q] / rho);
+                }
+        double ux = U[0];
+        double ut = U[1] * et[1] + U[2] * et[2];
+        const double om = a.omega;
+        const double chord = a.chord[ip], twist = a.twist[ip], width = a.width[ip];
+        if (a.corr) {
+            const double phi0 = atan2(ux, om * rr - ut);
+            const double al0 = phi0 - twist;
+            const double cd0 = a.cd0 + a.cd2 * al0 * al0;
+            const double fac = 1.0 / (1.0 - cd0 * chord / (4.0 * sqrt(M_PI) * a.eps));
+            ux *= fac;
+            ut *= fac;
+        }
+        const double phi = atan2(ux, om * rr - ut);
+        const double alpha = phi - twist;
+        const double wr = ut - om * rr;
+        const double urel2 = ux * ux + wr * wr;
+        const double alc = fmin(fmax(alpha, -a.alpha_clip), a.alpha_clip);
+        const double cl = a.cl_slope * alc;
+        const double cd = a.cd0 + a.cd2 * alpha * alpha;
+        const double q = 0.5 * a.rho_ref * chord * width * urel2;
+        const double lift = q * cl, drag = q * cd;
+        const double s = a.scale ? a.scale[p] : 1.0;
+        const double cph = cos(phi), sph = sin(phi);
+        fx = s * (lift * cph + drag * sph);
+        ft = s * (lift * sph - drag * cph);
+        // force on the fluid: minus the blade force
+        a.X[3 * p + 0] = X[0];
+        a.X[3 * p + 1] = X[1];
+        a.X[3 * p + 2] = X[2];
+        a.fv[3 * p + 0] = -fx;
+        a.fv[3 * p + 1] = -ft * et[1];
+        a.fv[3 * p + 2] = -ft * et[2];
+        a.out_alpha[p] = alpha;
+        a.out_fx[p] = fx;
+        a.out_ft[p] = ft;
+        a.out_urel[p] = sqrt(urel2);
+        a.out_phi[p] = phi;
+        a.out_u[3 * p + 0] = U[0];
+        a.out_u[3 * p + 1] = U[1];
+        a.out_u[3 * p + 2] = U[2];
+    }
+    red_t[p] = fx;
+    red_q[p] = rr * ft;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if (p < w) {
+            red_t[p] += red_t[p + w];
+            red_q[p] += red_q[p + w];
+        }
+        __syncthreads();
+    }
+    if (p == 0) {
+        const double T = red_t[0], Q = red_q[0];
+        a.st->thrust = T;
+        a.st->torque = Q;
+        a.st->power = a.omega * Q;
+        a.st->cp = a.omega * Q / (0.5 * a.rho_ref * a.area * a.u_inf * a.u_inf * a.u_inf);
+        a.st->ct = T / (0.5 * a.rho_ref * a.area * a.u_inf * a.u_inf);
+    }
+}
+
+// Gaussian projection of the point forces onto the cells of the rotor box; m += dt f (gather form)
+template <typename real>
+__global__ void __launch_bounds__(256) alm_spread_kernel(Field4<real> f, AlmArgs a) {
+    extern __shared__ double sh[];
+    double* sx = sh;                 // 3 n
+    double* sf = sh + 3 * a.n_act;   // 3 n
+    for (int i = threadIdx.x; i < 3 * a.n_act; i += blockDim.x) {
+        sx[i] = a.X[i];
+        sf[i] = a.fv[i];
+    }
+    __syncthreads();
+    const long long nb = (long long)a.box_n[0] * a.box_n[1] * a.box_n[2];
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    const int i = a.box_lo[0] + (int)(c % a.box_n[0]);
+    const long long r = c / a.box_n[0];
+    const int j = a.box_lo[1] + (int)(r % a.box_n[1]);
+    const int k = a.box_lo[2] + (int)(r / a.box_n[1]);
+    const double xc = a.g.x0[0] + (i + 0.5) * a.g.h[0];
+    const double yc = a.g.x0[1] + (j + 0.5) * a.g.h[1];
+    const double zc = a.g.x0[2] + (k + 0.5) * a.g.h[2];
+    const double ie2 = 1.0 / (a.eps * a.eps);
+    const double cut = 9.0 * a.eps * a.eps;
+    const double norm = 1.0 / (a.eps * a.eps * a.eps * M_PI * sqrt(M_PI));
+    double acc[3] = {0.0, 0.0, 0.0};
+    bool any = false;
+    for (int p = 0; p < a.n_act; ++p) {
+        const double dx = xc - sx[3 * p], dy = yc - sx[3 * p + 1], dz = zc - sx[3 * p + 2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 <= cut) {
+            const double gw = norm * exp(-r2 * ie2);
+            acc[0] += sf[3 * p] * gw;
+            acc[1] += sf[3 * p + 1] * gw;
+            acc[2] += sf[3 * p + 2] * gw;
+            any = true;
+        }
+    }
+    if (!any) return;
+    const double dt = a.st->dt;
+    const long long q = pidx(a.g, i, j, k);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f.v[1 + d][q] = (real)((double)f.v[1 + d][q] + dt * acc[d]);
+}
+
+template <typename real>
+hipError_t launch_alm(Field4<real> f, const AlmArgs& a, hipStream_t s) {
+    int bs = 64;
+    while (bs < a.n_act) bs <<= 1;
+    hipLaunchKernelGGL((alm_points_kernel<real>), dim3(1), dim3(bs), 0, s, f, a);
+    const long long nb = (long long)a.box_n[0] * a.box_n[1] * a.box_n[2];
+    const size_t shm = sizeof(double) * 6 * (size_t)a.n_act;
+    hipLaunchKernelGGL((alm_spread_kernel<real>), dim3((unsigned)((nb + 255) / 256)), dim3(256), shm, s, f, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// IBM
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double ibm_weight(const GridDesc& g, const double* X, int i, int j, int k) {
+    const double rx = (g.x0[0] + (i + 0.5) * g.h[0] - X[0]) / g.h[0];
+    const double ry = (g.x0[1] + (j + 0.5) * g.h[1] - X[1]) / g.h[1];
+    const double rz = (g.x0[2] + (k + 0.5) * g.h[2] - X[2]) / g.h[2];
+    return phi4d(rx) * phi4d(ry) * phi4d(rz);
+}
+
+// static V-bar_c = sum over the points whose support holds c of W V_p (fixed point order)
+__global__ void __launch_bounds__(256) ibm_vbar_kernel(IbmArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    const int i = a.cell[3 * c], j = a.cell[3 * c + 1], k = a.cell[3 * c + 2];
+    double v = 0.0;
+    for (int e = a.csr[c]; e < a.csr[c + 1]; ++e) {
+        const int p = a.ent[e];
+        v += ibm_weight(a.g, a.xyz + 3 * p, i, j, k) * a.g.h[0] * a.dS[p];
+    }
+    a.vbar[c] = v;
+}
+
+// per cell: S direct-forcing iterations (stationary points, v-bar = 0); FP64 block partials of sum F
+template <typename real>
+__global__ void __launch_bounds__(256) ibm_cells_kernel(Field4<real> f, IbmArgs a) {
+    __shared__ double red[3][256];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double F[3] = {0.0, 0.0, 0.0};
+    if (c < a.ncell) {
+        const int i = a.cell[3 * c], j = a.cell[3 * c + 1], k = a.cell[3 * c + 2];
+        const long long q = pidx(a.g, i, j, k);
+        const double dt = a.st->dt;
+        const double rho = a.rho_ref + (double)f.v[0][q];
+        const double vb = a.vbar[c];
+        const double vol = a.g.h[0] * a.g.h[1] * a.g.h[2];
+        double m[3] = {(double)f.v[1][q], (double)f.v[2][q], (double)f.v[3][q]};
+        for (int s = 0; s < a.iters; ++s) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double U = m[d] / rho;
+                const double Fs = rho * vb * (0.0 - U) / dt;
+                m[d] = m[d] + dt * Fs / vol;
+                F[d] += Fs;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) f.v[1 + d][q] = (real)m[d];
+    }
+    for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = F[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) a.partials[3 * blockIdx.x + d] = red[d][0];
+}
+
+__global__ void __launch_bounds__(256) ibm_final_kernel(IbmArgs a, int nblk) {
+    __shared__ double red[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int d = 0; d < 3; ++d) s[d] += a.partials[3 * b + d];
+    for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = s[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) a.st->ibm_force[d] = -red[d][0];  // load on the body
+        a.st->ibm_iters_used = a.iters;
+    }
+}
+
+// residual: max_p |v_p - sum_c W_{c->p} U_c| after the last iteration (max: order independent)
+template <typename real>
+__global__ void __launch_bounds__(256) ibm_resid_kernel(Field4<real> f, IbmArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npts) return;
+    const double* X = a.xyz + 3 * p;
+    int i0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) i0[d] = (int)floor((X[d] - a.g.x0[d]) / a.g.h[d] - 0.5);
+    double U[3] = {0.0, 0.0, 0.0};
+    for (int dk = -1; dk <= 2; ++dk)
+        for (int dj = -1; dj <= 2; ++dj)
+            for (int di = -1; di <= 2; ++di) {
+                const int i = i0[0] + di, j = i0[1] + dj, k = i0[2] + dk;
+                const double w = ibm_weight(a.g, X, i, j, k);
+                const long long q = pidx(a.g, i, j, k);
+                const double rho = a.rho_ref + (double)f.v[0][q];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) U[d] += w * ((double)f.v[1 + d][q] / rho);
+            }
+    const double r = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+    atomicMax(&a.st->ibm_res_bits, (unsigned long long)__double_as_longlong(r));
+}
+
+hipError_t launch_ibm_vbar(const IbmArgs& a, hipStream_t s) {
+    if (a.ncell <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ibm_vbar_kernel, dim3((a.ncell + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int ibm_blocks(int ncell) { return (ncell + 255) / 256; }
+
+template <typename real>
+hipError_t launch_ibm(Field4<real> f, const IbmArgs& a, hipStream_t s) {
+    if (a.ncell <= 0) return hipSuccess;
+    const int nblk = ibm_blocks(a.ncell);
+    hipLaunchKernelGGL((ibm_cells_kernel<real>), dim3(nblk), dim3(256), 0, s, f, a);
+    hipLaunchKernelGGL(ibm_final_kernel, dim3(1), dim3(256), 0, s, a, nblk);
+    hipLaunchKernelGGL((ibm_resid_kernel<real>), dim3((a.npts + 255) / 256), dim3(256), 0, s, f, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_alm<float>(Field4<float>, const AlmArgs&, hipStream_t);
+template hipError_t launch_alm<double>(Field4<double>, const AlmArgs&, hipStream_t);
+template hipError_t launch_ibm<float>(Field4<float>, const IbmArgs&, hipStream_t);
+template hipError_t launch_ibm<double>(Field4<double>, const IbmArgs&, hipStream_t);
+
+}  // namespace gks

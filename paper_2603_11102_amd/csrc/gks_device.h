@@ -1,0 +1,206 @@
+// gks_device.h -- device math of the high-order isothermal GKS step (gfx950).
+//
+// Reconstruction (Section 2: fifth-order WENO-JS, dimension by dimension, to the 2x2 Gauss points of
+// each face) and the gas-kinetic flux of the interface distribution f = g0 (1 - tau (a.u + A) + A t)
+// (Section 2, Eq. (flux); coefficients from the moment system of the Appendix).
+//
+// Cells have unit width in the stencil formulas; derivatives are scaled by 1/h by the caller.
+// Gauss points of a cell are xi = s sqrt(3)/6, s = -1 (m = 0) and s = +1 (m = 1).
+//
+// Flux: for the isothermal Maxwellian g0 with macroscopic state Q0 and spatial derivatives dQ0/dx_k,
+// the moments of f reduce exactly (the Chapman-Enskog identities of the BGK model) to
+//   F0 = E_n(Q0) - mu (dU/dx_n + grad U_n)            (no viscous mass flux, no bulk term),
+//   F1 = J_n(Q0) Qdot,  Qdot = -sum_k J_k(Q0) dQ0/dx_k  (rho0 <u_n A psi> with A from compatibility),
+// where E_k is the isothermal Euler flux and J_k its Jacobian; tau p0 = mu. The constant reference
+// pressure c^2 rho_ref is dropped from E_n: it is the same at every face and cancels in the divergence,
+// which keeps the O(Ma^2) pressure differences in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace gks {
+
+template <typename real> struct Rc;
+template <> struct Rc<float> {
+    static __device__ __forceinline__ float erf_(float x) { return erff(x); }
+    static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+};
+template <> struct Rc<double> {
+    static __device__ __forceinline__ double erf_(double x) { return erf(x); }
+    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+    static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+};
+
+#define GKS_SQRT3 1.7320508075688772935274463415059
+
+// ---------------------------------------------------------------------------------------------
+// WENO-JS smoothness indicators of the three quadratic sub-stencils of five cells q[-2..2]
+// ---------------------------------------------------------------------------------------------
+template <typename real>
+__device__ __forceinline__ void js_weights(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
+                                           real& w0, real& w1, real& w2) {
+    const real c13 = real(13.0 / 12.0);
+    real a = qm2 - real(2) * qm1 + q0, b = qm2 - real(4) * qm1 + real(3) * q0;
+    real b0 = c13 * a * a + real(0.25) * b * b;
+    a = qm1 - real(2) * q0 + qp1;
+    b = qm1 - qp1;
+    real b1 = c13 * a * a + real(0.25) * b * b;
+    a = q0 - real(2) * qp1 + qp2;
+    b = real(3) * q0 - real(4) * qp1 + qp2;
+    real b2 = c13 * a * a + real(0.25) * b * b;
+    real e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+    w0 = real(1) / (e0 * e0);
+    w1 = real(1) / (e1 * e1);
+    w2 = real(1) / (e2 * e2);
+}
+
+// Face values of cell 0: right face (xi = +1/2, linear weights 1/10, 3/5, 3/10) and left face
+// (xi = -1/2, weights 3/10, 3/5, 1/10). Both share the cell's smoothness indicators.
+template <typename real>
+__device__ __forceinline__ void weno_faces(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
+                                           real& right, real& left) {
+    real w0, w1, w2;
+    js_weights(qm2, qm1, q0, qp1, qp2, eps, w0, w1, w2);
+    const real s6 = real(1.0 / 6.0);
+    real r0 = s6 * (real(2) * qm2 - real(7) * qm1 + real(11) * q0);
+    real r1 = s6 * (-qm1 + real(5) * q0 + real(2) * qp1);
+    real r2 = s6 * (real(2) * q0 + real(5) * qp1 - qp2);
+    real a0 = real(0.1) * w0, a1 = real(0.6) * w1, a2 = real(0.3) * w2;
+    right = (a0 * r0 + a1 * r1 + a2 * r2) / (a0 + a1 + a2);
+    real l0 = s6 * (-qm2 + real(5) * qm1 + real(2) * q0);
+    real l1 = s6 * (real(2) * qm1 + real(5) * q0 - qp1);
+    real l2 = s6 * (real(11) * q0 - real(7) * qp1 + real(2) * qp2);
+    a0 = real(0.3) * w0;
+    a2 = real(0.1) * w2;
+    left = (a0 * l0 + a1 * l1 + a2 * l2) / (a0 + a1 + a2);
+}
+
+// WENO-JS values at the two Gauss points of cell 0. Each sub-stencil quadratic is q0 + s d_k at
+// xi = s sqrt3/6 (the two-point Gauss rule integrates it exactly, so its even part is q0); the linear
+// weights reproducing the quartic are (7/36 - s sqrt3/1080, 11/18, 7/36 + s sqrt3/1080).
+template <typename real>
+__device__ __forceinline__ void weno_gauss(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
+                                           real& vm, real& vp) {
+    real w0, w1, w2;
+    js_weights(qm2, qm1, q0, qp1, qp2, eps, w0, w1, w2);
+    const real r3 = real(GKS_SQRT3);
+    real d0 = r3 * (real(1.0 / 12.0) * qm2 - real(1.0 / 3.0) * qm1 + real(0.25) * q0);
+    real d1 = r3 * real(1.0 / 12.0) * (qp1 - qm1);
+    real d2 = r3 * (-real(0.25) * q0 + real(1.0 / 3.0) * qp1 - real(1.0 / 12.0) * qp2);
+    const real gc = real(7.0 / 36.0), gd = real(GKS_SQRT3 / 1080.0), g1 = real(11.0 / 18.0);
+    // s = +1
+    real a0 = (gc - gd) * w0, a1 = g1 * w1, a2 = (gc + gd) * w2;
+    vp = q0 + (a0 * d0 + a1 * d1 + a2 * d2) / (a0 + a1 + a2);
+    // s = -1
+    a0 = (gc + gd) * w0;
+    a2 = (gc - gd) * w2;
+    vm = q0 - (a0 * d0 + a1 * d1 + a2 * d2) / (a0 + a1 + a2);
+}
+
+// Quartic through five cell averages: values at the two Gauss points.
+// value = e.q + s sqrt3 o.q, e = (-1/4320, 1/1080, 719/720, 1/1080, -1/4320),
+// o = (7/432, -25/216, 0, 25/216, -7/432).
+template <typename real>
+__device__ __forceinline__ void quartic_gauss_value(real qm2, real qm1, real q0, real qp1, real qp2,
+                                                    real& vm, real& vp) {
+    real ev = real(-1.0 / 4320.0) * (qm2 + qp2) + real(1.0 / 1080.0) * (qm1 + qp1) + real(719.0 / 720.0) * q0;
+    real od = real(GKS_SQRT3) * (real(7.0 / 432.0) * (qm2 - qp2) + real(25.0 / 216.0) * (qp1 - qm1));
+    vm = ev - od;
+    vp = ev + od;
+}
+
+// Quartic through five cell averages: derivatives (per unit cell) at the two Gauss points.
+// e = (1/12, -2/3, 0, 2/3, -1/12), o = (-1/54, 13/54, -4/9, 13/54, -1/54).
+template <typename real>
+__device__ __forceinline__ void quartic_gauss_deriv(real qm2, real qm1, real q0, real qp1, real qp2,
+                                                    real& dm, real& dp) {
+    real ev = real(1.0 / 12.0) * (qm2 - qp2) + real(2.0 / 3.0) * (qp1 - qm1);
+    real od = real(GKS_SQRT3) * (real(-1.0 / 54.0) * (qm2 + qp2) + real(13.0 / 54.0) * (qm1 + qp1) -
+                                 real(4.0 / 9.0) * q0);
+    dm = ev - od;
+    dp = ev + od;
+}
+
+// erf(a) - erf(b) without cancellation when a ~ b in FP32: three-point Gauss-Legendre quadrature of
+// (2/sqrt(pi)) exp(-t^2) over [b, a] (relative error < 2e-8 for |a - b| < 1/4).
+template <typename real>
+__device__ __forceinline__ real erf_diff(real a, real b) {
+    return Rc<real>::erf_(a) - Rc<real>::erf_(b);
+}
+template <>
+__device__ __forceinline__ float erf_diff<float>(float a, float b) {
+    float h = 0.5f * (a - b);
+    if (fabsf(h) < 0.125f) {
+        float m = 0.5f * (a + b);
+        const float x1 = 0.77459666924148338f;  // sqrt(3/5)
+        float t0 = m - h * x1, t2 = m + h * x1;
+        float s = (5.0f / 9.0f) * (expf(-t0 * t0) + expf(-t2 * t2)) + (8.0f / 9.0f) * expf(-m * m);
+        return 1.1283791670955126f * h * s;  // 2/sqrt(pi)
+    }
+    return erff(a) - erff(b);
+}
+
+template <typename real>
+struct FluxConst {
+    real lam;      // lambda = Ma^2 / (2 U_ref^2)
+    real sl;       // sqrt(lambda)
+    real kk;       // 1 / (2 sqrt(pi lambda))
+    real c2;       // 1 / (2 lambda)
+    real mu;       // viscosity
+    real rho_ref;  // reference density
+};
+
+// Gas-kinetic flux at one Gauss point, in the face's local frame: variables (rho', m_n, m_t1, m_t2),
+// derivative directions (n, t1, t2). qL, qR: reconstructed left/right states; g[d][v]: dQ_v/dx_d.
+// Adds w * F0 (if NEED_F0) and w * F1 to f0, f1.
+template <typename real, bool NEED_F0>
+__device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], const real g[3][4],
+                                        const FluxConst<real>& k, real w, real f0[4], real f1[4]) {
+    // kinetic (half-space) average of the left and right Maxwellians, in deviation form
+    real rL = k.rho_ref + qL[0], rR = k.rho_ref + qR[0];
+    real uL = qL[1] / rL, uR = qR[1] / rR;
+    real aL = k.sl * uL, aR = k.sl * uR;
+    real eaL = Rc<real>::erf_(aL), eaR = Rc<real>::erf_(aR);
+    real hL = real(0.5) * (real(1) + eaL);
+    real hR = real(0.5) * (real(1) - eaR);
+    real eR = Rc<real>::exp_(-k.lam * uR * uR);
+    real eL = Rc<real>::exp_(-k.lam * uL * uL);
+    real dE = eR * Rc<real>::expm1_(k.lam * (uR - uL) * (uR + uL));  // eL - eR
+    real rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * real(0.5) * erf_diff<real>(aL, aR);
+    real m0[3];
+    m0[0] = qL[1] * hL + qR[1] * hR + k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
+    m0[1] = qL[2] * hL + qR[2] * hR;
+    m0[2] = qL[3] * hL + qR[3] * hR;
+    real r0 = k.rho_ref + rho0p;
+    real ir = real(1) / r0;
+    real U[3] = {m0[0] * ir, m0[1] * ir, m0[2] * ir};
+    // velocity gradients dU[d][j] = (dm_j/dx_d - U_j drho/dx_d) / rho0
+    real dU[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dU[d][j] = (g[d][1 + j] - U[j] * g[d][0]) * ir;
+    if (NEED_F0) {
+        f0[0] += w * m0[0];
+        f0[1] += w * (m0[0] * U[0] + k.c2 * rho0p - k.mu * real(2) * dU[0][0]);
+        f0[2] += w * (m0[0] * U[1] - k.mu * (dU[0][1] + dU[1][0]));
+        f0[3] += w * (m0[0] * U[2] - k.mu * (dU[0][2] + dU[2][0]));
+    }
+    // Euler time derivative of Q0
+    real divm = g[0][1] + g[1][2] + g[2][3];
+    real qd0 = -divm;
+    real qd[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        real adv = U[0] * dU[0][j] + U[1] * dU[1][j] + U[2] * dU[2][j];
+        qd[j] = -U[j] * divm - r0 * adv - k.c2 * g[j][0];
+    }
+    f1[0] += w * qd[0];
+    f1[1] += w * (real(2) * U[0] * qd[0] - U[0] * U[0] * qd0 + k.c2 * qd0);
+    f1[2] += w * (U[1] * qd[0] + U[0] * qd[1] - U[0] * U[1] * qd0);
+    f1[3] += w * (U[2] * qd[0] + U[0] * qd[2] - U[0] * U[2] * qd0);
+}
+
+}  // namespace gks

@@ -1,0 +1,91 @@
+// gks_internal.h -- structures shared by the host library and the kernels (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gks_device.h"
+
+namespace gks {
+
+constexpr int NG = 3;                    // ghost layers per side
+constexpr int TILE1 = 16, TILE2 = 16;    // tangential faces per workgroup (t1 x t2)
+constexpr int EXT1 = TILE1 + 4, EXT2 = TILE2 + 4;
+constexpr int FACE_THREADS = 512;        // 8 wave64 per workgroup
+
+// Arguments of the per-direction face kernel. Arrays are in the face's LOCAL variable order
+// (rho', m_normal, m_t1, m_t2); the caller permutes the global pointers.
+template <typename real>
+struct FaceArgs {
+    const real* q[4];        // reconstructed field (padded layout)
+    real* r0[4];             // accumulator of L (interior layout), stage 1
+    real* r1[4];             // accumulator of L_t (interior layout)
+    real* out_a[4];          // epilogue: stage 1 -> Q*, stage 2 -> Q^{n+1} (padded)
+    real* out_b[4];          // epilogue: stage 1 -> S (padded)
+    const real* s_in[4];     // epilogue: stage 2 reads S (padded)
+    const real* q_c[4];      // epilogue: stage 1 reads Q^n at the cell (padded)
+    int n_n, n_t1, n_t2;     // interior cells along normal, t1, t2
+    int chunk, tiles_t1, tiles_t2;
+    long long st_n, st_t1, st_t2;     // padded strides
+    long long ist_n, ist_t1, ist_t2;  // interior strides
+    long long pad0;                   // padded offset of interior cell (0,0,0)
+    real inv_hn, inv_h1, inv_h2;
+    real eps;
+    FluxConst<real> fc;
+    real g_local[3];                  // constant body force in local momentum order (stage 2 epilogue)
+    const double* dt_ptr;             // device dt of the current step
+    int mode;                         // 0: write, 1: accumulate, 2: accumulate + S2O4 epilogue
+};
+
+// Device-resident scalars of a context (lives in the workspace).
+struct DevState {
+    double t, dt, t_next;
+    unsigned long long umax2_bits;   // max |U|^2 over Q^n of the current step (bits of a double >= 0)
+    long long step;
+    double thrust, torque, power, cp, ct;
+    double ibm_force[3];
+    unsigned long long ibm_res_bits;
+    double win_p, win_t;
+    long long win_n;
+    double mass, mom[3];
+    unsigned long long umax_diag_bits;
+    int nonfinite;
+    int ibm_iters_used;
+};
+
+struct GridDesc {
+    int n[3];                 // interior cells x, y, z
+    long long st[3];          // padded strides x, y, z
+    long long pad0;           // padded offset of interior cell (0,0,0)
+    long long n_padded;       // elements per padded field
+    double h[3];
+    double x0[3];
+};
+
+template <typename real>
+struct Field4 {
+    real* v[4];
+};
+
+// host launchers (gks_stage.hip)
+template <typename real>
+hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s);
+template <typename real>
+int face_chunk(int n_n, int tiles);
+
+// host launchers (gks_aux.hip)
+template <typename real>
+hipError_t launch_ghost(Field4<real> f, const GridDesc& g, int axis, int bc_lo, int bc_hi, const double u_in[3],
+                        double c, double rho_ref, hipStream_t s);
+template <typename real>
+hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, unsigned long long* out_bits, hipStream_t s);
+hipError_t launch_dt(DevState* st, double cfl, double hmin, double c, double dt_fixed, hipStream_t s);
+hipError_t launch_finish(DevState* st, int has_rotor, hipStream_t s);
+hipError_t launch_window_reset(DevState* st, hipStream_t s);
+template <typename real>
+hipError_t launch_diag(Field4<real> f, const GridDesc& g, double rho_ref, double* partials, int nblk, DevState* st,
+                       hipStream_t s);
+int diag_blocks(const GridDesc& g);
+hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace gks

@@ -1,0 +1,256 @@
+// gks_stage.hip -- the S2O4 stage kernels: reconstruction, gas-kinetic flux, flux divergence and the
+// stage combination, one launch per face direction (Section 2, Eqs. (semi), (finite), (x_example),
+// (flux); the two-stage fourth-order combinations).
+//
+// One workgroup (512 threads = 8 wave64) owns a 16 x 16 tile of faces in the tangential plane and
+// marches along the face normal through a chunk of faces:
+//   * column phase: each of the 20 x 20 tangential columns (tile + 2-cell halo per side) keeps a
+//     5-cell window of the field in registers; per cell it evaluates the WENO-JS values at both of its
+//     faces with one set of smoothness indicators, the normal derivative D (cubic through four cells)
+//     and C = (q^L + q^R)/2 -> LDS;
+//   * t1 phase: WENO-JS at the two Gauss points of q^L, q^R, quartic Gauss values of D and C and the
+//     quartic Gauss derivative of C along t1 -> LDS;
+//   * t2 phase: the same along t2 for each Gauss line, giving per Gauss point q^L, q^R, dQ/dn, dQ/dt1,
+//     dQ/dt2 in registers (one thread per face and Gauss line);
+//   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
+//     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
+// No face flux is written to memory.
+#include "gks_internal.h"
+
+namespace gks {
+
+template <typename real, int STAGE>
+__global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
+    constexpr bool NEED_F0 = (STAGE == 1);
+    __shared__ real s_nrm[4][EXT2][EXT1];        // q^L, q^R, D, C of the current variable
+    __shared__ real s_t1[5][EXT2][TILE1][2];     // q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m
+
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    const int tile1 = b % a.tiles_t1;
+    b /= a.tiles_t1;
+    const int tile2 = b % a.tiles_t2;
+    b /= a.tiles_t2;
+    const int f0 = b * a.chunk;
+    const int f1 = min(f0 + a.chunk, a.n_n);  // residuals of cells [f0, f1); faces f0..f1
+    const int j0 = tile1 * TILE1, k0 = tile2 * TILE2;
+    const real eps = a.eps;
+
+    // column role
+    const bool col = tid < EXT1 * EXT2;
+    const int c1 = tid % EXT1, c2 = tid / EXT1;
+    const int jc = j0 - 2 + c1, kc = k0 - 2 + c2;
+    const bool col_ld = col && (jc < a.n_t1 + NG) && (kc < a.n_t2 + NG);
+    const long long cbase = a.pad0 + (long long)jc * a.st_t1 + (long long)kc * a.st_t2;
+    // t1 role
+    const bool t1r = tid < TILE1 * EXT2;
+    const int tj = tid % TILE1, tk = tid / TILE1;
+    // face role: face (fj, fk) of the tile, Gauss line m (partner lane tid ^ 1 holds the other line)
+    const int m = tid & 1;
+    const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
+    const bool face_ok = (j0 + fj < a.n_t1) && (k0 + fk < a.n_t2);
+
+    real ring[4][5];
+    real carry[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        carry[v] = real(0);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) ring[v][r] = real(0);
+    }
+    // warm-up: window of cells f0-3 .. f0+1, then the right-face value of cell f0-1 (q^L of face f0)
+    if (col_ld) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const long long idx = cbase + (long long)(f0 - 3 + r) * a.st_n;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ring[v][r] = a.q[v][idx];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            real right, left;
+            weno_faces<real>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left);
+            carry[v] = right;
+        }
+    }
+
+    const real dt = real(*a.dt_ptr);
+    real fprev0[4], fprev1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        fprev0[v] = real(0);
+        fprev1[v] = real(0);
+    }
+
+    for (int f = f0; f <= f1; ++f) {
+        // column phase setup: window cells f-2 .. f+2
+        if (col_ld) {
+            const long long idx = cbase + (long long)(f + 2) * a.st_n;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
+                ring[v][4] = a.q[v][idx];
+            }
+        }
+        real gp[4][2][5];  // [variable][Gauss n][q^L, q^R, d/dn, d/dt1, d/dt2]
+
+        auto column = [&](int v) {
+            if (col) {
+                real right, left;
+                weno_faces<real>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left);
+                const real qL = carry[v];
+                const real D = (ring[v][0] - real(15) * ring[v][1] + real(15) * ring[v][2] - ring[v][3]) *
+                               (real(1.0 / 12.0) * a.inv_hn);
+                s_nrm[0][c2][c1] = qL;
+                s_nrm[1][c2][c1] = left;
+                s_nrm[2][c2][c1] = D;
+                s_nrm[3][c2][c1] = real(0.5) * (qL + left);
+                carry[v] = right;
+            }
+        };
+
+        column(0);
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (t1r) {
+                real x[4][5];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[q][tk][tj + r];
+                real vm, vp;
+                weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
+                s_t1[0][tk][tj][0] = vm;
+                s_t1[0][tk][tj][1] = vp;
+                weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
+                s_t1[1][tk][tj][0] = vm;
+                s_t1[1][tk][tj][1] = vp;
+                quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
+                s_t1[2][tk][tj][0] = vm;
+                s_t1[2][tk][tj][1] = vp;
+                quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+                s_t1[3][tk][tj][0] = vm * a.inv_h1;
+                s_t1[3][tk][tj][1] = vp * a.inv_h1;
+                quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+                s_t1[4][tk][tj][0] = vm;
+                s_t1[4][tk][tj][1] = vp;
+            }
+            __syncthreads();
+            {
+                real y[5][5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+#pragma unroll
+                    for (int r = 0; r < 5; ++r) y[q][r] = s_t1[q][fk + r][fj][m];
+                real vm, vp;
+                weno_gauss<real>(y[0][0], y[0][1], y[0][2], y[0][3], y[0][4], eps, vm, vp);
+                gp[v][0][0] = vm;
+                gp[v][1][0] = vp;
+                weno_gauss<real>(y[1][0], y[1][1], y[1][2], y[1][3], y[1][4], eps, vm, vp);
+                gp[v][0][1] = vm;
+                gp[v][1][1] = vp;
+                quartic_gauss_value<real>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
+                gp[v][0][2] = vm;
+                gp[v][1][2] = vp;
+                quartic_gauss_value<real>(y[3][0], y[3][1], y[3][2], y[3][3], y[3][4], vm, vp);
+                gp[v][0][3] = vm;
+                gp[v][1][3] = vp;
+                quartic_gauss_deriv<real>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
+                gp[v][0][4] = vm * a.inv_h2;
+                gp[v][1][4] = vp * a.inv_h2;
+            }
+            if (v < 3) column(v + 1);
+            __syncthreads();
+        }
+
+        // flux at this thread's two Gauss points, quadrature weight 1/4 each
+        real fa0[4] = {0, 0, 0, 0}, fa1[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            real qL[4], qR[4], g[3][4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                qL[v] = gp[v][n][0];
+                qR[v] = gp[v][n][1];
+                g[0][v] = gp[v][n][2];
+                g[1][v] = gp[v][n][3];
+                g[2][v] = gp[v][n][4];
+            }
+            gp_flux<real, NEED_F0>(qL, qR, g, a.fc, real(0.25), fa0, fa1);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            fa1[v] += __shfl_xor(fa1[v], 1);
+            if (NEED_F0) fa0[v] += __shfl_xor(fa0[v], 1);
+        }
+        if (f > f0 && face_ok) {
+            const int cell = f - 1;
+            const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
+                                   (long long)(k0 + fk) * a.ist_t2;
+            const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)(j0 + fj) * a.st_t1 +
+                                   (long long)(k0 + fk) * a.st_t2;
+#pragma unroll
+            for (int vv = 0; vv < 2; ++vv) {
+                const int v = 2 * m + vv;  // lane m writes variables 2m, 2m+1
+                real d1 = -(fa1[v] - fprev1[v]) * a.inv_hn;
+                real d0 = NEED_F0 ? -(fa0[v] - fprev0[v]) * a.inv_hn : real(0);
+                if (a.mode == 0) {
+                    a.r1[v][ridx] = d1;
+                    if (NEED_F0) a.r0[v][ridx] = d0;
+                } else if (a.mode == 1) {
+                    a.r1[v][ridx] += d1;
+                    if (NEED_F0) a.r0[v][ridx] += d0;
+                } else {
+                    const real L1 = a.r1[v][ridx] + d1;
+                    if (NEED_F0) {
+                        const real L0 = a.r0[v][ridx] + d0;
+                        const real Q = a.q_c[v][pidx];
+                        a.out_a[v][pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
+                        a.out_b[v][pidx] = Q + dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1;
+                    } else {
+                        real add = (dt * dt * real(1.0 / 3.0)) * L1;
+                        if (v > 0) add += dt * a.g_local[v - 1];
+                        a.out_a[v][pidx] = a.s_in[v][pidx] + add;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            fprev1[v] = fa1[v];
+            if (NEED_F0) fprev0[v] = fa0[v];
+        }
+    }
+}
+
+template <typename real>
+int face_chunk(int n_n, int tiles) {
+    // enough workgroups to fill 256 CUs several times over, chunks of at least 8 faces
+    int want = 2048;
+    int nchunks = (want + tiles - 1) / tiles;
+    int chunk = (n_n + nchunks - 1) / nchunks;
+    if (chunk < 8) chunk = 8;
+    if (chunk > n_n) chunk = n_n;
+    return chunk;
+}
+
+template <typename real>
+hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
+    const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
+    const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
+    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (stage == 1)
+        hipLaunchKernelGGL((face_kernel<real, 1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((face_kernel<real, 2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_face<float>(const FaceArgs<float>&, int, hipStream_t);
+template hipError_t launch_face<double>(const FaceArgs<double>&, int, hipStream_t);
+template int face_chunk<float>(int, int);
+template int face_chunk<double>(int, int);
+
+}  // namespace gks

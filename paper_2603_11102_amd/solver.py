@@ -1,0 +1,183 @@
+"""GksSolver: owns the device buffers (torch tensors) and drives the C ABI of libgks.so.
+
+PyTorch supplies device memory and the HIP stream; every computation runs in the library's kernels.
+There is no CPU fallback: without a GPU or without the built library the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+NG = 3
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class GksSolver:
+    """One simulation context.
+
+    Fields are torch tensors of shape [4, nz+6, ny+6, nx+6] (rho - rho_ref, rho U, rho V, rho W) with
+    3 ghost layers, dtype float32 or float64 on ``device``.
+    """
+
+    def __init__(self, cfg, precision: str = "fp32", device: str = "cuda:0", max_act: Optional[int] = None,
+                 max_ibm: Optional[int] = None, q0: Optional[np.ndarray] = None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("GksSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = L.load()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.precision = precision
+        rotor = getattr(cfg, "rotor", None)
+        ibm = getattr(cfg, "ibm", None)
+        if max_act is None:
+            max_act = rotor.n_blades * rotor.n_per_blade if rotor is not None else 0
+        if max_ibm is None:
+            max_ibm = ibm.n if ibm is not None else 0
+        c = L.gks_config()
+        c.nx, c.ny, c.nz = cfg.nx, cfg.ny, cfg.nz
+        c.precision = L.GKS_FP32 if precision == "fp32" else L.GKS_FP64
+        c.x0, c.y0, c.z0 = cfg.x0, cfg.y0, cfg.z0
+        c.lx, c.ly, c.lz = cfg.lx, cfg.ly, cfg.lz
+        c.ma, c.u_ref, c.rho_ref, c.mu = cfg.ma, cfg.u_ref, cfg.rho_ref, cfg.mu
+        c.cfl, c.dt_fixed = cfg.cfl, cfg.dt_fixed
+        for s in range(6):
+            c.bc[s] = L.BC[cfg.bc[s]]
+        for j in range(3):
+            c.u_in[j] = cfg.u_in[j]
+            c.body_force[j] = cfg.body_force[j]
+        c.weno_eps = cfg.weno_eps
+        c.ibm_iters = cfg.ibm_iters
+        c.max_act = max_act
+        c.max_ibm = max_ibm
+        self.c_cfg = c
+        shape = (4, cfg.nz + 2 * NG, cfg.ny + 2 * NG, cfg.nx + 2 * NG)
+        self.q = torch.zeros(shape, dtype=self.dtype, device=self.device)
+        self.q_stage = torch.zeros_like(self.q)
+        self.q_acc = torch.zeros_like(self.q)
+        q0 = cfg.q0 if q0 is None else q0
+        self.set_interior(q0)
+        nbytes = self.lib.gks_workspace_bytes(C.byref(c))
+        if nbytes == 0:
+            raise L.GksError(L.GKS_E_INVALID_ARG, "invalid configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = _ptr(self.workspace)
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        rc = self.lib.gks_init(C.byref(c), self._field(self.q), self._field(self.q_stage), self._field(self.q_acc),
+                               C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                               C.byref(ctx))
+        L.check(self.lib, None, rc)
+        self.ctx = ctx
+        self.n_act = 0
+        self.scale = None
+        self.checkpoints = None
+        if rotor is not None:
+            self.set_rotor(rotor)
+        if ibm is not None:
+            self.set_ibm(ibm)
+
+    # ------------------------------------------------------------------ buffers
+    def _field(self, t: torch.Tensor) -> L.gks_field:
+        f = L.gks_field()
+        f.rho, f.mx, f.my, f.mz = (_ptr(t[v]) for v in range(4))
+        return f
+
+    def set_interior(self, q0):
+        """Load cell averages [4, nz, ny, nx] of (rho, rho U, rho V, rho W) into the field."""
+        q = torch.as_tensor(np.asarray(q0), dtype=torch.float64).clone()
+        q[0] -= self.cfg.rho_ref
+        self.q[:, NG:-NG, NG:-NG, NG:-NG] = q.to(self.dtype).to(self.device)
+
+    def interior(self) -> torch.Tensor:
+        """Interior cell averages [4, nz, ny, nx]: (rho - rho_ref, rho U, rho V, rho W), float64 on the host."""
+        torch.cuda.synchronize(self.device)
+        return self.q[:, NG:-NG, NG:-NG, NG:-NG].to(torch.float64).cpu()
+
+    # ------------------------------------------------------------------ body forces
+    def set_rotor(self, rotor, scale: Optional[torch.Tensor] = None):
+        n_act = rotor.n_blades * rotor.n_per_blade
+        self._rotor_arrays = [np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+                              for a in (rotor.r, rotor.chord, rotor.twist, rotor.width)]
+        if scale is None:
+            scale = torch.as_tensor(rotor.scales(), dtype=torch.float64, device=self.device)
+        self.scale = scale
+        r = L.gks_rotor()
+        r.n_blades, r.n_per_blade = rotor.n_blades, rotor.n_per_blade
+        for j in range(3):
+            r.hub[j] = rotor.hub[j]
+        r.omega, r.theta0, r.radius, r.u_inf = rotor.omega, rotor.theta0, rotor.radius, rotor.u_inf
+        dp = C.POINTER(C.c_double)
+        r.r, r.chord, r.twist, r.width = (a.ctypes.data_as(dp) for a in self._rotor_arrays)
+        r.eps, r.cl_slope, r.alpha_clip = rotor.eps, rotor.cl_slope, rotor.alpha_clip
+        r.cd0, r.cd2 = rotor.cd0, rotor.cd2
+        r.u_inf_correction = 1 if rotor.u_inf_correction else 0
+        r.scale = C.c_void_p(_ptr(self.scale))
+        L.check(self.lib, self.ctx, self.lib.gks_set_actuators(self.ctx, C.byref(r)))
+        self.n_act = n_act
+
+    def set_ibm(self, ibm):
+        xyz = np.ascontiguousarray(np.asarray(ibm.xyz, dtype=np.float64))
+        ds = np.ascontiguousarray(np.asarray(ibm.dS, dtype=np.float64))
+        dp = C.POINTER(C.c_double)
+        L.check(self.lib, self.ctx, self.lib.gks_set_ibm_points(self.ctx, xyz.shape[0], xyz.ctypes.data_as(dp),
+                                                                ds.ctypes.data_as(dp), None))
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, n: int = 1):
+        L.check(self.lib, self.ctx, self.lib.gks_step(self.ctx, int(n)))
+
+    def forces(self, per_point: bool = False, check: bool = True) -> dict:
+        out = L.gks_forces_out()
+        arrs = {}
+        if per_point and self.n_act:
+            for k in ("alpha", "fx", "ftheta", "urel"):
+                arrs[k] = np.zeros(self.n_act)
+                setattr(out, k, arrs[k].ctypes.data_as(C.POINTER(C.c_double)))
+        rc = self.lib.gks_forces(self.ctx, C.byref(out))
+        if check:
+            L.check(self.lib, self.ctx, rc)
+        d = {k: getattr(out, k) for k in ("t", "dt", "step", "thrust", "torque", "power", "cp", "ct",
+                                           "ibm_residual", "ibm_iters_used", "flags", "mass", "umax",
+                                           "window_power", "window_thrust", "window_steps")}
+        d["ibm_force"] = list(out.ibm_force)
+        d["mom"] = list(out.mom)
+        d["status"] = rc
+        d.update(arrs)
+        return d
+
+    def set_timing(self, enable: bool = True):
+        L.check(self.lib, self.ctx, self.lib.gks_set_timing(self.ctx, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        """Accumulated milliseconds and launch-group counts per category since timing was enabled."""
+        n = len(L.TIMERS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        L.check(self.lib, self.ctx, self.lib.gks_read_timing(self.ctx, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(L.TIMERS)}
+
+    def reset_window(self):
+        L.check(self.lib, self.ctx, self.lib.gks_reset_window(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.gks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,141 @@
+"""GPU parity of the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 agrees with the oracle to 1e-12 relative (max norm per variable); FP32 to 1e-5; integer
+results (step counts) exactly; reductions to 1e-12 (FP64) relative. Sizes span several 16 x 16 tiles
+with ragged tails; the 32^3 Taylor-Green case compares against a stored oracle result written by
+tests/golden/make_golden.py."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import oracle_dev, print_case, rel_errors, rel_l2, run_gpu, run_oracle
+from synth import make_case
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(__file__)
+
+
+def test_fp64_tgv32_ten_steps_vs_stored_oracle():
+    cfg = make_case("tgv")
+    print_case("tgv32-fp64", steps=10)
+    g = np.load(os.path.join(HERE, "golden", "tgv32_oracle_10steps.npz"))
+    s, outs = run_gpu(cfg, "fp64", 10)
+    ref = torch.tensor(g["q"])
+    ref[0] -= cfg.rho_ref
+    err = rel_errors(s.interior(), ref)
+    assert max(err) < 1e-12, err
+    assert abs(outs[-1]["t"] - float(g["t"])) < 1e-14
+    assert all(abs(o["dt"] - d) < 1e-15 for o, d in zip(outs, g["dt"]))
+    assert outs[-1]["step"] == 10
+
+
+@pytest.mark.parametrize("case,grid,steps", [
+    ("channel", (21, 18, 35), 2),      # no-slip walls in y, periodic x/z, body force, ragged tiles
+    ("tgv", (17, 33, 20), 2),          # periodic, ragged in every direction
+])
+def test_fp64_small_cases_vs_oracle(case, grid, steps):
+    cfg = make_case(case, grid=grid)
+    print_case(case + "-fp64", grid=grid, steps=steps)
+    s, gouts = run_gpu(cfg, "fp64", steps)
+    o, oouts = run_oracle(cfg, steps)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    for a, b in zip(gouts, oouts):
+        assert abs(a["dt"] - b["dt"]) < 1e-15 * b["dt"] * 10
+
+
+def _perturbed_stream(cfg, seed=9, amp=0.05):
+    rng = np.random.default_rng(seed)
+    q = cfg.q0.copy()
+    q[1:] += amp * rng.uniform(-1, 1, size=q[1:].shape)
+    q[0] += 0.2 * amp * rng.uniform(-1, 1, size=q[0].shape)
+    return q
+
+
+def test_fp64_inflow_outflow_slip_vs_oracle():
+    cfg = make_case("alm", grid=(36, 18, 18)).with_(rotor=None)
+    cfg = cfg.with_(q0=_perturbed_stream(cfg))
+    print_case("inflow-outflow-slip-fp64", grid=(36, 18, 18))
+    s, _ = run_gpu(cfg, "fp64", 2)
+    o, _ = run_oracle(cfg, 2)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+
+
+def test_fp32_vs_oracle():
+    cfg = make_case("tgv", grid=(24, 20, 18))
+    print_case("tgv-fp32", grid=(24, 20, 18))
+    s, _ = run_gpu(cfg, "fp32", 3)
+    o, _ = run_oracle(cfg, 3)
+    ref = oracle_dev(o.Q, cfg.rho_ref)
+    err = rel_l2(s.interior(), ref)
+    assert max(err) < 1e-5, err
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-14), ("fp32", 2e-6)])
+def test_free_stream_preserved(precision, tol):
+    cfg = make_case("alm", grid=(36, 18, 18)).with_(rotor=None)
+    print_case("free-stream", precision=precision)
+    s, _ = run_gpu(cfg, precision, 3)
+    q = s.interior()
+    ref = oracle_dev(torch.tensor(cfg.q0), cfg.rho_ref)
+    assert float((q - ref).abs().max()) < tol
+
+
+def test_periodic_conservation_fp64():
+    cfg = make_case("tgv", grid=(24, 24, 24))
+    print_case("conservation-fp64")
+    from paper_2603_11102_amd import GksSolver
+    s = GksSolver(cfg, precision="fp64")
+    f0 = s.forces()
+    s.step(5)
+    f1 = s.forces()
+    vol = cfg.dx * cfg.dy * cfg.dz
+    scale = cfg.n_cells * vol
+    assert abs(f1["mass"] - f0["mass"]) < 1e-13 * scale
+    for a, b in zip(f0["mom"], f1["mom"]):
+        assert abs(a - b) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bitwise_run_to_run(precision):
+    cfg = make_case("alm", grid=(48, 24, 24))
+    print_case("determinism", precision=precision)
+    a, oa = run_gpu(cfg, precision, 2)
+    b, ob = run_gpu(cfg, precision, 2)
+    assert torch.equal(a.interior(), b.interior())
+    assert oa[-1]["power"] == ob[-1]["power"] and oa[-1]["thrust"] == ob[-1]["thrust"]
+
+
+def test_alm_fp64_vs_oracle():
+    cfg = make_case("alm", grid=(48, 24, 24))
+    cfg = cfg.with_(q0=_perturbed_stream(cfg, seed=3, amp=0.02))
+    print_case("alm-fp64", grid=(48, 24, 24))
+    s, gouts = run_gpu(cfg, "fp64", 2)
+    o, oouts = run_oracle(cfg, 2)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    for a, b in zip(gouts, oouts):
+        alm = b["alm"]
+        assert np.allclose(a["alpha"], alm["alpha"].numpy(), rtol=1e-12, atol=1e-14)
+        assert np.allclose(a["fx"], alm["fx"].numpy(), rtol=1e-11, atol=1e-16)
+        assert np.allclose(a["ftheta"], alm["ftheta"].numpy(), rtol=1e-11, atol=1e-16)
+        for k in ("thrust", "torque", "power", "cp", "ct"):
+            assert abs(a[k] - float(alm[k])) <= 1e-12 * abs(float(alm[k])), k
+
+
+def test_ibm_fp64_vs_oracle():
+    cfg = make_case("alm_ibm", grid=(64, 32, 32))
+    print_case("alm-ibm-fp64", grid=(64, 32, 32), n_ibm=cfg.ibm.n)
+    s, gouts = run_gpu(cfg, "fp64", 1)
+    o, oouts = run_oracle(cfg, 1)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    ib = oouts[0]["ibm"]
+    ref_f = ib["body_force"].numpy()
+    assert np.allclose(gouts[0]["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())
+    assert abs(gouts[0]["ibm_residual"] - float(ib["residual"])) < 1e-12 * max(1.0, float(ib["residual"]))
+    assert gouts[0]["ibm_iters_used"] == cfg.ibm_iters
