@@ -58,7 +58,7 @@ extern "C" {
 #define GKS_WARN_MACH 2       /* Ma > 0.3: outside the weakly compressible regime */
 
 typedef struct gks_config {
-    int32_t nx, ny, nz;          /* interior cells per axis, each >= 1 */
+    int32_t nx, ny, nz;          /* interior cells per axis, each >= 3 */
     int32_t precision;           /* GKS_FP32 or GKS_FP64: storage and arithmetic of the stage kernels */
     double x0, y0, z0;           /* low corner of the domain */
     double lx, ly, lz;           /* domain lengths (uniform spacing lx/nx, ...) */
@@ -169,13 +169,17 @@ int gks_set_checkpoints(gks_ctx* ctx, void* buffer, int32_t capacity);
 /* Bytes of device scratch gks_adjoint needs. */
 size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
 
-/* Reverse-mode gradient of J = w[0] * mean_n P^n + w[1] * mean_n T^n over the checkpointed window of
- * nsteps steps with respect to the per-point force scalings s_p, written to grad_s (DEVICE, n_act
- * doubles). The WENO nonlinear weights are frozen at their forward values (differentiated as
- * constants); everything else is linearised exactly. FP64 contexts with periodic, wall or outflow
- * boundaries and a fixed dt only. adj_ws: device scratch of gks_adjoint_workspace_bytes. */
-int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, void* adj_ws,
-                size_t adj_ws_bytes);
+/* Reverse-mode gradient of J = w[0] * mean_n P^n + w[1] * mean_n T^n over the first nsteps
+ * checkpointed steps of the window with respect to the per-point force scalings s_p, written to grad_s
+ * (DEVICE, n_act doubles, overwritten). If grad_q0 is not NULL it receives dJ/dQ^0 (DEVICE, 4 arrays of
+ * nx*ny*nz doubles back to back, interior cells, x fastest; variable 0 is the density). The WENO
+ * nonlinear weights are frozen at their forward values (differentiated as constants); everything else
+ * (flux, kinetic average, S2O4 combination, ghost cells, actuator-line sampling, forces and projection)
+ * is linearised exactly. Requires an FP64 context with a rotor, no immersed bodies, a fixed dt and
+ * periodic, wall or outflow boundaries. The stage buffers q_stage and q_acc are overwritten; q is not.
+ * adj_ws: device scratch of gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
+int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0,
+                void* adj_ws, size_t adj_ws_bytes);
 
 /* Per-launch timing with HIP events recorded on the context's stream around each launch group.
  * Categories (index into the arrays of gks_read_timing): */

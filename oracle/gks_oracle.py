@@ -60,6 +60,7 @@ __all__ = [
     "linear_point", "constants", "ghost_fill", "kinetic_average", "maxwellian_moment",
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
+    "rotor_objective", "rotor_gradient",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -710,3 +711,29 @@ class Oracle:
         self.n += 1
         self.history.append(out)
         return out
+
+
+# ================================================================================================
+# adjoint reference (gradient of the rotor objective with respect to the per-point force scalings)
+# ================================================================================================
+
+def rotor_objective(cfg, scales, nsteps, w, weno_ctl=None, q0=None):
+    """J = w0 mean_n P^n + w1 mean_n T^n over nsteps steps (P, T from the actuator line model of each
+    step). ``scales`` is a float64 tensor of per-point force scalings s_p (it may require grad)."""
+    o = Oracle(cfg, q0=q0, scales=scales, weno_ctl=weno_ctl)
+    J = 0.0
+    for _ in range(nsteps):
+        out = o.step()
+        J = J + (w[0] * out["alm"]["power"] + w[1] * out["alm"]["thrust"]) / nsteps
+    return J, o
+
+
+def rotor_gradient(cfg, scales, nsteps, w, frozen=True, q0=None):
+    """dJ/ds by reverse-mode differentiation of the oracle forward. frozen=True treats every WENO
+    nonlinear weight as a constant at its forward value (the linearisation the GPU adjoint implements);
+    frozen=False differentiates the weights too."""
+    s = torch.as_tensor(np.asarray(scales, dtype=np.float64)).clone().requires_grad_(True)
+    ctl = WenoControl("detach") if frozen else None
+    J, _ = rotor_objective(cfg, s, nsteps, w, ctl, q0)
+    J.backward()
+    return float(J.detach()), s.grad.detach().clone()

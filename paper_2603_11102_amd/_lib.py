@@ -107,7 +107,7 @@ def load(path: str = LIB_PATH):
     lib.gks_set_checkpoints.restype = C.c_int
     lib.gks_adjoint_workspace_bytes.argtypes = [C.POINTER(gks_config), C.c_int32]
     lib.gks_adjoint_workspace_bytes.restype = C.c_size_t
-    lib.gks_adjoint.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P, P, C.c_size_t]
+    lib.gks_adjoint.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P, P, P, C.c_size_t]
     lib.gks_adjoint.restype = C.c_int
     lib.gks_set_timing.argtypes = [P, C.c_int32]
     lib.gks_set_timing.restype = C.c_int

@@ -1,15 +1,661 @@
-// gks_adjoint.hip -- discrete adjoint of the S2O4 step with the actuator-line body force.
+// gks_adjoint.hip -- discrete adjoint of the S2O4 step (FP64) with the actuator-line body force, for
+// the gradient of a rotor objective with respect to per-point force scalings.
+//
+// Forward operator per face direction (Section 2): normal WENO/derivative reconstruction ->
+// t1 Gauss-point sweep -> t2 Gauss-point sweep -> gas-kinetic flux at the 2x2 Gauss points ->
+// face quadrature and divergence. Its transpose is applied pass by pass in gather form (each output
+// is one thread summing a fixed list of terms), with the WENO nonlinear weights frozen at their
+// forward values; every other operation is linearised exactly. No atomics are used, so gradients are
+// bitwise reproducible.
+#include <algorithm>
+
 #include "gks_adjoint.h"
-#include "gks_internal.h"
 
 namespace gks {
 
+namespace {
+
+__device__ __forceinline__ long long face_ix(const AdjFaceArgs& a, int f, int j, int k) {
+    return ((long long)f * a.n_t2 + k) * a.n_t1 + j;
+}
+__device__ __forceinline__ long long t1_ix(const AdjFaceArgs& a, int f, int j, int kx) {
+    return ((long long)f * (a.n_t2 + 4) + (kx + 2)) * a.n_t1 + j;
+}
+__device__ __forceinline__ long long n_ix(const AdjFaceArgs& a, int f, int jx, int kx) {
+    return ((long long)f * (a.n_t2 + 4) + (kx + 2)) * (a.n_t1 + 4) + (jx + 2);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// pass A: recompute the face pipeline of one direction, store frozen weights and Gauss-point adjoints
+// ------------------------------------------------------------------------------------------------
+template <int STAGE>
+__global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArgs a) {
+    constexpr bool NEED_F0 = (STAGE == 1);
+    __shared__ double s_nrm[4][EXT2][EXT1];
+    __shared__ double s_t1[5][EXT2][TILE1][2];
+
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    const int tile1 = b % a.tiles_t1;
+    b /= a.tiles_t1;
+    const int tile2 = b % a.tiles_t2;
+    b /= a.tiles_t2;
+    const int f0 = b * a.chunk;
+    const int f1 = min(f0 + a.chunk, a.n_n);
+    const int j0 = tile1 * TILE1, k0 = tile2 * TILE2;
+    const double eps = a.eps;
+
+    const bool col = tid < EXT1 * EXT2;
+    const int c1 = tid % EXT1, c2 = tid / EXT1;
+    const int jc = j0 - 2 + c1, kc = k0 - 2 + c2;
+    const bool col_ld = col && (jc < a.n_t1 + NG) && (kc < a.n_t2 + NG);
+    const bool col_st = col && (jc < a.n_t1 + 2) && (kc < a.n_t2 + 2);
+    const long long cbase = a.pad0 + (long long)jc * a.st_t1 + (long long)kc * a.st_t2;
+    const bool t1r = tid < TILE1 * EXT2;
+    const int tj = tid % TILE1, tk = tid / TILE1;
+    const bool t1_st = t1r && (j0 + tj < a.n_t1) && (k0 - 2 + tk < a.n_t2 + 2);
+    const int m = tid & 1;
+    const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
+    const bool face_ok = (j0 + fj < a.n_t1) && (k0 + fk < a.n_t2);
+
+    double ring[4][5];
+    double carry[4];
+    for (int v = 0; v < 4; ++v) {
+        carry[v] = 0.0;
+        for (int r = 0; r < 5; ++r) ring[v][r] = 0.0;
+    }
+    if (col_ld) {
+        for (int r = 0; r < 5; ++r) {
+            const long long idx = cbase + (long long)(f0 - 3 + r) * a.st_n;
+            for (int v = 0; v < 4; ++v) ring[v][r] = a.q[v][idx];
+        }
+        for (int v = 0; v < 4; ++v) {
+            double right, left, wr[3], wl[3];
+            weno_faces_w<double>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left, wr, wl);
+            carry[v] = right;
+            if (col_st) {
+                const long long p = n_ix(a, f0, jc, kc);
+                for (int kk = 0; kk < 3; ++kk) a.w_n[((v * 2 + 0) * 3 + kk) * a.nnpos + p] = wr[kk];
+            }
+        }
+    }
+
+    for (int f = f0; f <= f1; ++f) {
+        if (col_ld) {
+            const long long idx = cbase + (long long)(f + 2) * a.st_n;
+            for (int v = 0; v < 4; ++v) {
+                for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
+                ring[v][4] = a.q[v][idx];
+            }
+        }
+        double gp[4][2][5];
+
+        auto column = [&](int v) {
+            if (col) {
+                double right, left, wr[3], wl[3];
+                weno_faces_w<double>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left,
+                                     wr, wl);
+                const double qL = carry[v];
+                const double D = (ring[v][0] - 15.0 * ring[v][1] + 15.0 * ring[v][2] - ring[v][3]) * (a.inv_hn / 12.0);
+                s_nrm[0][c2][c1] = qL;
+                s_nrm[1][c2][c1] = left;
+                s_nrm[2][c2][c1] = D;
+                s_nrm[3][c2][c1] = 0.5 * (qL + left);
+                carry[v] = right;
+                if (col_st) {
+                    const long long p = n_ix(a, f, jc, kc);
+                    for (int kk = 0; kk < 3; ++kk) a.w_n[((v * 2 + 1) * 3 + kk) * a.nnpos + p] = wl[kk];
+                    if (f + 1 <= f1) {
+                        const long long p1 = n_ix(a, f + 1, jc, kc);
+                        for (int kk = 0; kk < 3; ++kk) a.w_n[((v * 2 + 0) * 3 + kk) * a.nnpos + p1] = wr[kk];
+                    }
+                }
+            }
+        };
+
+        column(0);
+        __syncthreads();
+        for (int v = 0; v < 4; ++v) {
+            if (t1r) {
+                double x[4][5];
+                for (int q = 0; q < 4; ++q)
+                    for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[q][tk][tj + r];
+                double vm, vp, wm[3], wp[3];
+                const long long p = t1_st ? t1_ix(a, f, j0 + tj, k0 - 2 + tk) : 0;
+                for (int side = 0; side < 2; ++side) {
+                    weno_gauss_w<double>(x[side][0], x[side][1], x[side][2], x[side][3], x[side][4], eps, vm, vp, wm, wp);
+                    s_t1[side][tk][tj][0] = vm;
+                    s_t1[side][tk][tj][1] = vp;
+                    if (t1_st)
+                        for (int kk = 0; kk < 3; ++kk) {
+                            a.w_t1[(((v * 2 + side) * 2 + 0) * 3 + kk) * a.nt1pos + p] = wm[kk];
+                            a.w_t1[(((v * 2 + side) * 2 + 1) * 3 + kk) * a.nt1pos + p] = wp[kk];
+                        }
+                }
+                quartic_gauss_value<double>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
+                s_t1[2][tk][tj][0] = vm;
+                s_t1[2][tk][tj][1] = vp;
+                quartic_gauss_deriv<double>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+                s_t1[3][tk][tj][0] = vm * a.inv_h1;
+                s_t1[3][tk][tj][1] = vp * a.inv_h1;
+                quartic_gauss_value<double>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+                s_t1[4][tk][tj][0] = vm;
+                s_t1[4][tk][tj][1] = vp;
+            }
+            __syncthreads();
+            {
+                double y[5][5];
+                for (int q = 0; q < 5; ++q)
+                    for (int r = 0; r < 5; ++r) y[q][r] = s_t1[q][fk + r][fj][m];
+                double vm, vp, wm[3], wp[3];
+                const long long fi = face_ok ? face_ix(a, f, j0 + fj, k0 + fk) : 0;
+                for (int side = 0; side < 2; ++side) {
+                    weno_gauss_w<double>(y[side][0], y[side][1], y[side][2], y[side][3], y[side][4], eps, vm, vp, wm, wp);
+                    gp[v][0][side] = vm;
+                    gp[v][1][side] = vp;
+                    if (face_ok)
+                        for (int kk = 0; kk < 3; ++kk) {
+                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 0) * 3 + kk) * a.nface + fi] = wm[kk];
+                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 1) * 3 + kk) * a.nface + fi] = wp[kk];
+                        }
+                }
+                quartic_gauss_value<double>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
+                gp[v][0][2] = vm;
+                gp[v][1][2] = vp;
+                quartic_gauss_value<double>(y[3][0], y[3][1], y[3][2], y[3][3], y[3][4], vm, vp);
+                gp[v][0][3] = vm;
+                gp[v][1][3] = vp;
+                quartic_gauss_deriv<double>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
+                gp[v][0][4] = vm * a.inv_h2;
+                gp[v][1][4] = vp * a.inv_h2;
+            }
+            if (v < 3) column(v + 1);
+            __syncthreads();
+        }
+
+        if (face_ok) {
+            // seeds of the face flux: L(i) = -(F(i+1/2) - F(i-1/2))/h  =>  Fbar(f) = (mu(f) - mu(f-1))/h
+            const long long jk = (long long)(j0 + fj) * a.ist_t1 + (long long)(k0 + fk) * a.ist_t2;
+            double b0[4], b1[4];
+            for (int v = 0; v < 4; ++v) {
+                const double hi1 = f < a.n_n ? a.mu1[v][(long long)f * a.ist_n + jk] : 0.0;
+                const double lo1 = f >= 1 ? a.mu1[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
+                b1[v] = (hi1 - lo1) * a.inv_hn;
+                if (NEED_F0) {
+                    const double hi0 = f < a.n_n ? a.mu0[v][(long long)f * a.ist_n + jk] : 0.0;
+                    const double lo0 = f >= 1 ? a.mu0[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
+                    b0[v] = (hi0 - lo0) * a.inv_hn;
+                } else {
+                    b0[v] = 0.0;
+                }
+            }
+            const long long fi = face_ix(a, f, j0 + fj, k0 + fk);
+            for (int n = 0; n < 2; ++n) {
+                double qL[4], qR[4], g[3][4], qLb[4] = {0, 0, 0, 0}, qRb[4] = {0, 0, 0, 0};
+                double gb[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+                for (int v = 0; v < 4; ++v) {
+                    qL[v] = gp[v][n][0];
+                    qR[v] = gp[v][n][1];
+                    g[0][v] = gp[v][n][2];
+                    g[1][v] = gp[v][n][3];
+                    g[2][v] = gp[v][n][4];
+                }
+                gp_flux_adj<NEED_F0>(qL, qR, g, a.fc, 0.25, b0, b1, qLb, qRb, gb);
+                for (int v = 0; v < 4; ++v) {
+                    const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
+                    a.gpbar[base] = qLb[v];
+                    a.gpbar[base + a.nface] = qRb[v];
+                    a.gpbar[base + 2 * a.nface] = gb[0][v];
+                    a.gpbar[base + 3 * a.nface] = gb[1][v];
+                    a.gpbar[base + 4 * a.nface] = gb[2][v];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// pass B: transpose of the t2 sweep -> adjoints of the t1 line values (q^L_m, q^R_m, D_m, Ct1_m, C_m)
+// ------------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
+    const long long total = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 2;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int m = (int)(t & 1);
+    long long r_ = t >> 1;
+    const int j = (int)(r_ % a.n_t1);
+    r_ /= a.n_t1;
+    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
+    const int f = (int)(r_ / (a.n_t2 + 4));
+    double bar[4][5];
+    for (int v = 0; v < 4; ++v)
+        for (int q = 0; q < 5; ++q) bar[v][q] = 0.0;
+    for (int k = max(0, kx - 2); k <= min(a.n_t2 - 1, kx + 2); ++k) {
+        const int r = kx - k + 2;
+        const long long fi = face_ix(a, f, j, k);
+        for (int n = 0; n < 2; ++n) {
+            const int side = n == 0 ? 2 : 3;
+            const int s = n == 0 ? -1 : 1;
+            const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h2;
+            for (int v = 0; v < 4; ++v) {
+                const long long gbase = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
+                double wL[3], wR[3];
+                for (int kk = 0; kk < 3; ++kk) {
+                    wL[kk] = a.w_t2[((((v * 2 + m) * 2 + 0) * 2 + n) * 3 + kk) * a.nface + fi];
+                    wR[kk] = a.w_t2[((((v * 2 + m) * 2 + 1) * 2 + n) * 3 + kk) * a.nface + fi];
+                }
+                bar[v][0] += weno_eff(side, wL, r) * a.gpbar[gbase];
+                bar[v][1] += weno_eff(side, wR, r) * a.gpbar[gbase + a.nface];
+                bar[v][2] += cv * a.gpbar[gbase + 2 * a.nface];
+                bar[v][3] += cv * a.gpbar[gbase + 3 * a.nface];
+                bar[v][4] += cd * a.gpbar[gbase + 4 * a.nface];
+            }
+        }
+    }
+    const long long p = t1_ix(a, f, j, kx);
+    for (int v = 0; v < 4; ++v)
+        for (int q = 0; q < 5; ++q) a.t1bar[(long long)((v * 2 + m) * 5 + q) * a.nt1pos + p] = bar[v][q];
+}
+
+// ------------------------------------------------------------------------------------------------
+// pass C: transpose of the t1 sweep and of C = (q^L + q^R)/2 -> adjoints of q^L, q^R, D per face
+// position (tangential halo included)
+// ------------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
+    const long long total = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int jx = (int)(t % (a.n_t1 + 4)) - 2;
+    long long r_ = t / (a.n_t1 + 4);
+    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
+    const int f = (int)(r_ / (a.n_t2 + 4));
+    double bar[4][3], Cb[4];
+    for (int v = 0; v < 4; ++v) {
+        Cb[v] = 0.0;
+        for (int q = 0; q < 3; ++q) bar[v][q] = 0.0;
+    }
+    for (int j = max(0, jx - 2); j <= min(a.n_t1 - 1, jx + 2); ++j) {
+        const int r = jx - j + 2;
+        const long long p = t1_ix(a, f, j, kx);
+        for (int m = 0; m < 2; ++m) {
+            const int side = m == 0 ? 2 : 3;
+            const int s = m == 0 ? -1 : 1;
+            const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h1;
+            for (int v = 0; v < 4; ++v) {
+                const long long tb = (long long)((v * 2 + m) * 5) * a.nt1pos + p;
+                double wL[3], wR[3];
+                for (int kk = 0; kk < 3; ++kk) {
+                    wL[kk] = a.w_t1[(((v * 2 + 0) * 2 + m) * 3 + kk) * a.nt1pos + p];
+                    wR[kk] = a.w_t1[(((v * 2 + 1) * 2 + m) * 3 + kk) * a.nt1pos + p];
+                }
+                bar[v][0] += weno_eff(side, wL, r) * a.t1bar[tb];
+                bar[v][1] += weno_eff(side, wR, r) * a.t1bar[tb + a.nt1pos];
+                bar[v][2] += cv * a.t1bar[tb + 2 * a.nt1pos];
+                Cb[v] += cd * a.t1bar[tb + 3 * a.nt1pos];
+                Cb[v] += cv * a.t1bar[tb + 4 * a.nt1pos];
+            }
+        }
+    }
+    const long long p = n_ix(a, f, jx, kx);
+    for (int v = 0; v < 4; ++v) {
+        a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[v][0] + 0.5 * Cb[v];
+        a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[v][1] + 0.5 * Cb[v];
+        a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[v][2];
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// pass D: transpose of the normal reconstruction -> padded cell adjoint (accumulated)
+// ------------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
+    const long long total = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int jx = (int)(t % (a.n_t1 + 4)) - 2;
+    long long r_ = t / (a.n_t1 + 4);
+    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
+    const int i = (int)(r_ / (a.n_t2 + 4)) - 3;
+    double bar[4] = {0, 0, 0, 0};
+    // q^L(f) = sum_r W^L_f[r] Q(f-3+r)
+    for (int f = max(0, i - 1); f <= min(a.n_n, i + 3); ++f) {
+        const int r = i - f + 3;
+        const long long p = n_ix(a, f, jx, kx);
+        for (int v = 0; v < 4; ++v) {
+            double w[3];
+            for (int kk = 0; kk < 3; ++kk) w[kk] = a.w_n[((v * 2 + 0) * 3 + kk) * a.nnpos + p];
+            bar[v] += weno_eff(0, w, r) * a.fabar[(long long)(v * 3 + 0) * a.nnpos + p];
+        }
+    }
+    // q^R(f) = sum_r W^R_f[r] Q(f-2+r)
+    for (int f = max(0, i - 2); f <= min(a.n_n, i + 2); ++f) {
+        const int r = i - f + 2;
+        const long long p = n_ix(a, f, jx, kx);
+        for (int v = 0; v < 4; ++v) {
+            double w[3];
+            for (int kk = 0; kk < 3; ++kk) w[kk] = a.w_n[((v * 2 + 1) * 3 + kk) * a.nnpos + p];
+            bar[v] += weno_eff(1, w, r) * a.fabar[(long long)(v * 3 + 1) * a.nnpos + p];
+        }
+    }
+    // D(f) = (Q(f-2) - 15 Q(f-1) + 15 Q(f) - Q(f+1)) / (12 h)
+    const double cD[4] = {1.0 / 12.0, -15.0 / 12.0, 15.0 / 12.0, -1.0 / 12.0};
+    for (int f = max(0, i - 1); f <= min(a.n_n, i + 2); ++f) {
+        const int r = i - f + 2;
+        const long long p = n_ix(a, f, jx, kx);
+        for (int v = 0; v < 4; ++v) bar[v] += cD[r] * a.inv_hn * a.fabar[(long long)(v * 3 + 2) * a.nnpos + p];
+    }
+    const long long q = a.pad0 + (long long)i * a.st_n + (long long)jx * a.st_t1 + (long long)kx * a.st_t2;
+    for (int v = 0; v < 4; ++v) a.acc[v][q] += bar[v];
+}
+
+hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) {
+    const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
+    const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
+    if (stage == 1)
+        hipLaunchKernelGGL((adj_face_kernel<1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((adj_face_kernel<2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
+    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 2;
+    hipLaunchKernelGGL(adj_t2_kernel, dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
+    const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    hipLaunchKernelGGL(adj_t1_kernel, dim3((unsigned)((nC + 255) / 256)), dim3(256), 0, s, a);
+    const long long nD = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    hipLaunchKernelGGL(adj_normal_kernel, dim3((unsigned)((nD + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// transpose of the ghost fill: axes in reverse order (z, y, x); each thread folds the six ghost cells
+// of one line in a fixed order
+// ------------------------------------------------------------------------------------------------
+struct FoldArgs {
+    int axis, n, np1, np2;
+    long long st_a, st_1, st_2;
+    int bc_lo, bc_hi;
+};
+
+__global__ void adj_fold_kernel(Field4<double> f, FoldArgs g) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)g.np1 * g.np2) return;
+    const int p1 = (int)(t % g.np1), p2 = (int)(t / g.np1);
+    const long long base = (long long)p1 * g.st_1 + (long long)p2 * g.st_2;
+    for (int side = 0; side < 2; ++side) {
+        const int kind = side == 0 ? g.bc_lo : g.bc_hi;
+        for (int layer = 0; layer < 3; ++layer) {
+            const int gi = side == 0 ? (2 - layer) : (g.n + 3 + layer);
+            int src_i;
+            if (kind == 0) src_i = side == 0 ? (g.n - 1 - layer) : layer;
+            else if (kind == 1 || kind == 2) src_i = side == 0 ? layer : (g.n - 1 - layer);
+            else src_i = side == 0 ? 0 : g.n - 1;
+            const long long dst = base + (long long)gi * g.st_a;
+            const long long src = base + (long long)(src_i + 3) * g.st_a;
+            for (int v = 0; v < 4; ++v) {
+                double sg = 1.0;
+                if (kind == 1 && v > 0) sg = -1.0;
+                if (kind == 2 && v == 1 + g.axis) sg = -1.0;
+                f.v[v][src] += sg * f.v[v][dst];
+                f.v[v][dst] = 0.0;
+            }
+        }
+    }
+}
+
+hipError_t launch_adj_fold(double* fp[4], const GridDesc& gd, const int bc[6], hipStream_t s) {
+    Field4<double> f;
+    for (int v = 0; v < 4; ++v) f.v[v] = fp[v];
+    for (int axis = 2; axis >= 0; --axis) {
+        FoldArgs g;
+        g.axis = axis;
+        g.n = gd.n[axis];
+        const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+        g.np1 = gd.n[a1] + 6;
+        g.np2 = gd.n[a2] + 6;
+        g.st_a = gd.st[axis];
+        g.st_1 = gd.st[a1];
+        g.st_2 = gd.st[a2];
+        g.bc_lo = bc[2 * axis];
+        g.bc_hi = bc[2 * axis + 1];
+        const long long total = (long long)g.np1 * g.np2;
+        hipLaunchKernelGGL(adj_fold_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f, g);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// elementwise helpers
+// ------------------------------------------------------------------------------------------------
+__global__ void axpby_kernel(double* y, const double* x, double a, const double* z, double b, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = a * x[i] + (z ? b * z[i] : 0.0);
+}
+
+hipError_t launch_axpby(double* y, const double* x, double a, const double* z, double b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, a, z, b, n);
+    return hipGetLastError();
+}
+
+__global__ void pad_to_int_kernel(double* dst, const double* src, double a, const double* src2, double b, GridDesc g) {
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int i = (int)(c % g.n[0]);
+    const long long r = c / g.n[0];
+    const int j = (int)(r % g.n[1]);
+    const int k = (int)(r / g.n[1]);
+    const long long p = g.pad0 + i * g.st[0] + j * g.st[1] + (long long)k * g.st[2];
+    dst[c] = a * src[p] + (src2 ? b * src2[p] : 0.0);
+}
+
+hipError_t launch_pad_to_int(double* dst, const double* src, double a, const double* src2, double b,
+                             const GridDesc& g, hipStream_t s) {
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    hipLaunchKernelGGL(pad_to_int_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, a, src2, b, g);
+    return hipGetLastError();
+}
+
+__global__ void zero_kernel(double* y, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = 0.0;
+}
+
+hipError_t launch_zero(double* y, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// actuator-line adjoint
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ long long pidx_g(const GridDesc& g, int i, int j, int k) {
+    return g.pad0 + (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
+}
+
+// per point: fvbar = dt sum_cells G(x - X_p) lambda_m(x) over the projection sphere
+__global__ void alm_adj_gather_kernel(AlmAdjArgs A) {
+    const AlmArgs& a = A.fwd;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_act) return;
+    const double X[3] = {a.X[3 * p], a.X[3 * p + 1], a.X[3 * p + 2]};
+    const double cut = 9.0 * a.eps * a.eps, ie2 = 1.0 / (a.eps * a.eps);
+    const double norm = 1.0 / (a.eps * a.eps * a.eps * M_PI * sqrt(M_PI));
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = (int)ceil((X[d] - 3.0 * a.eps - a.g.x0[d]) / a.g.h[d] - 0.5);
+        hi[d] = (int)floor((X[d] + 3.0 * a.eps - a.g.x0[d]) / a.g.h[d] - 0.5);
+        lo[d] = max(lo[d], a.box_lo[d]);
+        hi[d] = min(hi[d], a.box_lo[d] + a.box_n[d] - 1);
+    }
+    double acc[3] = {0, 0, 0};
+    for (int k = lo[2]; k <= hi[2]; ++k)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+            for (int i = lo[0]; i <= hi[0]; ++i) {
+                const double dx = a.g.x0[0] + (i + 0.5) * a.g.h[0] - X[0];
+                const double dy = a.g.x0[1] + (j + 0.5) * a.g.h[1] - X[1];
+                const double dz = a.g.x0[2] + (k + 0.5) * a.g.h[2] - X[2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 <= cut) {
+                    const double gw = norm * exp(-r2 * ie2);
+                    const long long q = pidx_g(a.g, i, j, k);
+                    for (int c = 0; c < 3; ++c) acc[c] += gw * A.lam_m[c][q];
+                }
+            }
+    const double dt = a.st->dt;
+    for (int c = 0; c < 3; ++c) A.pt[c * a.n_act + p] = dt * acc[c];
+}
+
+// per point: reverse of the blade-element forces; gradient in s and the adjoint of the sampled U
+__global__ void alm_adj_points_kernel(AlmAdjArgs A) {
+    const AlmArgs& a = A.fwd;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_act) return;
+    const int bl = p / a.npb, ip = p % a.npb;
+    const double t = a.st->t_next;
+    const double th = a.theta0 + a.omega * t + 2.0 * M_PI * (double)bl / (double)a.nb;
+    const double et1 = -sin(th), et2 = cos(th);
+    const double rr = a.r[ip], chord = a.chord[ip], twist = a.twist[ip], width = a.width[ip];
+    const double om = a.omega;
+    const double U0 = a.out_u[3 * p], U1 = a.out_u[3 * p + 1], U2 = a.out_u[3 * p + 2];
+    const double ux0 = U0, ut0 = U1 * et1 + U2 * et2;
+    // forward recompute
+    double ux = ux0, ut = ut0, fac = 1.0, g = 1.0, al0 = 0.0, U2_0 = 0.0;
+    const double kc = chord / (4.0 * sqrt(M_PI) * a.eps);
+    if (a.corr) {
+        const double x0 = om * rr - ut0;
+        U2_0 = ux0 * ux0 + x0 * x0;
+        al0 = atan2(ux0, x0) - twist;
+        const double cd0 = a.cd0 + a.cd2 * al0 * al0;
+        g = 1.0 - cd0 * kc;
+        fac = 1.0 / g;
+        ux = ux0 * fac;
+        ut = ut0 * fac;
+    }
+    const double xx = om * rr - ut;
+    const double phi = atan2(ux, xx);
+    const double alpha = phi - twist;
+    const double wr = ut - om * rr;
+    const double U2r = ux * ux + wr * wr;
+    const bool inside = (alpha > -a.alpha_clip) && (alpha < a.alpha_clip);
+    const double alc = fmin(fmax(alpha, -a.alpha_clip), a.alpha_clip);
+    const double cl = a.cl_slope * alc, cd = a.cd0 + a.cd2 * alpha * alpha;
+    const double q = 0.5 * a.rho_ref * chord * width * U2r;
+    const double L = q * cl, D = q * cd;
+    const double cph = cos(phi), sph = sin(phi);
+    const double fx0 = L * cph + D * sph, ft0 = L * sph - D * cph;
+    const double sp = a.scale ? a.scale[p] : 1.0;
+    // reverse
+    const double fv0 = A.pt[p], fv1 = A.pt[a.n_act + p], fv2 = A.pt[2 * a.n_act + p];
+    const double fxb = -fv0 + A.w1 * A.inv_n;
+    const double ftb = -(fv1 * et1 + fv2 * et2) + A.w0 * A.inv_n * om * rr;
+    A.grad_s[p] += fxb * fx0 + ftb * ft0;
+    const double fx0b = sp * fxb, ft0b = sp * ftb;
+    const double Lb = fx0b * cph + ft0b * sph;
+    const double Db = fx0b * sph - ft0b * cph;
+    double phib = -fx0b * ft0 + ft0b * fx0;
+    const double qb = Lb * cl + Db * cd;
+    const double clb = Lb * q, cdb = Db * q;
+    const double alb = clb * a.cl_slope * (inside ? 1.0 : 0.0) + cdb * 2.0 * a.cd2 * alpha;
+    phib += alb;
+    const double U2b = qb * 0.5 * a.rho_ref * chord * width;
+    double uxb = U2b * 2.0 * ux + phib * xx / U2r;
+    double utb = U2b * 2.0 * wr + phib * ux / U2r;
+    if (a.corr) {
+        const double facb = uxb * ux0 + utb * ut0;
+        uxb *= fac;
+        utb *= fac;
+        const double gb = -facb / (g * g);
+        const double cd0b = -gb * kc;
+        const double al0b = cd0b * 2.0 * a.cd2 * al0;
+        const double x0 = om * rr - ut0;
+        uxb += al0b * x0 / U2_0;
+        utb += al0b * ux0 / U2_0;
+    }
+    A.pt[3 * a.n_act + p] = uxb;
+    A.pt[4 * a.n_act + p] = utb * et1;
+    A.pt[5 * a.n_act + p] = utb * et2;
+}
+
+// adjoint of the trilinear sampling, points in fixed order (one thread)
+__global__ void alm_adj_scatter_kernel(AlmAdjArgs A) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const AlmArgs& a = A.fwd;
+    for (int p = 0; p < a.n_act; ++p) {
+        const double Ub[3] = {A.pt[3 * a.n_act + p], A.pt[4 * a.n_act + p], A.pt[5 * a.n_act + p]};
+        int i0[3];
+        double w1[3];
+        for (int d = 0; d < 3; ++d) {
+            const double fc = (a.X[3 * p + d] - a.g.x0[d]) / a.g.h[d] - 0.5;
+            const double fl = floor(fc);
+            i0[d] = (int)fl;
+            w1[d] = fc - fl;
+        }
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) * (dz ? w1[2] : 1.0 - w1[2]);
+                    const long long q = pidx_g(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+                    const double rho = a.rho_ref + A.qpre[0][q];
+                    double dot = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        const double Uc = A.qpre[1 + c][q] / rho;
+                        A.lam_pre[1 + c][q] += w * Ub[c] / rho;
+                        dot += Ub[c] * Uc;
+                    }
+                    A.lam_pre[0][q] += -w * dot / rho;
+                }
+    }
+}
+
+hipError_t launch_alm_adjoint(const AlmAdjArgs& A, hipStream_t s) {
+    const int n = A.fwd.n_act;
+    hipLaunchKernelGGL(alm_adj_gather_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(alm_adj_points_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(alm_adj_scatter_kernel, dim3(1), dim3(64), 0, s, A);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// workspace
+// ------------------------------------------------------------------------------------------------
+void adjoint_carve(char* base, int nx, int ny, int nz, int n_act, AdjBuffers* b, size_t* total) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    const size_t np = (size_t)(nx + 6) * (ny + 6) * (nz + 6);
+    const size_t N = (size_t)nx * ny * nz;
+    double** pads[6] = {b->lam, b->lam_pre, b->lam_star, b->acc, b->qwork, b->qpre};
+    for (int a = 0; a < 6; ++a)
+        for (int v = 0; v < 4; ++v) pads[a][v] = reinterpret_cast<double*>(take(np * 8));
+    for (int v = 0; v < 4; ++v) b->mu0[v] = reinterpret_cast<double*>(take(N * 8));
+    for (int v = 0; v < 4; ++v) b->mu1[v] = reinterpret_cast<double*>(take(N * 8));
+    const int n[3] = {nx, ny, nz};
+    const int ax[3][3] = {{0, 1, 2}, {1, 0, 2}, {2, 0, 1}};
+    size_t nface = 0, nt1 = 0, nn = 0;
+    for (int d = 0; d < 3; ++d) {
+        const size_t a0 = n[ax[d][0]] + 1, a1 = n[ax[d][1]], a2 = n[ax[d][2]];
+        nface = std::max(nface, a0 * a1 * a2);
+        nt1 = std::max(nt1, a0 * a1 * (a2 + 4));
+        nn = std::max(nn, a0 * (a1 + 4) * (a2 + 4));
+    }
+    b->gpbar = reinterpret_cast<double*>(take(80 * nface * 8));
+    b->w_t2 = reinterpret_cast<double*>(take(96 * nface * 8));
+    b->w_t1 = reinterpret_cast<double*>(take(48 * nt1 * 8));
+    b->t1bar = reinterpret_cast<double*>(take(40 * nt1 * 8));
+    b->w_n = reinterpret_cast<double*>(take(24 * nn * 8));
+    b->fabar = reinterpret_cast<double*>(take(12 * nn * 8));
+    b->pt = reinterpret_cast<double*>(take(16 * (size_t)std::max(n_act, 1) * 8));
+    *total = off;
+}
+
 size_t adjoint_workspace_bytes(int nx, int ny, int nz, int n_act) {
-    (void)nx;
-    (void)ny;
-    (void)nz;
-    (void)n_act;
-    return 256;
+    AdjBuffers b;
+    size_t t = 0;
+    adjoint_carve(nullptr, nx, ny, nz, n_act, &b, &t);
+    return t;
 }
 
 }  // namespace gks

@@ -182,8 +182,11 @@ int ghost_all(gks_ctx* c, void* const p[4]) {
     return GKS_OK;
 }
 
+// Face-kernel arguments for direction d. stage 1: reads src, writes out_a = Q*, out_b = S and reads
+// q_c = Q^n in the epilogue; stage 2: reads src = Q*, writes out_a = Q^{n+1} from s_in = S.
 template <typename real>
-FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
+FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], void* const out_a[4],
+                             void* const out_b[4], void* const q_c[4]) {
     FaceArgs<real> a;
     std::memset(&a, 0, sizeof(a));
     const int* pm = kPerm[d];
@@ -194,13 +197,12 @@ FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
         a.q[v] = static_cast<const real*>(src[gv]);
         a.r0[v] = static_cast<real*>(c->r0[gv]);
         a.r1[v] = static_cast<real*>(c->r1[gv]);
+        a.out_a[v] = static_cast<real*>(out_a[gv]);
         if (stage == 1) {
-            a.out_a[v] = static_cast<real*>(c->qs[gv]);
-            a.out_b[v] = static_cast<real*>(c->qa[gv]);
-            a.q_c[v] = static_cast<const real*>(c->q[gv]);
+            a.out_b[v] = static_cast<real*>(out_b[gv]);
+            a.q_c[v] = static_cast<const real*>(q_c[gv]);
         } else {
-            a.out_a[v] = static_cast<real*>(c->q[gv]);
-            a.s_in[v] = static_cast<const real*>(c->qa[gv]);
+            a.s_in[v] = static_cast<const real*>(out_b[gv]);
         }
     }
     a.n_n = c->g.n[ax[0]];
@@ -229,6 +231,60 @@ FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
     for (int j = 0; j < 3; ++j) a.g_local[j] = real(c->cfg.body_force[pm[1 + j] - 1]);
     a.dt_ptr = &c->st->dt;
     a.mode = d == 0 ? 0 : (d == 1 ? 1 : 2);
+    return a;
+}
+
+template <typename real>
+FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
+    if (stage == 1) return face_args_buf<real>(c, d, 1, src, c->qs, c->qa, c->q);
+    return face_args_buf<real>(c, d, 2, src, c->q, c->qa, nullptr);
+}
+
+AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4]) {
+    AdjFaceArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const int* pm = kPerm[d];
+    const int* ax = kAxes[d];
+    const long long ist[3] = {1, c->cfg.nx, (long long)c->cfg.nx * c->cfg.ny};
+    for (int v = 0; v < 4; ++v) {
+        const int gv = pm[v];
+        a.q[v] = static_cast<const double*>(src[gv]);
+        a.mu0[v] = B.mu0[gv];
+        a.mu1[v] = B.mu1[gv];
+        a.acc[v] = B.acc[gv];
+    }
+    a.gpbar = B.gpbar;
+    a.w_t2 = B.w_t2;
+    a.w_t1 = B.w_t1;
+    a.w_n = B.w_n;
+    a.t1bar = B.t1bar;
+    a.fabar = B.fabar;
+    a.n_n = c->g.n[ax[0]];
+    a.n_t1 = c->g.n[ax[1]];
+    a.n_t2 = c->g.n[ax[2]];
+    a.tiles_t1 = (a.n_t1 + TILE1 - 1) / TILE1;
+    a.tiles_t2 = (a.n_t2 + TILE2 - 1) / TILE2;
+    a.chunk = c->chunk[d];
+    a.st_n = c->g.st[ax[0]];
+    a.st_t1 = c->g.st[ax[1]];
+    a.st_t2 = c->g.st[ax[2]];
+    a.ist_n = ist[ax[0]];
+    a.ist_t1 = ist[ax[1]];
+    a.ist_t2 = ist[ax[2]];
+    a.pad0 = c->g.pad0;
+    a.nface = (long long)(a.n_n + 1) * a.n_t1 * a.n_t2;
+    a.nt1pos = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4);
+    a.nnpos = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    a.inv_hn = 1.0 / c->g.h[ax[0]];
+    a.inv_h1 = 1.0 / c->g.h[ax[1]];
+    a.inv_h2 = 1.0 / c->g.h[ax[2]];
+    a.eps = c->eps;
+    a.fc.lam = c->lam;
+    a.fc.sl = std::sqrt(c->lam);
+    a.fc.kk = 1.0 / (2.0 * std::sqrt(M_PI * c->lam));
+    a.fc.c2 = 1.0 / (2.0 * c->lam);
+    a.fc.mu = c->cfg.mu;
+    a.fc.rho_ref = c->cfg.rho_ref;
     return a;
 }
 
@@ -657,12 +713,97 @@ size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act) {
     return adjoint_workspace_bytes(cfg->nx, cfg->ny, cfg->nz, n_act);
 }
 
-int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, void* adj_ws, size_t adj_ws_bytes) {
+int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0, void* adj_ws,
+                size_t adj_ws_bytes) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!w || !grad_s || !adj_ws) return fail(c, GKS_E_INVALID_ARG, "null argument");
-    return fail(c, GKS_E_UNSUPPORTED, "adjoint not available in this build");
-    (void)nsteps;
-    (void)adj_ws_bytes;
+    if (c->cfg.precision != GKS_FP64) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs an FP64 context");
+    if (c->cfg.cfl > 0) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a fixed dt (cfl <= 0)");
+    if (!c->has_rotor) return fail(c, GKS_E_STATE, "the adjoint needs a rotor (gks_set_actuators)");
+    if (c->has_ibm) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover immersed bodies");
+    for (int sd = 0; sd < 6; ++sd)
+        if (c->cfg.bc[sd] == GKS_BC_INFLOW) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover inflow boundaries");
+    if (!c->ckpt || nsteps < 1 || nsteps > c->ckpt_n)
+        return fail(c, GKS_E_STATE, "need at least nsteps checkpointed steps (gks_set_checkpoints, then gks_step)");
+    if (reinterpret_cast<uintptr_t>(adj_ws) % 256) return fail(c, GKS_E_INVALID_ARG, "adj_ws must be 256-byte aligned");
+    const size_t need = adjoint_workspace_bytes(c->cfg.nx, c->cfg.ny, c->cfg.nz, c->alm.n_act);
+    if (adj_ws_bytes < need)
+        return fail(c, GKS_E_INVALID_ARG, "adjoint workspace too small: need " + std::to_string(need) + " bytes");
+    AdjBuffers B;
+    size_t tot = 0;
+    adjoint_carve(static_cast<char*>(adj_ws), c->cfg.nx, c->cfg.ny, c->cfg.nz, c->alm.n_act, &B, &tot);
+    const long long np = c->g.n_padded;
+    const double dt = c->cfg.dt_fixed;
+    hipStream_t S = c->stream;
+    for (int v = 0; v < 4; ++v) HIPCHK(c, launch_zero(B.lam[v], np, S));
+    HIPCHK(c, launch_zero(grad_s, c->alm.n_act, S));
+    const size_t slot = gks_checkpoint_slot_bytes(&c->cfg);
+    const size_t fb = ((size_t)np * 8 + 255) & ~size_t(255);
+    void* qwork[4];
+    void* qpre[4];
+    for (int v = 0; v < 4; ++v) {
+        qwork[v] = B.qwork[v];
+        qpre[v] = B.qpre[v];
+    }
+    for (int n = nsteps - 1; n >= 0; --n) {
+        // recompute step n from its checkpoint
+        const char* src = c->ckpt + (size_t)n * slot;
+        for (int v = 0; v < 4; ++v) HIPCHK(c, launch_copy_field(src + v * fb, B.qwork[v], (size_t)np * 8, S));
+        HIPCHK(c, launch_copy_field(src + slot - 256, &c->st->t, sizeof(double), S));
+        HIPCHK(c, launch_dt(c->st, 0.0, c->hmin, c->c, dt, S));
+        int rc = ghost_all<double>(c, qwork);
+        if (rc) return rc;
+        for (int d = 0; d < 3; ++d)
+            HIPCHK(c, launch_face<double>(face_args_buf<double>(c, d, 1, qwork, c->qs, c->qa, qwork), 1, S));
+        rc = ghost_all<double>(c, c->qs);
+        if (rc) return rc;
+        for (int d = 0; d < 3; ++d)
+            HIPCHK(c, launch_face<double>(face_args_buf<double>(c, d, 2, c->qs, qpre, c->qa, nullptr), 2, S));
+        HIPCHK(c, launch_alm_points_only(field<double>(qpre), c->alm, S));
+        // actuator line: lam_pre = lam + (sampling path); gradient in s
+        for (int v = 0; v < 4; ++v) HIPCHK(c, launch_axpby(B.lam_pre[v], B.lam[v], 1.0, nullptr, 0.0, np, S));
+        AlmAdjArgs A;
+        std::memset(&A, 0, sizeof(A));
+        A.fwd = c->alm;
+        for (int v = 0; v < 3; ++v) A.lam_m[v] = B.lam[1 + v];
+        for (int v = 0; v < 4; ++v) {
+            A.lam_pre[v] = B.lam_pre[v];
+            A.qpre[v] = B.qpre[v];
+        }
+        A.grad_s = grad_s;
+        A.pt = B.pt;
+        A.w0 = w[0];
+        A.w1 = w[1];
+        A.inv_n = 1.0 / nsteps;
+        HIPCHK(c, launch_alm_adjoint(A, S));
+        // stage 2: lam* = (dt^2/3) J_Lt(Q*)^T lam_pre
+        for (int v = 0; v < 4; ++v) {
+            HIPCHK(c, launch_pad_to_int(B.mu1[v], B.lam_pre[v], dt * dt / 3.0, nullptr, 0.0, c->g, S));
+            HIPCHK(c, launch_zero(B.acc[v], np, S));
+        }
+        for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, c->qs), 2, S));
+        HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, S));
+        for (int v = 0; v < 4; ++v) HIPCHK(c, launch_axpby(B.lam_star[v], B.acc[v], 1.0, nullptr, 0.0, np, S));
+        // stage 1: seeds dt lam_pre + dt/2 lam* (of L) and dt^2/6 lam_pre + dt^2/8 lam* (of L_t) at Q^n
+        for (int v = 0; v < 4; ++v) {
+            HIPCHK(c, launch_pad_to_int(B.mu0[v], B.lam_pre[v], dt, B.lam_star[v], 0.5 * dt, c->g, S));
+            HIPCHK(c, launch_pad_to_int(B.mu1[v], B.lam_pre[v], dt * dt / 6.0, B.lam_star[v], dt * dt / 8.0, c->g, S));
+            HIPCHK(c, launch_zero(B.acc[v], np, S));
+        }
+        for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, qwork), 1, S));
+        HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, S));
+        // lam^n = lam_pre + lam* + J^T(...)
+        for (int v = 0; v < 4; ++v) {
+            HIPCHK(c, launch_axpby(B.lam[v], B.lam_pre[v], 1.0, B.lam_star[v], 1.0, np, S));
+            HIPCHK(c, launch_axpby(B.lam[v], B.lam[v], 1.0, B.acc[v], 1.0, np, S));
+        }
+    }
+    if (grad_q0) {
+        const long long N = (long long)c->cfg.nx * c->cfg.ny * c->cfg.nz;
+        for (int v = 0; v < 4; ++v) HIPCHK(c, launch_pad_to_int(grad_q0 + v * N, B.lam[v], 1.0, nullptr, 0.0, c->g, S));
+    }
+    HIPCHK(c, hipStreamSynchronize(S));
+    return GKS_OK;
 }
 
 int gks_set_timing(gks_ctx* c, int32_t enable) {

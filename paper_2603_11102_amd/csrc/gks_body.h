@@ -44,6 +44,7 @@ struct IbmArgs {
 template <typename real>
 hipError_t launch_alm(Field4<real> f, const AlmArgs& a, hipStream_t s);
 hipError_t launch_ibm_vbar(const IbmArgs& a, hipStream_t s);
+hipError_t launch_alm_points_only(Field4<double> f, const AlmArgs& a, hipStream_t s);
 template <typename real>
 hipError_t launch_ibm(Field4<real> f, const IbmArgs& a, hipStream_t s);
 int ibm_blocks(int ncell);

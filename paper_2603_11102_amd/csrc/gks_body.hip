@@ -180,6 +180,13 @@ hipError_t launch_alm(Field4<real> f, const AlmArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_alm_points_only(Field4<double> f, const AlmArgs& a, hipStream_t s) {
+    int bs = 64;
+    while (bs < a.n_act) bs <<= 1;
+    hipLaunchKernelGGL((alm_points_kernel<double>), dim3(1), dim3(bs), 0, s, f, a);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------------
 // IBM
 // ------------------------------------------------------------------------------------------------

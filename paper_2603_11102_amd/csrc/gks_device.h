@@ -35,12 +35,25 @@ template <> struct Rc<double> {
 
 #define GKS_SQRT3 1.7320508075688772935274463415059
 
+// Reciprocal: FP32 uses the hardware v_rcp_f32 (about 1 ulp); FP64 refines v_rcp_f64 by two Newton
+// steps (about 1 ulp). Arguments are positive normal numbers here (densities, WENO denominators).
+template <typename real> __device__ __forceinline__ real rcp(real x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return y;
+}
+
 // ---------------------------------------------------------------------------------------------
-// WENO-JS smoothness indicators of the three quadratic sub-stencils of five cells q[-2..2]
+// WENO-JS smoothness indicators of the three quadratic sub-stencils of five cells q[-2..2].
+// Returns P_k = prod_{j != k} (eps + beta_j)^2: the nonlinear weights gamma_k / (eps + beta_k)^2,
+// normalised, equal gamma_k P_k / sum_j gamma_j P_j, so one reciprocal per evaluation point suffices.
 // ---------------------------------------------------------------------------------------------
 template <typename real>
 __device__ __forceinline__ void js_weights(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
-                                           real& w0, real& w1, real& w2) {
+                                           real& P0, real& P1, real& P2) {
     const real c13 = real(13.0 / 12.0);
     real a = qm2 - real(2) * qm1 + q0, b = qm2 - real(4) * qm1 + real(3) * q0;
     real b0 = c13 * a * a + real(0.25) * b * b;
@@ -51,9 +64,12 @@ __device__ __forceinline__ void js_weights(real qm2, real qm1, real q0, real qp1
     b = real(3) * q0 - real(4) * qp1 + qp2;
     real b2 = c13 * a * a + real(0.25) * b * b;
     real e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
-    w0 = real(1) / (e0 * e0);
-    w1 = real(1) / (e1 * e1);
-    w2 = real(1) / (e2 * e2);
+    e0 *= e0;
+    e1 *= e1;
+    e2 *= e2;
+    P0 = e1 * e2;
+    P1 = e0 * e2;
+    P2 = e0 * e1;
 }
 
 // Face values of cell 0: right face (xi = +1/2, linear weights 1/10, 3/5, 3/10) and left face
@@ -61,20 +77,20 @@ __device__ __forceinline__ void js_weights(real qm2, real qm1, real q0, real qp1
 template <typename real>
 __device__ __forceinline__ void weno_faces(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                            real& right, real& left) {
-    real w0, w1, w2;
-    js_weights(qm2, qm1, q0, qp1, qp2, eps, w0, w1, w2);
+    real P0, P1, P2;
+    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
     const real s6 = real(1.0 / 6.0);
     real r0 = s6 * (real(2) * qm2 - real(7) * qm1 + real(11) * q0);
     real r1 = s6 * (-qm1 + real(5) * q0 + real(2) * qp1);
     real r2 = s6 * (real(2) * q0 + real(5) * qp1 - qp2);
-    real a0 = real(0.1) * w0, a1 = real(0.6) * w1, a2 = real(0.3) * w2;
-    right = (a0 * r0 + a1 * r1 + a2 * r2) / (a0 + a1 + a2);
+    real a0 = real(0.1) * P0, a1 = real(0.6) * P1, a2 = real(0.3) * P2;
+    right = (a0 * r0 + a1 * r1 + a2 * r2) * rcp<real>(a0 + a1 + a2);
     real l0 = s6 * (-qm2 + real(5) * qm1 + real(2) * q0);
     real l1 = s6 * (real(2) * qm1 + real(5) * q0 - qp1);
     real l2 = s6 * (real(11) * q0 - real(7) * qp1 + real(2) * qp2);
-    a0 = real(0.3) * w0;
-    a2 = real(0.1) * w2;
-    left = (a0 * l0 + a1 * l1 + a2 * l2) / (a0 + a1 + a2);
+    a0 = real(0.3) * P0;
+    a2 = real(0.1) * P2;
+    left = (a0 * l0 + a1 * l1 + a2 * l2) * rcp<real>(a0 + a1 + a2);
 }
 
 // WENO-JS values at the two Gauss points of cell 0. Each sub-stencil quadratic is q0 + s d_k at
@@ -83,20 +99,20 @@ __device__ __forceinline__ void weno_faces(real qm2, real qm1, real q0, real qp1
 template <typename real>
 __device__ __forceinline__ void weno_gauss(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                            real& vm, real& vp) {
-    real w0, w1, w2;
-    js_weights(qm2, qm1, q0, qp1, qp2, eps, w0, w1, w2);
+    real P0, P1, P2;
+    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
     const real r3 = real(GKS_SQRT3);
     real d0 = r3 * (real(1.0 / 12.0) * qm2 - real(1.0 / 3.0) * qm1 + real(0.25) * q0);
     real d1 = r3 * real(1.0 / 12.0) * (qp1 - qm1);
     real d2 = r3 * (-real(0.25) * q0 + real(1.0 / 3.0) * qp1 - real(1.0 / 12.0) * qp2);
     const real gc = real(7.0 / 36.0), gd = real(GKS_SQRT3 / 1080.0), g1 = real(11.0 / 18.0);
     // s = +1
-    real a0 = (gc - gd) * w0, a1 = g1 * w1, a2 = (gc + gd) * w2;
-    vp = q0 + (a0 * d0 + a1 * d1 + a2 * d2) / (a0 + a1 + a2);
+    real a0 = (gc - gd) * P0, a1 = g1 * P1, a2 = (gc + gd) * P2;
+    vp = q0 + (a0 * d0 + a1 * d1 + a2 * d2) * rcp<real>(a0 + a1 + a2);
     // s = -1
-    a0 = (gc + gd) * w0;
-    a2 = (gc - gd) * w2;
-    vm = q0 - (a0 * d0 + a1 * d1 + a2 * d2) / (a0 + a1 + a2);
+    a0 = (gc + gd) * P0;
+    a2 = (gc - gd) * P2;
+    vm = q0 - (a0 * d0 + a1 * d1 + a2 * d2) * rcp<real>(a0 + a1 + a2);
 }
 
 // Quartic through five cell averages: values at the two Gauss points.
@@ -160,7 +176,7 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
                                         const FluxConst<real>& k, real w, real f0[4], real f1[4]) {
     // kinetic (half-space) average of the left and right Maxwellians, in deviation form
     real rL = k.rho_ref + qL[0], rR = k.rho_ref + qR[0];
-    real uL = qL[1] / rL, uR = qR[1] / rR;
+    real uL = qL[1] * rcp<real>(rL), uR = qR[1] * rcp<real>(rR);
     real aL = k.sl * uL, aR = k.sl * uR;
     real eaL = Rc<real>::erf_(aL), eaR = Rc<real>::erf_(aR);
     real hL = real(0.5) * (real(1) + eaL);
@@ -174,7 +190,7 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
     m0[1] = qL[2] * hL + qR[2] * hR;
     m0[2] = qL[3] * hL + qR[3] * hR;
     real r0 = k.rho_ref + rho0p;
-    real ir = real(1) / r0;
+    real ir = rcp<real>(r0);
     real U[3] = {m0[0] * ir, m0[1] * ir, m0[2] * ir};
     // velocity gradients dU[d][j] = (dm_j/dx_d - U_j drho/dx_d) / rho0
     real dU[3][3];
@@ -201,6 +217,237 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
     f1[1] += w * (real(2) * U[0] * qd[0] - U[0] * U[0] * qd0 + k.c2 * qd0);
     f1[2] += w * (U[1] * qd[0] + U[0] * qd[1] - U[0] * U[1] * qd0);
     f1[3] += w * (U[2] * qd[0] + U[0] * qd[2] - U[0] * U[2] * qd0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint support (FP64): WENO evaluations that also return their normalised nonlinear weights, the
+// sub-stencil coefficients those weights combine, and the reverse of gp_flux.
+// ---------------------------------------------------------------------------------------------
+template <typename real>
+__device__ __forceinline__ void weno_faces_w(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
+                                             real& right, real& left, real wr[3], real wl[3]) {
+    real P0, P1, P2;
+    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
+    const real s6 = real(1.0 / 6.0);
+    real r0 = s6 * (real(2) * qm2 - real(7) * qm1 + real(11) * q0);
+    real r1 = s6 * (-qm1 + real(5) * q0 + real(2) * qp1);
+    real r2 = s6 * (real(2) * q0 + real(5) * qp1 - qp2);
+    real a0 = real(0.1) * P0, a1 = real(0.6) * P1, a2 = real(0.3) * P2;
+    real is = rcp<real>(a0 + a1 + a2);
+    wr[0] = a0 * is;
+    wr[1] = a1 * is;
+    wr[2] = a2 * is;
+    right = (a0 * r0 + a1 * r1 + a2 * r2) * is;
+    real l0 = s6 * (-qm2 + real(5) * qm1 + real(2) * q0);
+    real l1 = s6 * (real(2) * qm1 + real(5) * q0 - qp1);
+    real l2 = s6 * (real(11) * q0 - real(7) * qp1 + real(2) * qp2);
+    a0 = real(0.3) * P0;
+    a2 = real(0.1) * P2;
+    is = rcp<real>(a0 + a1 + a2);
+    wl[0] = a0 * is;
+    wl[1] = a1 * is;
+    wl[2] = a2 * is;
+    left = (a0 * l0 + a1 * l1 + a2 * l2) * is;
+}
+
+template <typename real>
+__device__ __forceinline__ void weno_gauss_w(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
+                                             real& vm, real& vp, real wm[3], real wp[3]) {
+    real P0, P1, P2;
+    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
+    const real r3 = real(GKS_SQRT3);
+    real d0 = r3 * (real(1.0 / 12.0) * qm2 - real(1.0 / 3.0) * qm1 + real(0.25) * q0);
+    real d1 = r3 * real(1.0 / 12.0) * (qp1 - qm1);
+    real d2 = r3 * (-real(0.25) * q0 + real(1.0 / 3.0) * qp1 - real(1.0 / 12.0) * qp2);
+    const real gc = real(7.0 / 36.0), gd = real(GKS_SQRT3 / 1080.0), g1 = real(11.0 / 18.0);
+    real a0 = (gc - gd) * P0, a1 = g1 * P1, a2 = (gc + gd) * P2;
+    real is = rcp<real>(a0 + a1 + a2);
+    wp[0] = a0 * is;
+    wp[1] = a1 * is;
+    wp[2] = a2 * is;
+    vp = q0 + (a0 * d0 + a1 * d1 + a2 * d2) * is;
+    a0 = (gc + gd) * P0;
+    a2 = (gc - gd) * P2;
+    is = rcp<real>(a0 + a1 + a2);
+    wm[0] = a0 * is;
+    wm[1] = a1 * is;
+    wm[2] = a2 * is;
+    vm = q0 - (a0 * d0 + a1 * d1 + a2 * d2) * is;
+}
+
+// Coefficient of cell r (0..4 over the stencil -2..2) in sub-stencil k's value:
+//   face xi = +1/2 (side 0) and xi = -1/2 (side 1); Gauss point s = -1 (side 2) and s = +1 (side 3).
+__device__ __forceinline__ double sub_coef(int side, int k, int r) {
+    const int l = r - k;
+    if (l < 0 || l > 2) return 0.0;
+    const double t = GKS_SQRT3;
+    switch (side) {
+        case 0: {
+            const double c[3][3] = {{2.0 / 6, -7.0 / 6, 11.0 / 6}, {-1.0 / 6, 5.0 / 6, 2.0 / 6}, {2.0 / 6, 5.0 / 6, -1.0 / 6}};
+            return c[k][l];
+        }
+        case 1: {
+            const double c[3][3] = {{-1.0 / 6, 5.0 / 6, 2.0 / 6}, {2.0 / 6, 5.0 / 6, -1.0 / 6}, {11.0 / 6, -7.0 / 6, 2.0 / 6}};
+            return c[k][l];
+        }
+        default: {
+            const double s = side == 2 ? -1.0 : 1.0;
+            const double c[3][3] = {{s * t / 12, -s * t / 3, 1.0 + s * t / 4},
+                                    {-s * t / 12, 1.0, s * t / 12},
+                                    {1.0 - s * t / 4, s * t / 3, -s * t / 12}};
+            return c[k][l];
+        }
+    }
+}
+
+// Effective linear weight of stencil cell r for nonlinear weights w[3] on a given side.
+__device__ __forceinline__ double weno_eff(int side, const double w[3], int r) {
+    return w[0] * sub_coef(side, 0, r) + w[1] * sub_coef(side, 1, r) + w[2] * sub_coef(side, 2, r);
+}
+
+// Quartic Gauss value (deriv = 0) or derivative (deriv = 1) coefficient of stencil cell r at s.
+__device__ __forceinline__ double quartic_coef(int deriv, int s, int r) {
+    const double t = GKS_SQRT3;
+    if (deriv == 0) {
+        const double e[5] = {-1.0 / 4320, 1.0 / 1080, 719.0 / 720, 1.0 / 1080, -1.0 / 4320};
+        const double o[5] = {7.0 / 432, -25.0 / 216, 0.0, 25.0 / 216, -7.0 / 432};
+        return e[r] + s * t * o[r];
+    }
+    const double e[5] = {1.0 / 12, -2.0 / 3, 0.0, 2.0 / 3, -1.0 / 12};
+    const double o[5] = {-1.0 / 54, 13.0 / 54, -4.0 / 9, 13.0 / 54, -1.0 / 54};
+    return e[r] + s * t * o[r];
+}
+
+// Reverse of gp_flux (FP64): given the adjoints b0 (of the accumulated F0 contribution, stage 1
+// only) and b1 (of F1), add the adjoints of the Gauss-point inputs to qLb, qRb, gb.
+template <bool NEED_F0>
+__device__ __forceinline__ void gp_flux_adj(const double qL[4], const double qR[4], const double g[3][4],
+                                            const FluxConst<double>& k, double w, const double b0[4],
+                                            const double b1[4], double qLb[4], double qRb[4], double gb[3][4]) {
+    // ---- forward recompute
+    const double rL = k.rho_ref + qL[0], rR = k.rho_ref + qR[0];
+    const double irL = rcp<double>(rL), irR = rcp<double>(rR);
+    const double uL = qL[1] * irL, uR = qR[1] * irR;
+    const double aL = k.sl * uL, aR = k.sl * uR;
+    const double EaL = erf(aL), EaR = erf(aR);
+    const double hL = 0.5 * (1.0 + EaL), hR = 0.5 * (1.0 - EaR);
+    const double eR = exp(-k.lam * uR * uR), eL = exp(-k.lam * uL * uL);
+    const double dE = eR * expm1(k.lam * (uR - uL) * (uR + uL));
+    const double rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * 0.5 * erf_diff<double>(aL, aR);
+    double m0[3];
+    m0[0] = qL[1] * hL + qR[1] * hR + k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
+    m0[1] = qL[2] * hL + qR[2] * hR;
+    m0[2] = qL[3] * hL + qR[3] * hR;
+    const double r0 = k.rho_ref + rho0p;
+    const double ir = rcp<double>(r0);
+    double U[3] = {m0[0] * ir, m0[1] * ir, m0[2] * ir};
+    double dU[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < 3; ++j) dU[d][j] = (g[d][1 + j] - U[j] * g[d][0]) * ir;
+    const double divm = g[0][1] + g[1][2] + g[2][3];
+    const double qd0 = -divm;
+    double adv[3], qd[3];
+    for (int j = 0; j < 3; ++j) {
+        adv[j] = U[0] * dU[0][j] + U[1] * dU[1][j] + U[2] * dU[2][j];
+        qd[j] = -U[j] * divm - r0 * adv[j] - k.c2 * g[j][0];
+    }
+    // ---- reverse
+    double A1[4], A0[4];
+    for (int v = 0; v < 4; ++v) {
+        A1[v] = w * b1[v];
+        A0[v] = NEED_F0 ? w * b0[v] : 0.0;
+    }
+    double Ub[3] = {0, 0, 0}, m0b[3] = {0, 0, 0}, dUb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double qdb[3] = {0, 0, 0};
+    double qd0b = 0.0, r0b = 0.0, r0pb = 0.0, irb = 0.0, divmb = 0.0;
+    // F1
+    qdb[0] += A1[0];
+    Ub[0] += A1[1] * (2.0 * qd[0] - 2.0 * U[0] * qd0);
+    qdb[0] += A1[1] * 2.0 * U[0];
+    qd0b += A1[1] * (-U[0] * U[0] + k.c2);
+    for (int j = 1; j < 3; ++j) {
+        Ub[j] += A1[1 + j] * (qd[0] - U[0] * qd0);
+        Ub[0] += A1[1 + j] * (qd[j] - U[j] * qd0);
+        qdb[0] += A1[1 + j] * U[j];
+        qdb[j] += A1[1 + j] * U[0];
+        qd0b += -A1[1 + j] * U[0] * U[j];
+    }
+    double advb[3];
+    for (int j = 0; j < 3; ++j) {
+        Ub[j] += -qdb[j] * divm;
+        divmb += -qdb[j] * U[j];
+        r0b += -qdb[j] * adv[j];
+        advb[j] = -qdb[j] * r0;
+        gb[j][0] += -k.c2 * qdb[j];
+    }
+    for (int j = 0; j < 3; ++j)
+        for (int d = 0; d < 3; ++d) {
+            Ub[d] += advb[j] * dU[d][j];
+            dUb[d][j] += advb[j] * U[d];
+        }
+    divmb += -qd0b;
+    gb[0][1] += divmb;
+    gb[1][2] += divmb;
+    gb[2][3] += divmb;
+    // F0
+    if (NEED_F0) {
+        m0b[0] += A0[0];
+        m0b[0] += A0[1] * U[0];
+        Ub[0] += A0[1] * m0[0];
+        r0pb += A0[1] * k.c2;
+        dUb[0][0] += -2.0 * k.mu * A0[1];
+        for (int j = 1; j < 3; ++j) {
+            m0b[0] += A0[1 + j] * U[j];
+            Ub[j] += A0[1 + j] * m0[0];
+            dUb[0][j] += -k.mu * A0[1 + j];
+            dUb[j][0] += -k.mu * A0[1 + j];
+        }
+    }
+    // velocity gradients
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < 3; ++j) {
+            gb[d][1 + j] += dUb[d][j] * ir;
+            Ub[j] += -dUb[d][j] * g[d][0] * ir;
+            gb[d][0] += -dUb[d][j] * U[j] * ir;
+            irb += dUb[d][j] * dU[d][j] * r0;
+        }
+    for (int j = 0; j < 3; ++j) {
+        m0b[j] += Ub[j] * ir;
+        irb += Ub[j] * m0[j];
+    }
+    r0b += -irb * ir * ir;
+    r0pb += r0b;
+    // kinetic average
+    double hLb = 0.0, hRb = 0.0, eLb = 0.0, eRb = 0.0, EaLb = 0.0, EaRb = 0.0;
+    for (int j = 1; j < 3; ++j) {
+        qLb[1 + j] += m0b[j] * hL;
+        qRb[1 + j] += m0b[j] * hR;
+        hLb += m0b[j] * qL[1 + j];
+        hRb += m0b[j] * qR[1 + j];
+    }
+    qLb[1] += m0b[0] * hL;
+    qRb[1] += m0b[0] * hR;
+    hLb += m0b[0] * qL[1];
+    hRb += m0b[0] * qR[1];
+    qLb[0] += m0b[0] * k.kk * eL;
+    qRb[0] += -m0b[0] * k.kk * eR;
+    eLb += m0b[0] * k.kk * (qL[0] + k.rho_ref);
+    eRb += -m0b[0] * k.kk * (qR[0] + k.rho_ref);
+    qLb[0] += r0pb * hL;
+    qRb[0] += r0pb * hR;
+    hLb += r0pb * qL[0];
+    hRb += r0pb * qR[0];
+    EaLb += 0.5 * k.rho_ref * r0pb;
+    EaRb += -0.5 * k.rho_ref * r0pb;
+    EaLb += 0.5 * hLb;
+    EaRb += -0.5 * hRb;
+    const double c2pi = 1.1283791670955126;  // 2 / sqrt(pi)
+    double uLb = k.sl * EaLb * c2pi * exp(-aL * aL) + eLb * eL * (-2.0 * k.lam * uL);
+    double uRb = k.sl * EaRb * c2pi * exp(-aR * aR) + eRb * eR * (-2.0 * k.lam * uR);
+    qLb[1] += uLb * irL;
+    qLb[0] += -uLb * qL[1] * irL * irL;
+    qRb[1] += uRb * irR;
+    qRb[0] += -uRb * qR[1] * irR * irR;
 }
 
 }  // namespace gks

@@ -74,6 +74,13 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
         }
     }
 
+    // software pipelining: the cell entering the window at the next step is loaded one step ahead
+    real nxt[4] = {real(0), real(0), real(0), real(0)};
+    if (col_ld) {
+        const long long idx = cbase + (long long)(f0 + 2) * a.st_n;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
+    }
     const real dt = real(*a.dt_ptr);
     real fprev0[4], fprev1[4];
 #pragma unroll
@@ -83,14 +90,18 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     }
 
     for (int f = f0; f <= f1; ++f) {
-        // column phase setup: window cells f-2 .. f+2
+        // column phase setup: window cells f-2 .. f+2; prefetch cell f+3
         if (col_ld) {
-            const long long idx = cbase + (long long)(f + 2) * a.st_n;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
-                ring[v][4] = a.q[v][idx];
+                ring[v][4] = nxt[v];
+            }
+            if (f < f1) {
+                const long long idx = cbase + (long long)(f + 3) * a.st_n;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
             }
         }
         real gp[4][2][5];  // [variable][Gauss n][q^L, q^R, d/dn, d/dt1, d/dt2]

@@ -168,6 +168,32 @@ class GksSolver:
         L.check(self.lib, self.ctx, self.lib.gks_read_timing(self.ctx, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(L.TIMERS)}
 
+    # ------------------------------------------------------------------ adjoint
+    def set_checkpoints(self, capacity: int):
+        """Register a device buffer of `capacity` checkpoint slots; the next steps store Q^n per step."""
+        slot = self.lib.gks_checkpoint_slot_bytes(C.byref(self.c_cfg))
+        self._ckpt = torch.empty(capacity * slot + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._ckpt.data_ptr() + 255) // 256 * 256
+        L.check(self.lib, self.ctx, self.lib.gks_set_checkpoints(self.ctx, C.c_void_p(ptr), int(capacity)))
+
+    def adjoint(self, nsteps: int, w, want_field: bool = False):
+        """Gradient of J = w0 mean P + w1 mean T over the checkpointed window with respect to the force
+        scalings (device float64 [n_act]); optionally dJ/dQ^0 as [4, nz, ny, nx]."""
+        nbytes = self.lib.gks_adjoint_workspace_bytes(C.byref(self.c_cfg), self.n_act)
+        if getattr(self, "_adj_ws", None) is None or self._adj_ws.numel() < nbytes + 256:
+            self._adj_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._adj_ws.data_ptr() + 255) // 256 * 256
+        grad_s = torch.empty(self.n_act, dtype=torch.float64, device=self.device)
+        gq = None
+        if want_field:
+            gq = torch.empty((4, self.cfg.nz, self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.device)
+        wv = (C.c_double * 2)(float(w[0]), float(w[1]))
+        rc = self.lib.gks_adjoint(self.ctx, int(nsteps), wv, C.c_void_p(grad_s.data_ptr()),
+                                  C.c_void_p(gq.data_ptr()) if gq is not None else None,
+                                  C.c_void_p(ptr), C.c_size_t(nbytes))
+        L.check(self.lib, self.ctx, rc)
+        return grad_s, gq
+
     def reset_window(self):
         L.check(self.lib, self.ctx, self.lib.gks_reset_window(self.ctx))
 
