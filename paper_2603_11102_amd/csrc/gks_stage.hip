@@ -7,14 +7,16 @@
 //   * column phase: each of the 20 x 20 tangential columns (tile + 2-cell halo per side) keeps a
 //     5-cell window of the field in registers; per cell it evaluates the WENO-JS values at both of its
 //     faces with one set of smoothness indicators, the normal derivative D (cubic through four cells)
-//     and C = (q^L + q^R)/2 -> LDS;
+//     and C = (q^L + q^R)/2 for all four variables -> LDS;
 //   * t1 phase: WENO-JS at the two Gauss points of q^L, q^R, quartic Gauss values of D and C and the
-//     quartic Gauss derivative of C along t1 -> LDS;
+//     quartic Gauss derivative of C along t1, the 4 x 320 (variable, position) items spread over all
+//     512 threads -> LDS;
 //   * t2 phase: the same along t2 for each Gauss line, giving per Gauss point q^L, q^R, dQ/dn, dQ/dt1,
 //     dQ/dt2 in registers (one thread per face and Gauss line);
 //   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
-// No face flux is written to memory.
+// No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
+// variables (77 KB in FP32, 154 KB in FP64 of the 160 KB per CU).
 #include "gks_internal.h"
 
 namespace gks {
@@ -22,8 +24,9 @@ namespace gks {
 template <typename real, int STAGE>
 __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
     constexpr bool NEED_F0 = (STAGE == 1);
-    __shared__ real s_nrm[4][EXT2][EXT1];        // q^L, q^R, D, C of the current variable
-    __shared__ real s_t1[5][EXT2][TILE1][2];     // q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m
+    constexpr int NT1 = TILE1 * EXT2;             // t1 items per variable (320)
+    __shared__ real s_nrm[4][4][EXT2][EXT1];      // [variable][q^L, q^R, D, C]
+    __shared__ real s_t1[4][5][EXT2][TILE1][2];   // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
 
     const int tid = threadIdx.x;
     int b = blockIdx.x;
@@ -42,9 +45,6 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     const int jc = j0 - 2 + c1, kc = k0 - 2 + c2;
     const bool col_ld = col && (jc < a.n_t1 + NG) && (kc < a.n_t2 + NG);
     const long long cbase = a.pad0 + (long long)jc * a.st_t1 + (long long)kc * a.st_t2;
-    // t1 role
-    const bool t1r = tid < TILE1 * EXT2;
-    const int tj = tid % TILE1, tk = tid / TILE1;
     // face role: face (fj, fk) of the tile, Gauss line m (partner lane tid ^ 1 holds the other line)
     const int m = tid & 1;
     const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
@@ -73,7 +73,6 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             carry[v] = right;
         }
     }
-
     // software pipelining: the cell entering the window at the next step is loaded one step ahead
     real nxt[4] = {real(0), real(0), real(0), real(0)};
     if (col_ld) {
@@ -90,93 +89,89 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     }
 
     for (int f = f0; f <= f1; ++f) {
-        // column phase setup: window cells f-2 .. f+2; prefetch cell f+3
-        if (col_ld) {
+        // ---- column phase (all variables): window cells f-2 .. f+2, prefetch cell f+3
+        if (col) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
                 ring[v][4] = nxt[v];
             }
-            if (f < f1) {
+            if (col_ld && f < f1) {
                 const long long idx = cbase + (long long)(f + 3) * a.st_n;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
             }
-        }
-        real gp[4][2][5];  // [variable][Gauss n][q^L, q^R, d/dn, d/dt1, d/dt2]
-
-        auto column = [&](int v) {
-            if (col) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
                 real right, left;
                 weno_faces<real>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left);
                 const real qL = carry[v];
                 const real D = (ring[v][0] - real(15) * ring[v][1] + real(15) * ring[v][2] - ring[v][3]) *
                                (real(1.0 / 12.0) * a.inv_hn);
-                s_nrm[0][c2][c1] = qL;
-                s_nrm[1][c2][c1] = left;
-                s_nrm[2][c2][c1] = D;
-                s_nrm[3][c2][c1] = real(0.5) * (qL + left);
+                s_nrm[v][0][c2][c1] = qL;
+                s_nrm[v][1][c2][c1] = left;
+                s_nrm[v][2][c2][c1] = D;
+                s_nrm[v][3][c2][c1] = real(0.5) * (qL + left);
                 carry[v] = right;
             }
-        };
-
-        column(0);
+        }
         __syncthreads();
+        // ---- t1 phase: 4 x 320 (variable, item) pairs spread over all threads
+        for (int it = tid; it < 4 * NT1; it += FACE_THREADS) {
+            const int v = it / NT1, item = it - v * NT1;
+            const int tj = item % TILE1, tk = item / TILE1;
+            real x[4][5];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[v][q][tk][tj + r];
+            real vm, vp;
+            weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
+            s_t1[v][0][tk][tj][0] = vm;
+            s_t1[v][0][tk][tj][1] = vp;
+            weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
+            s_t1[v][1][tk][tj][0] = vm;
+            s_t1[v][1][tk][tj][1] = vp;
+            quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
+            s_t1[v][2][tk][tj][0] = vm;
+            s_t1[v][2][tk][tj][1] = vp;
+            quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+            s_t1[v][3][tk][tj][0] = vm * a.inv_h1;
+            s_t1[v][3][tk][tj][1] = vp * a.inv_h1;
+            quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+            s_t1[v][4][tk][tj][0] = vm;
+            s_t1[v][4][tk][tj][1] = vp;
+        }
+        __syncthreads();
+        // ---- t2 phase: per thread one face and one Gauss line, all variables
+        real gp[4][2][5];  // [variable][Gauss n][q^L, q^R, d/dn, d/dt1, d/dt2]
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            if (t1r) {
-                real x[4][5];
+            real y[5][5];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 5; ++q)
 #pragma unroll
-                    for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[q][tk][tj + r];
-                real vm, vp;
-                weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
-                s_t1[0][tk][tj][0] = vm;
-                s_t1[0][tk][tj][1] = vp;
-                weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
-                s_t1[1][tk][tj][0] = vm;
-                s_t1[1][tk][tj][1] = vp;
-                quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
-                s_t1[2][tk][tj][0] = vm;
-                s_t1[2][tk][tj][1] = vp;
-                quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-                s_t1[3][tk][tj][0] = vm * a.inv_h1;
-                s_t1[3][tk][tj][1] = vp * a.inv_h1;
-                quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-                s_t1[4][tk][tj][0] = vm;
-                s_t1[4][tk][tj][1] = vp;
-            }
-            __syncthreads();
-            {
-                real y[5][5];
-#pragma unroll
-                for (int q = 0; q < 5; ++q)
-#pragma unroll
-                    for (int r = 0; r < 5; ++r) y[q][r] = s_t1[q][fk + r][fj][m];
-                real vm, vp;
-                weno_gauss<real>(y[0][0], y[0][1], y[0][2], y[0][3], y[0][4], eps, vm, vp);
-                gp[v][0][0] = vm;
-                gp[v][1][0] = vp;
-                weno_gauss<real>(y[1][0], y[1][1], y[1][2], y[1][3], y[1][4], eps, vm, vp);
-                gp[v][0][1] = vm;
-                gp[v][1][1] = vp;
-                quartic_gauss_value<real>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
-                gp[v][0][2] = vm;
-                gp[v][1][2] = vp;
-                quartic_gauss_value<real>(y[3][0], y[3][1], y[3][2], y[3][3], y[3][4], vm, vp);
-                gp[v][0][3] = vm;
-                gp[v][1][3] = vp;
-                quartic_gauss_deriv<real>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
-                gp[v][0][4] = vm * a.inv_h2;
-                gp[v][1][4] = vp * a.inv_h2;
-            }
-            if (v < 3) column(v + 1);
-            __syncthreads();
+                for (int r = 0; r < 5; ++r) y[q][r] = s_t1[v][q][fk + r][fj][m];
+            real vm, vp;
+            weno_gauss<real>(y[0][0], y[0][1], y[0][2], y[0][3], y[0][4], eps, vm, vp);
+            gp[v][0][0] = vm;
+            gp[v][1][0] = vp;
+            weno_gauss<real>(y[1][0], y[1][1], y[1][2], y[1][3], y[1][4], eps, vm, vp);
+            gp[v][0][1] = vm;
+            gp[v][1][1] = vp;
+            quartic_gauss_value<real>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
+            gp[v][0][2] = vm;
+            gp[v][1][2] = vp;
+            quartic_gauss_value<real>(y[3][0], y[3][1], y[3][2], y[3][3], y[3][4], vm, vp);
+            gp[v][0][3] = vm;
+            gp[v][1][3] = vp;
+            quartic_gauss_deriv<real>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
+            gp[v][0][4] = vm * a.inv_h2;
+            gp[v][1][4] = vp * a.inv_h2;
         }
 
-        // flux at this thread's two Gauss points, quadrature weight 1/4 each
+        // ---- flux at this thread's two Gauss points, quadrature weight 1/4 each
         real fa0[4] = {0, 0, 0, 0}, fa1[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int n = 0; n < 2; ++n) {
