@@ -158,6 +158,63 @@ __device__ __forceinline__ float erf_diff<float>(float a, float b) {
     return erff(a) - erff(b);
 }
 
+// Kinetic-average transcendentals: erf(aL), erf(aR), erf(aL) - erf(aR) and expm1(x).
+// FP64: library functions. FP32, when |aL|, |aR| <= 1/4: the Maclaurin series of erf through x^9
+// (truncation < 1e-9 relative) and, for the difference, (2/sqrt(pi)) d (1 - S3/3 + S5/10 - S7/42 +
+// S9/216) with d = a - b and S_k = (a^k - b^k)/(a - b) from S_k = (a + b) S_{k-1} - ab S_{k-2}, which
+// has no cancellation when a ~ b; expm1 by its series through x^5 when |x| <= 1/16.
+template <typename real>
+struct KinTrans {
+    static __device__ __forceinline__ void erfs(real aL, real aR, real& eL, real& eR, real& ed) {
+        eL = Rc<real>::erf_(aL);
+        eR = Rc<real>::erf_(aR);
+        ed = erf_diff<real>(aL, aR);
+    }
+    static __device__ __forceinline__ real expm1_(real x) { return Rc<real>::expm1_(x); }
+};
+template <>
+struct KinTrans<float> {
+    static __device__ __forceinline__ float erf_small(float x) {
+        const float x2 = x * x;
+        float p = fmaf(x2, 1.0f / 216.0f, -1.0f / 42.0f);
+        p = fmaf(x2, p, 0.1f);
+        p = fmaf(x2, p, -1.0f / 3.0f);
+        p = fmaf(x2, p, 1.0f);
+        return 1.1283791670955126f * x * p;
+    }
+    static __device__ __forceinline__ void erfs(float aL, float aR, float& eL, float& eR, float& ed) {
+        if (fabsf(aL) <= 0.25f && fabsf(aR) <= 0.25f) {
+            eL = erf_small(aL);
+            eR = erf_small(aR);
+            const float p = aL + aR, q = aL * aR;
+            float s1 = 1.0f, s2 = p;
+            float s3 = fmaf(p, s2, -q * s1);
+            float s4 = fmaf(p, s3, -q * s2);
+            float s5 = fmaf(p, s4, -q * s3);
+            float s6 = fmaf(p, s5, -q * s4);
+            float s7 = fmaf(p, s6, -q * s5);
+            float s8 = fmaf(p, s7, -q * s6);
+            float s9 = fmaf(p, s8, -q * s7);
+            const float poly = 1.0f - s3 * (1.0f / 3.0f) + s5 * 0.1f - s7 * (1.0f / 42.0f) + s9 * (1.0f / 216.0f);
+            ed = 1.1283791670955126f * (aL - aR) * poly;
+        } else {
+            eL = erff(aL);
+            eR = erff(aR);
+            ed = erf_diff<float>(aL, aR);
+        }
+    }
+    static __device__ __forceinline__ float expm1_(float x) {
+        if (fabsf(x) <= 0.0625f) {
+            float p = fmaf(x, 1.0f / 120.0f, 1.0f / 24.0f);
+            p = fmaf(x, p, 1.0f / 6.0f);
+            p = fmaf(x, p, 0.5f);
+            p = fmaf(x, p, 1.0f);
+            return x * p;
+        }
+        return expm1f(x);
+    }
+};
+
 template <typename real>
 struct FluxConst {
     real lam;      // lambda = Ma^2 / (2 U_ref^2)
@@ -178,13 +235,14 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
     real rL = k.rho_ref + qL[0], rR = k.rho_ref + qR[0];
     real uL = qL[1] * rcp<real>(rL), uR = qR[1] * rcp<real>(rR);
     real aL = k.sl * uL, aR = k.sl * uR;
-    real eaL = Rc<real>::erf_(aL), eaR = Rc<real>::erf_(aR);
+    real eaL, eaR, ead;
+    KinTrans<real>::erfs(aL, aR, eaL, eaR, ead);
     real hL = real(0.5) * (real(1) + eaL);
     real hR = real(0.5) * (real(1) - eaR);
     real eR = Rc<real>::exp_(-k.lam * uR * uR);
     real eL = Rc<real>::exp_(-k.lam * uL * uL);
-    real dE = eR * Rc<real>::expm1_(k.lam * (uR - uL) * (uR + uL));  // eL - eR
-    real rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * real(0.5) * erf_diff<real>(aL, aR);
+    real dE = eR * KinTrans<real>::expm1_(k.lam * (uR - uL) * (uR + uL));  // eL - eR
+    real rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * real(0.5) * ead;
     real m0[3];
     m0[0] = qL[1] * hL + qR[1] * hR + k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
     m0[1] = qL[2] * hL + qR[2] * hR;
