@@ -97,7 +97,7 @@ typedef struct gks_rotor {
     double cl_slope, alpha_clip;     /* synthetic polar C_L = cl_slope * clamp(alpha, +-alpha_clip) */
     double cd0, cd2;                 /* C_D = cd0 + cd2 alpha^2 (alpha in rad) */
     int32_t u_inf_correction;        /* 1: free-stream velocity correction of Section 3.1 */
-    int32_t reserved;
+    int32_t tip_correction;          /* 1: tip correction of Section 4.4, Eq. (tip-correction), on F_x and F_theta */
     const double* scale;             /* DEVICE, n_act doubles: per-point force scaling s_p; NULL = 1 */
 } gks_rotor;
 
@@ -180,6 +180,26 @@ size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
  * adj_ws: device scratch of gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
 int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0,
                 void* adj_ws, size_t adj_ws_bytes);
+
+/* Running flow statistics of the cell velocity U = (rho U)/rho (Sections 4.1, 4.2, 4.3.2). The caller
+ * provides a DEVICE buffer of gks_statistics_bytes (8-byte aligned); gks_set_statistics clears it and
+ * from then on every `interval`-th step adds a sample (mean and co-moments updated per cell in FP64).
+ * NULL disables. */
+size_t gks_statistics_bytes(const gks_config* cfg);
+int gks_set_statistics(gks_ctx* ctx, void* buffer, int32_t interval);
+
+/* Enqueue the statistics of the samples so far into DEVICE arrays (each may be NULL; interior cells,
+ * x fastest): mean [3][n] (U, V, W), rms [3][n] = sqrt(<U'^2>) etc., stress [3][n] = <U'V'>, <U'W'>,
+ * <V'W'>, tke [n] = (<U'^2> + <V'^2> + <W'^2>) / (2 u_inf^2), with n = nx*ny*nz; nsamples (host) gets
+ * the sample count. */
+int gks_read_statistics(gks_ctx* ctx, double u_inf, double* mean, double* rms, double* stress, double* tke,
+                        int64_t* nsamples);
+
+/* Per-step load history (the C_P / C_T time histories of Section 4.4.1): each step appends 10 doubles
+ * (t, dt, thrust, torque, power, C_P, C_T, IBM force x, y, z) to the DEVICE buffer until `capacity`
+ * records are written. NULL disables. gks_history_count returns the records written. */
+int gks_set_history(gks_ctx* ctx, double* buffer, int32_t capacity);
+int gks_history_count(gks_ctx* ctx, int64_t* count);
 
 /* Per-launch timing with HIP events recorded on the context's stream around each launch group.
  * Categories (index into the arrays of gks_read_timing): */

@@ -38,6 +38,11 @@ R8  Body force after the step: (rho U) += dt (G + f_ALM + F_IBM / |Omega|): the 
 R9  ALM: force on the fluid is minus the blade force; phi = atan2(U_x, omega r - U_theta); free-stream
     correction applied once with C_D at the uncorrected angle; rho in L, D is rho_ref; synthetic polar
     C_L = cl_slope * clamp(alpha, +-clip), C_D = cd0 + cd2 alpha^2 (radians).
+R12 Tip correction (Section 4.4, Eq. (tip-correction)): applied to F_x with (c1, c2) = (0.1219, 21.52)
+    and to F_theta with (0.0984, 13.026), lambda = omega R / U_inf, phi the flow angle used for the
+    forces; the exponential is capped at 1 so that sin(phi) <= 0 gives f = 0 instead of NaN.
+R13 Statistics: the printed RMS <sqrt((phi - <phi>)^2)> is read as sqrt(<(phi - <phi>)^2>); time
+    averages over samples taken after every `interval`-th step.
 R10 IBM: Peskin 4-point delta, tensor product, in both directions; fixed iteration count; stationary
     points (v_p = 0); residual reported after the last iteration.
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
@@ -60,7 +65,7 @@ __all__ = [
     "linear_point", "constants", "ghost_fill", "kinetic_average", "maxwellian_moment",
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
-    "rotor_objective", "rotor_gradient",
+    "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -504,6 +509,17 @@ def _trilinear(Q, cfg, X):
     return torch.stack(out, 0)  # [n, 3]
 
 
+def tip_factor(rotor, r, phi, c1, c2):
+    """f = (2/pi) acos(exp(-g1 N (R - r) / (2 r sin phi))), g1 = exp(-c1 (N lambda - c2)) + 0.1
+    (Section 4.4, Eq. (tip-correction)); lambda = omega R / U_inf."""
+    N = rotor.n_blades
+    tsr = rotor.omega * rotor.radius / rotor.u_inf
+    g1 = math.exp(-c1 * (N * tsr - c2)) + 0.1
+    e = torch.exp(-g1 * N * (rotor.radius - r) / (2.0 * r * torch.sin(phi)))
+    e = torch.clamp(e, max=1.0)
+    return 2.0 / math.pi * torch.acos(e)
+
+
 def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     """Sample, blade-element forces, Gaussian projection truncated at 3 eps, momentum update
     (Section 3.1, Eqs. (axial-tangential), (Gaussian); Section 3.3; reading R9).
@@ -540,6 +556,9 @@ def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     drag = 0.5 * cfg.rho_ref * chord * width * cd(alpha) * urel2
     fx = scales * (lift * torch.cos(phi) + drag * torch.sin(phi))
     ft = scales * (lift * torch.sin(phi) - drag * torch.cos(phi))
+    if getattr(rotor, "tip_correction", False):
+        fx = fx * tip_factor(rotor, r, phi, 0.1219, 21.52)
+        ft = ft * tip_factor(rotor, r, phi, 0.0984, 13.026)
     thrust = fx.sum()
     torque = (r * ft).sum()
     power = om * torque
@@ -737,3 +756,21 @@ def rotor_gradient(cfg, scales, nsteps, w, frozen=True, q0=None):
     J, _ = rotor_objective(cfg, s, nsteps, w, ctl, q0)
     J.backward()
     return float(J.detach()), s.grad.detach().clone()
+
+
+# ================================================================================================
+# flow statistics (Sections 4.1, 4.2, 4.3.2) and load histories (Section 4.4.1)
+# ================================================================================================
+
+def flow_statistics(samples, u_inf=1.0):
+    """Time statistics of the cell velocity U = (rho U)/rho over a list of fields [4, nz, ny, nx],
+    by definition (two passes): mean U-bar, fluctuation U' = U - U-bar, RMS sqrt(<U'^2>) (reading R13:
+    the square root outside the average), Reynolds stresses <U'V'>, <U'W'>, <V'W'> and
+    TKE = (<U'^2> + <V'^2> + <W'^2>) / (2 U_inf^2)."""
+    U = torch.stack([q[1:] / q[0:1] for q in samples], 0)  # [n, 3, nz, ny, nx]
+    mean = U.mean(0)
+    d = U - mean
+    var = (d * d).mean(0)
+    stress = torch.stack([(d[:, 0] * d[:, 1]).mean(0), (d[:, 0] * d[:, 2]).mean(0), (d[:, 1] * d[:, 2]).mean(0)], 0)
+    return {"mean": mean, "rms": torch.sqrt(var), "stress": stress, "tke": 0.5 * var.sum(0) / u_inf ** 2,
+            "n": len(samples)}

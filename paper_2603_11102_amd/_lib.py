@@ -48,7 +48,7 @@ class gks_rotor(C.Structure):
         ("twist", C.POINTER(C.c_double)), ("width", C.POINTER(C.c_double)),
         ("eps", C.c_double), ("cl_slope", C.c_double), ("alpha_clip", C.c_double),
         ("cd0", C.c_double), ("cd2", C.c_double),
-        ("u_inf_correction", C.c_int32), ("reserved", C.c_int32),
+        ("u_inf_correction", C.c_int32), ("tip_correction", C.c_int32),
         ("scale", C.c_void_p),
     ]
 
@@ -71,7 +71,8 @@ EXPORTS = (
     "gks_workspace_bytes", "gks_init", "gks_set_actuators", "gks_set_ibm_points", "gks_step",
     "gks_forces", "gks_reset_window", "gks_checkpoint_slot_bytes", "gks_set_checkpoints",
     "gks_adjoint_workspace_bytes", "gks_adjoint", "gks_set_timing", "gks_read_timing", "gks_destroy",
-    "gks_last_error",
+    "gks_last_error", "gks_statistics_bytes", "gks_set_statistics", "gks_read_statistics", "gks_set_history",
+    "gks_history_count",
 )
 TIMERS = ("ghost", "dt", "s1x", "s1y", "s1z", "s2x", "s2y", "s2z", "alm", "ibm", "other")
 
@@ -113,6 +114,16 @@ def load(path: str = LIB_PATH):
     lib.gks_set_timing.restype = C.c_int
     lib.gks_read_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
     lib.gks_read_timing.restype = C.c_int
+    lib.gks_statistics_bytes.argtypes = [C.POINTER(gks_config)]
+    lib.gks_statistics_bytes.restype = C.c_size_t
+    lib.gks_set_statistics.argtypes = [P, P, C.c_int32]
+    lib.gks_set_statistics.restype = C.c_int
+    lib.gks_read_statistics.argtypes = [P, C.c_double, P, P, P, P, C.POINTER(C.c_int64)]
+    lib.gks_read_statistics.restype = C.c_int
+    lib.gks_set_history.argtypes = [P, P, C.c_int32]
+    lib.gks_set_history.restype = C.c_int
+    lib.gks_history_count.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.gks_history_count.restype = C.c_int
     lib.gks_destroy.argtypes = [P]
     lib.gks_destroy.restype = None
     lib.gks_last_error.argtypes = [P]

@@ -542,7 +542,13 @@ __global__ void alm_adj_points_kernel(AlmAdjArgs A) {
     const double q = 0.5 * a.rho_ref * chord * width * U2r;
     const double L = q * cl, D = q * cd;
     const double cph = cos(phi), sph = sin(phi);
-    const double fx0 = L * cph + D * sph, ft0 = L * sph - D * cph;
+    const double X0 = L * cph + D * sph, Y0 = L * sph - D * cph;
+    double fa = 1.0, ftn = 1.0, dfa = 0.0, dft = 0.0;
+    if (a.tip) {
+        fa = tip_factor(a.g1_axi, a.nb, a.radius, rr, phi, &dfa);
+        ftn = tip_factor(a.g1_tan, a.nb, a.radius, rr, phi, &dft);
+    }
+    const double fx0 = fa * X0, ft0 = ftn * Y0;
     const double sp = a.scale ? a.scale[p] : 1.0;
     // reverse
     const double fv0 = A.pt[p], fv1 = A.pt[a.n_act + p], fv2 = A.pt[2 * a.n_act + p];
@@ -550,9 +556,10 @@ __global__ void alm_adj_points_kernel(AlmAdjArgs A) {
     const double ftb = -(fv1 * et1 + fv2 * et2) + A.w0 * A.inv_n * om * rr;
     A.grad_s[p] += fxb * fx0 + ftb * ft0;
     const double fx0b = sp * fxb, ft0b = sp * ftb;
-    const double Lb = fx0b * cph + ft0b * sph;
-    const double Db = fx0b * sph - ft0b * cph;
-    double phib = -fx0b * ft0 + ft0b * fx0;
+    const double X0b = fx0b * fa, Y0b = ft0b * ftn;
+    const double Lb = X0b * cph + Y0b * sph;
+    const double Db = X0b * sph - Y0b * cph;
+    double phib = -X0b * Y0 + Y0b * X0 + fx0b * X0 * dfa + ft0b * Y0 * dft;
     const double qb = Lb * cl + Db * cd;
     const double clb = Lb * q, cdb = Db * q;
     const double alb = clb * a.cl_slope * (inside ? 1.0 : 0.0) + cdb * 2.0 * a.cd2 * alpha;

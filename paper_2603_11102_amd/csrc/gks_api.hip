@@ -14,6 +14,7 @@
 #include "gks_adjoint.h"
 #include "gks_body.h"
 #include "gks_internal.h"
+#include "gks_stats.h"
 
 using namespace gks;
 
@@ -64,6 +65,14 @@ struct gks_ctx {
     char* ckpt;
     int ckpt_cap;
     int ckpt_n;
+    // running statistics and load history
+    double* stats_buf;
+    int stats_interval;
+    long long stats_n;
+    long long host_step;
+    double* hist_buf;
+    int hist_cap;
+    long long hist_n;
     // event timing
     int timing;
     std::vector<hipEvent_t> ev_pool;
@@ -373,7 +382,18 @@ int steps(gks_ctx* c, int nsteps) {
             tend(c, tp);
         }
         tp = tbeg(c, GKS_TIMER_OTHER);
-        HIPCHK(c, launch_finish(c->st, c->has_rotor, c->stream));
+        double* hist = (c->hist_buf && c->hist_n < c->hist_cap) ? c->hist_buf + 10 * c->hist_n : nullptr;
+        HIPCHK(c, launch_finish(c->st, c->has_rotor, hist, c->stream));
+        if (hist) c->hist_n++;
+        c->host_step++;
+        if (c->stats_buf && c->host_step % c->stats_interval == 0) {
+            StatsArgs sa;
+            sa.g = c->g;
+            sa.rho_ref = c->cfg.rho_ref;
+            sa.buf = c->stats_buf;
+            c->stats_n++;
+            HIPCHK(c, launch_stats_accum<real>(field<real>(c->q), sa, 1.0 / (double)c->stats_n, c->stream));
+        }
         tend(c, tp);
     }
     return GKS_OK;
@@ -522,6 +542,16 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
     a.nb = r->n_blades;
     a.npb = r->n_per_blade;
     a.corr = r->u_inf_correction ? 1 : 0;
+    a.tip = r->tip_correction ? 1 : 0;
+    {
+        const double tsr = r->omega * r->radius / r->u_inf;
+        a.g1_axi = std::exp(-0.1219 * (r->n_blades * tsr - 21.52)) + 0.1;   // Section 4.4 constants
+        a.g1_tan = std::exp(-0.0984 * (r->n_blades * tsr - 13.026)) + 0.1;
+    }
+    if (r->tip_correction)
+        for (int i = 0; i < r->n_per_blade; ++i)
+            if (!(r->r[i] > 0) || !(r->r[i] < r->radius))
+                return fail(c, GKS_E_INVALID_ARG, "tip correction needs 0 < r < radius for every point");
     for (int d = 0; d < 3; ++d) a.hub[d] = r->hub[d];
     a.omega = r->omega;
     a.theta0 = r->theta0;
@@ -803,6 +833,59 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
         for (int v = 0; v < 4; ++v) HIPCHK(c, launch_pad_to_int(grad_q0 + v * N, B.lam[v], 1.0, nullptr, 0.0, c->g, S));
     }
     HIPCHK(c, hipStreamSynchronize(S));
+    return GKS_OK;
+}
+
+size_t gks_statistics_bytes(const gks_config* cfg) {
+    if (!validate(cfg).empty()) return 0;
+    return 9 * sizeof(double) * (size_t)cfg->nx * cfg->ny * cfg->nz;
+}
+
+int gks_set_statistics(gks_ctx* c, void* buffer, int32_t interval) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (buffer && interval < 1) return fail(c, GKS_E_INVALID_ARG, "interval must be >= 1");
+    if (buffer && reinterpret_cast<uintptr_t>(buffer) % 8) return fail(c, GKS_E_INVALID_ARG, "statistics buffer must be 8-byte aligned");
+    c->stats_buf = static_cast<double*>(buffer);
+    c->stats_interval = buffer ? interval : 0;
+    c->stats_n = 0;
+    c->host_step = 0;
+    if (buffer) {
+        StatsArgs sa;
+        sa.g = c->g;
+        sa.rho_ref = c->cfg.rho_ref;
+        sa.buf = c->stats_buf;
+        HIPCHK(c, launch_stats_zero(sa, c->stream));
+    }
+    return GKS_OK;
+}
+
+int gks_read_statistics(gks_ctx* c, double u_inf, double* mean, double* rms, double* stress, double* tke,
+                        int64_t* nsamples) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (!c->stats_buf) return fail(c, GKS_E_STATE, "statistics are not enabled (gks_set_statistics)");
+    if (!(u_inf > 0)) return fail(c, GKS_E_INVALID_ARG, "u_inf must be > 0");
+    if (nsamples) *nsamples = c->stats_n;
+    if (c->stats_n == 0) return fail(c, GKS_E_STATE, "no samples yet");
+    StatsArgs sa;
+    sa.g = c->g;
+    sa.rho_ref = c->cfg.rho_ref;
+    sa.buf = c->stats_buf;
+    HIPCHK(c, launch_stats_final(sa, 1.0 / (double)c->stats_n, 1.0 / (u_inf * u_inf), mean, rms, stress, tke, c->stream));
+    return GKS_OK;
+}
+
+int gks_set_history(gks_ctx* c, double* buffer, int32_t capacity) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (buffer && capacity < 1) return fail(c, GKS_E_INVALID_ARG, "capacity must be >= 1");
+    c->hist_buf = buffer;
+    c->hist_cap = buffer ? capacity : 0;
+    c->hist_n = 0;
+    return GKS_OK;
+}
+
+int gks_history_count(gks_ctx* c, int64_t* count) {
+    if (!c || !count) return GKS_E_INVALID_ARG;
+    *count = c->hist_n;
     return GKS_OK;
 }
 

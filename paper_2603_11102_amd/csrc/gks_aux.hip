@@ -142,7 +142,7 @@ hipError_t launch_dt(DevState* st, double cfl, double hmin, double c, double dt_
     return hipGetLastError();
 }
 
-__global__ void finish_kernel(DevState* st, int has_rotor) {
+__global__ void finish_kernel(DevState* st, int has_rotor, double* hist) {
     if (threadIdx.x != 0) return;
     st->t = st->t_next;
     st->step += 1;
@@ -151,10 +151,24 @@ __global__ void finish_kernel(DevState* st, int has_rotor) {
         st->win_t += st->thrust;
     }
     st->win_n += 1;
+    if (hist) {
+        double h[10];
+        h[0] = st->t;
+        h[1] = st->dt;
+        h[2] = st->thrust;
+        h[3] = st->torque;
+        h[4] = st->power;
+        h[5] = st->cp;
+        h[6] = st->ct;
+        h[7] = st->ibm_force[0];
+        h[8] = st->ibm_force[1];
+        h[9] = st->ibm_force[2];
+        for (int i = 0; i < 10; ++i) hist[i] = h[i];
+    }
 }
 
-hipError_t launch_finish(DevState* st, int has_rotor, hipStream_t s) {
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, st, has_rotor);
+hipError_t launch_finish(DevState* st, int has_rotor, double* hist, hipStream_t s) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, st, has_rotor, hist);
     return hipGetLastError();
 }
 

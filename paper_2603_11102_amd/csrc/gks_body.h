@@ -7,6 +7,8 @@ namespace gks {
 
 struct AlmArgs {
     int n_act, nb, npb, corr;
+    int tip;               // tip correction on (Section 4.4)
+    double g1_axi, g1_tan; // g1 = exp(-c1 (N lambda - c2)) + 0.1 for the axial and tangential factors
     double hub[3];
     double omega, theta0, radius, u_inf, eps, cl_slope, alpha_clip, cd0, cd2, rho_ref, area;
     const double* r;      // device, npb
@@ -40,6 +42,19 @@ struct IbmArgs {
     GridDesc g;
     DevState* st;
 };
+
+// Tip-correction factor f = (2/pi) acos(min(1, exp(-g1 N (R - r) / (2 r sin phi)))) and df/dphi.
+__device__ __forceinline__ double tip_factor(double g1, int N, double R, double r, double phi, double* dfdphi) {
+    const double sp = sin(phi);
+    const double K = g1 * N * (R - r) / (2.0 * r);
+    const double E = exp(-K / sp);
+    if (!(E < 1.0)) {
+        if (dfdphi) *dfdphi = 0.0;
+        return 0.0;
+    }
+    if (dfdphi) *dfdphi = -(2.0 / M_PI) * E * K * cos(phi) / (sp * sp * sqrt(1.0 - E * E));
+    return (2.0 / M_PI) * acos(E);
+}
 
 template <typename real>
 hipError_t launch_alm(Field4<real> f, const AlmArgs& a, hipStream_t s);

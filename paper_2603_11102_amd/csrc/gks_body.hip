@@ -89,6 +89,10 @@ __global__ void __launch_bounds__(1024) alm_points_kernel(Field4<real> f, AlmArg
         const double cph = cos(phi), sph = sin(phi);
         fx = s * (lift * cph + drag * sph);
         ft = s * (lift * sph - drag * cph);
+        if (a.tip) {
+            fx *= tip_factor(a.g1_axi, a.nb, a.radius, rr, phi, nullptr);
+            ft *= tip_factor(a.g1_tan, a.nb, a.radius, rr, phi, nullptr);
+        }
         // force on the fluid: minus the blade force
         a.X[3 * p + 0] = X[0];
         a.X[3 * p + 1] = X[1];

@@ -54,16 +54,18 @@ template <> __device__ __forceinline__ double rcp<double>(double x) {
 template <typename real>
 __device__ __forceinline__ void js_weights(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                            real& P0, real& P1, real& P2) {
-    const real c13 = real(13.0 / 12.0);
+    // 4 beta_k = (13/3) a^2 + b^2; with eps scaled by 4 as well every (eps + beta_k)^2 gains the same
+    // factor 16, which cancels in the normalised weights.
+    const real c133 = real(13.0 / 3.0);
+    const real e4 = real(4) * eps;
     real a = qm2 - real(2) * qm1 + q0, b = qm2 - real(4) * qm1 + real(3) * q0;
-    real b0 = c13 * a * a + real(0.25) * b * b;
+    real e0 = e4 + c133 * a * a + b * b;
     a = qm1 - real(2) * q0 + qp1;
     b = qm1 - qp1;
-    real b1 = c13 * a * a + real(0.25) * b * b;
+    real e1 = e4 + c133 * a * a + b * b;
     a = q0 - real(2) * qp1 + qp2;
     b = real(3) * q0 - real(4) * qp1 + qp2;
-    real b2 = c13 * a * a + real(0.25) * b * b;
-    real e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+    real e2 = e4 + c133 * a * a + b * b;
     e0 *= e0;
     e1 *= e1;
     e2 *= e2;
@@ -101,10 +103,10 @@ __device__ __forceinline__ void weno_gauss(real qm2, real qm1, real q0, real qp1
                                            real& vm, real& vp) {
     real P0, P1, P2;
     js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
-    const real r3 = real(GKS_SQRT3);
-    real d0 = r3 * (real(1.0 / 12.0) * qm2 - real(1.0 / 3.0) * qm1 + real(0.25) * q0);
-    real d1 = r3 * real(1.0 / 12.0) * (qp1 - qm1);
-    real d2 = r3 * (-real(0.25) * q0 + real(1.0 / 3.0) * qp1 - real(1.0 / 12.0) * qp2);
+    const real r12 = real(GKS_SQRT3 / 12.0), r3 = real(GKS_SQRT3 / 3.0), r4 = real(GKS_SQRT3 / 4.0);
+    real d0 = r12 * qm2 - r3 * qm1 + r4 * q0;
+    real d1 = r12 * (qp1 - qm1);
+    real d2 = -r4 * q0 + r3 * qp1 - r12 * qp2;
     const real gc = real(7.0 / 36.0), gd = real(GKS_SQRT3 / 1080.0), g1 = real(11.0 / 18.0);
     // s = +1
     real a0 = (gc - gd) * P0, a1 = g1 * P1, a2 = (gc + gd) * P2;

@@ -80,7 +80,7 @@ hipError_t launch_ghost(Field4<real> f, const GridDesc& g, int axis, int bc_lo, 
 template <typename real>
 hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, unsigned long long* out_bits, hipStream_t s);
 hipError_t launch_dt(DevState* st, double cfl, double hmin, double c, double dt_fixed, hipStream_t s);
-hipError_t launch_finish(DevState* st, int has_rotor, hipStream_t s);
+hipError_t launch_finish(DevState* st, int has_rotor, double* hist, hipStream_t s);
 hipError_t launch_window_reset(DevState* st, hipStream_t s);
 template <typename real>
 hipError_t launch_diag(Field4<real> f, const GridDesc& g, double rho_ref, double* partials, int nblk, DevState* st,

@@ -123,6 +123,7 @@ class GksSolver:
         r.eps, r.cl_slope, r.alpha_clip = rotor.eps, rotor.cl_slope, rotor.alpha_clip
         r.cd0, r.cd2 = rotor.cd0, rotor.cd2
         r.u_inf_correction = 1 if rotor.u_inf_correction else 0
+        r.tip_correction = 1 if getattr(rotor, "tip_correction", False) else 0
         r.scale = C.c_void_p(_ptr(self.scale))
         L.check(self.lib, self.ctx, self.lib.gks_set_actuators(self.ctx, C.byref(r)))
         self.n_act = n_act
@@ -167,6 +168,36 @@ class GksSolver:
         cnt = (C.c_int64 * n)()
         L.check(self.lib, self.ctx, self.lib.gks_read_timing(self.ctx, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(L.TIMERS)}
+
+    # ------------------------------------------------------------------ statistics and histories
+    def enable_statistics(self, interval: int = 1):
+        nbytes = self.lib.gks_statistics_bytes(C.byref(self.c_cfg))
+        self._stats = torch.empty(nbytes // 8, dtype=torch.float64, device=self.device)
+        L.check(self.lib, self.ctx, self.lib.gks_set_statistics(self.ctx, C.c_void_p(self._stats.data_ptr()), int(interval)))
+
+    def statistics(self, u_inf: float = 1.0) -> dict:
+        """Mean [3, nz, ny, nx], rms [3, ...], stress (<U'V'>, <U'W'>, <V'W'>) [3, ...], tke [...] on the device."""
+        shp = (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+        out = {k: torch.empty((3,) + shp, dtype=torch.float64, device=self.device) for k in ("mean", "rms", "stress")}
+        out["tke"] = torch.empty(shp, dtype=torch.float64, device=self.device)
+        n = C.c_int64()
+        L.check(self.lib, self.ctx, self.lib.gks_read_statistics(
+            self.ctx, float(u_inf), *(C.c_void_p(out[k].data_ptr()) for k in ("mean", "rms", "stress", "tke")),
+            C.byref(n)))
+        torch.cuda.synchronize(self.device)
+        out["n"] = n.value
+        return out
+
+    def enable_history(self, capacity: int):
+        self._hist = torch.zeros((capacity, 10), dtype=torch.float64, device=self.device)
+        L.check(self.lib, self.ctx, self.lib.gks_set_history(self.ctx, C.c_void_p(self._hist.data_ptr()), int(capacity)))
+
+    def history(self) -> torch.Tensor:
+        """Records (t, dt, thrust, torque, power, C_P, C_T, IBM force x, y, z) of the steps so far."""
+        n = C.c_int64()
+        L.check(self.lib, self.ctx, self.lib.gks_history_count(self.ctx, C.byref(n)))
+        torch.cuda.synchronize(self.device)
+        return self._hist[: n.value].cpu()
 
     # ------------------------------------------------------------------ adjoint
     def set_checkpoints(self, capacity: int):

@@ -49,6 +49,7 @@ class RotorSpec:
     cd0: float = 0.01
     cd2: float = 0.02
     u_inf_correction: bool = True
+    tip_correction: bool = False        # Shen tip correction of the NTNU case (Section 4.4)
     scale: Optional[np.ndarray] = None  # per actuator point, n_blades * n_per_blade
 
     @property

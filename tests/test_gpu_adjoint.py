@@ -28,8 +28,11 @@ def _gpu_window(cfg, scales, nsteps, w=W, want_field=False, q0=None):
     return s, J, sc
 
 
-def test_adjoint_matches_oracle_reference():
+@pytest.mark.parametrize("tip", [False, True])
+def test_adjoint_matches_oracle_reference(tip):
+    from dataclasses import replace
     cfg = make_case("adjoint", grid=(20, 20, 20))
+    cfg = cfg.with_(rotor=replace(cfg.rotor, tip_correction=tip))
     n = cfg.rotor.n_act
     rng = np.random.default_rng(0)
     s0 = 1.0 + 0.1 * rng.standard_normal(n)

@@ -110,10 +110,12 @@ def test_bitwise_run_to_run(precision):
     assert oa[-1]["power"] == ob[-1]["power"] and oa[-1]["thrust"] == ob[-1]["thrust"]
 
 
-def test_alm_fp64_vs_oracle():
+@pytest.mark.parametrize("tip", [False, True])
+def test_alm_fp64_vs_oracle(tip):
+    from dataclasses import replace
     cfg = make_case("alm", grid=(48, 24, 24))
-    cfg = cfg.with_(q0=_perturbed_stream(cfg, seed=3, amp=0.02))
-    print_case("alm-fp64", grid=(48, 24, 24))
+    cfg = cfg.with_(q0=_perturbed_stream(cfg, seed=3, amp=0.02), rotor=replace(cfg.rotor, tip_correction=tip))
+    print_case("alm-fp64", grid=(48, 24, 24), tip=tip)
     s, gouts = run_gpu(cfg, "fp64", 2)
     o, oouts = run_oracle(cfg, 2)
     err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))

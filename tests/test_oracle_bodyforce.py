@@ -161,3 +161,39 @@ def test_oracle_step_with_rotor_and_body_runs():
     assert math.isfinite(float(out["alm"]["power"]))
     assert float(out["ibm"]["residual"]) >= 0
     assert torch.isfinite(o.Q).all()
+
+
+def test_tip_correction_factor():
+    # Section 4.4, Eq. (tip-correction): printed constants, f -> 0 at the tip, f -> 1 inboard, f in [0, 1]
+    from oracle import tip_factor
+    cfg, Q = _uniform_alm_case()
+    rot = cfg.rotor
+    ax = GOLD["tip_correction_axial_c1_c2"]["value"]
+    tg = GOLD["tip_correction_tangential_c1_c2"]["value"]
+    assert ax == [0.1219, 21.52] and tg == [0.0984, 13.026]
+    phi = torch.tensor(0.15, dtype=F64)
+    rr = torch.tensor(np.linspace(0.05, 0.5, 200) * rot.radius / 0.5, dtype=F64)
+    for c1, c2 in (ax, tg):
+        f = tip_factor(rot, rr, phi, c1, c2)
+        assert float(f[-1]) == 0.0
+        assert float(f.min()) >= 0.0 and float(f.max()) <= 1.0
+        assert torch.all(f[1:] <= f[:-1] + 1e-15)
+        # by hand at r = 0.8 R
+        N, lam = rot.n_blades, rot.omega * rot.radius / rot.u_inf
+        g1 = math.exp(-c1 * (N * lam - c2)) + 0.1
+        r8 = 0.8 * rot.radius
+        ref = 2 / math.pi * math.acos(math.exp(-g1 * N * (rot.radius - r8) / (2 * r8 * math.sin(0.15))))
+        got = float(tip_factor(rot, torch.tensor(r8, dtype=F64), phi, c1, c2))
+        assert abs(got - ref) < 1e-14
+
+
+def test_tip_correction_reduces_tip_loads():
+    cfg, Q = _uniform_alm_case()
+    rot = cfg.rotor
+    from dataclasses import replace
+    _, a = alm_apply(Q, 0.0, 0.0, cfg, rot)
+    _, b = alm_apply(Q, 0.0, 0.0, cfg, replace(rot, tip_correction=True))
+    assert float(b["thrust"]) < float(a["thrust"]) and float(b["power"]) < float(a["power"])
+    n = rot.n_per_blade
+    assert float(b["fx"][n - 1]) < 0.5 * float(a["fx"][n - 1])
+    assert abs(float(b["fx"][0]) / float(a["fx"][0]) - 1.0) < 1e-3

@@ -164,3 +164,28 @@ def test_taylor_green_initial_dissipation():
     rate = (energy(o.Q) - e0) / cfg.dt_fixed
     expect = -6.0 * nu * e0
     assert abs(rate / expect - 1.0) < 0.02, (rate, expect)
+
+
+def test_flow_statistics_definitions():
+    from oracle import flow_statistics
+    rng = np.random.default_rng(0)
+    base = np.zeros((4, 3, 4, 5))
+    base[0] = 1.0
+    # constant field: zero fluctuations
+    s = flow_statistics([torch.tensor(base + 0.0) for _ in range(4)])
+    assert float(s["rms"].abs().max()) == 0.0 and float(s["tke"].abs().max()) == 0.0
+    # two states U = 1 +- a (rho = 2): mean 1, rms a, TKE a^2/2, zero shear stress
+    a = 0.3
+    q1, q2 = base.copy(), base.copy()
+    q1[0] = q2[0] = 2.0
+    q1[1] = 2.0 * (1 + a)
+    q2[1] = 2.0 * (1 - a)
+    s = flow_statistics([torch.tensor(q1), torch.tensor(q2)], u_inf=1.0)
+    assert torch.allclose(s["mean"][0], torch.tensor(1.0, dtype=torch.float64))
+    assert torch.allclose(s["rms"][0], torch.tensor(a, dtype=torch.float64))
+    assert torch.allclose(s["tke"], torch.tensor(0.5 * a * a, dtype=torch.float64))
+    # correlated U, V: <U'V'> = a b
+    q1[2] = 2.0 * 0.5
+    q2[2] = -2.0 * 0.5
+    s = flow_statistics([torch.tensor(q1), torch.tensor(q2)])
+    assert torch.allclose(s["stress"][0], torch.tensor(a * 0.5, dtype=torch.float64))
