@@ -48,6 +48,8 @@ struct gks_ctx {
     DevState* st;
     void* r0[4];
     void* r1[4];
+    void* rx0[4];
+    void* rx1[4];
     double* diag_partials;
     int diag_nblk;
     double lam, c, hmin, eps;
@@ -108,6 +110,8 @@ struct Layout {
     DevState* st;
     void* r0[4];
     void* r1[4];
+    void* rx0[4];
+    void* rx1[4];
     double* diag;
     char* alm;
     char* ibm;
@@ -146,6 +150,9 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     L->st = cv.ptr<DevState>(sizeof(DevState));
     for (int v = 0; v < 4; ++v) L->r0[v] = cv.ptr<void>(N * es);
     for (int v = 0; v < 4; ++v) L->r1[v] = cv.ptr<void>(N * es);
+    const size_t NB = (size_t)c->nx * ((c->ny + 15) / 16) * 16 * c->nz;
+    for (int v = 0; v < 4; ++v) L->rx0[v] = cv.ptr<void>(NB * es);
+    for (int v = 0; v < 4; ++v) L->rx1[v] = cv.ptr<void>(NB * es);
     L->diag = cv.ptr<double>(sizeof(double) * 4 * 1024);
     size_t ab = alm_block_bytes(c->max_act);
     L->alm = ab ? cv.ptr<char>(ab) : nullptr;
@@ -206,6 +213,8 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
         a.q[v] = static_cast<const real*>(src[gv]);
         a.r0[v] = static_cast<real*>(c->r0[gv]);
         a.r1[v] = static_cast<real*>(c->r1[gv]);
+        a.rx0[v] = static_cast<real*>(c->rx0[gv]);
+        a.rx1[v] = static_cast<real*>(c->rx1[gv]);
         a.out_a[v] = static_cast<real*>(out_a[gv]);
         if (stage == 1) {
             a.out_b[v] = static_cast<real*>(out_b[gv]);
@@ -239,7 +248,13 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.fc.rho_ref = real(c->cfg.rho_ref);
     for (int j = 0; j < 3; ++j) a.g_local[j] = real(c->cfg.body_force[pm[1 + j] - 1]);
     a.dt_ptr = &c->st->dt;
-    a.mode = d == 0 ? 0 : (d == 1 ? 1 : 2);
+    // x faces write their own arrays in the blocked layout [z][y/16][x][y%16] so that the x pass
+    // stores contiguous runs; the y pass writes the main arrays, the z pass accumulates both and
+    // applies the S2O4 combination
+    a.rx_kind = d == 0 ? 1 : (d == 2 ? 2 : 0);
+    a.rx_nx = c->cfg.nx;
+    a.rx_nyb = (c->cfg.ny + 15) / 16;
+    a.mode = d == 0 ? 3 : (d == 1 ? 0 : 4);
     return a;
 }
 
@@ -456,6 +471,8 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     for (int v = 0; v < 4; ++v) {
         c->r0[v] = L.r0[v];
         c->r1[v] = L.r1[v];
+        c->rx0[v] = L.rx0[v];
+        c->rx1[v] = L.rx1[v];
     }
     c->diag_partials = L.diag;
     c->alm_mem = reinterpret_cast<double*>(L.alm);

@@ -20,6 +20,10 @@ struct FaceArgs {
     const real* q[4];        // reconstructed field (padded layout)
     real* r0[4];             // accumulator of L (interior layout), stage 1
     real* r1[4];             // accumulator of L_t (interior layout)
+    real* rx0[4];            // x-direction contributions of L in the blocked layout [z][y/16][x][y%16]
+    real* rx1[4];            // x-direction contributions of L_t, same layout
+    int rx_kind;             // 1: x faces (n, t1, t2) = (x, y, z); 2: z faces (n, t1, t2) = (z, x, y)
+    int rx_nx, rx_nyb;       // nx and ceil(ny / 16) of the blocked layout
     real* out_a[4];          // epilogue: stage 1 -> Q*, stage 2 -> Q^{n+1} (padded)
     real* out_b[4];          // epilogue: stage 1 -> S (padded)
     const real* s_in[4];     // epilogue: stage 2 reads S (padded)
@@ -34,8 +38,15 @@ struct FaceArgs {
     FluxConst<real> fc;
     real g_local[3];                  // constant body force in local momentum order (stage 2 epilogue)
     const double* dt_ptr;             // device dt of the current step
-    int mode;                         // 0: write, 1: accumulate, 2: accumulate + S2O4 epilogue
+    int mode;  // 0: write, 1: accumulate, 2: accumulate + S2O4 epilogue,
+               // 3: write the transposed x-direction arrays, 4: accumulate + add them + epilogue
 };
+
+// Index of cell (x, y, z) in the blocked layout [z][y/16][x][y%16]: the x pass stores 16 consecutive y
+// per row (its lanes run along y), the z pass reads a 16 x 16 (x, y) tile as one contiguous block.
+__host__ __device__ inline long long rx_block_index(int x, int y, int z, int nx, int nyb) {
+    return (((long long)z * nyb + (y >> 4)) * nx + x) * 16 + (y & 15);
+}
 
 // Device-resident scalars of a context (lives in the workspace).
 struct DevState {

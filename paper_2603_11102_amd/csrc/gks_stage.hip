@@ -202,6 +202,18 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                 const int v = 2 * m + vv;  // lane m writes variables 2m, 2m+1
                 real d1 = -(fa1[v] - fprev1[v]) * a.inv_hn;
                 real d0 = NEED_F0 ? -(fa0[v] - fprev0[v]) * a.inv_hn : real(0);
+                if (a.mode >= 3) {
+                    const long long xidx =
+                        a.rx_kind == 1 ? rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb)
+                                       : rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+                    if (a.mode == 3) {
+                        a.rx1[v][xidx] = d1;
+                        if (NEED_F0) a.rx0[v][xidx] = d0;
+                        continue;
+                    }
+                    d1 += a.rx1[v][xidx];
+                    if (NEED_F0) d0 += a.rx0[v][xidx];
+                }
                 if (a.mode == 0) {
                     a.r1[v][ridx] = d1;
                     if (NEED_F0) a.r0[v][ridx] = d0;
