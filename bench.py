@@ -31,6 +31,29 @@ FLOP_PER_CELL_STEP = 3 * (FLOP_STAGE1_PER_CELL_DIR + FLOP_STAGE2_PER_CELL_DIR) +
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per stage-1 face-kernel launch (mean over the x, y, z launches) of the FP32 channel workload,
+# from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+# "bench.py --steps 2 --warmup 1 --no-fp64 --no-cpu-baseline", each scaled by what the same counter reads
+# for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024": FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
+# The figure belongs to the kernel sources it was measured on; bench reports null once they differ.
+TRAFFIC = {"sources_sha256": None, "fetch_bytes": None, "write_bytes": None}
+KERNEL_SOURCES = ("gks_stage.hip", "gks_device.h", "gks_internal.h")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_11102_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(case, precision):
+    if case != "channel" or precision != "fp32" or TRAFFIC["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
 
 def _time_steps(s, steps):
     import torch
@@ -51,6 +74,7 @@ def run_gpu(cfg, precision, steps, warmup):
     s.step(warmup)
     torch.cuda.synchronize()
     ms = _time_steps(s, steps)
+    torch.cuda.synchronize()
     s.set_timing(True)
     ms_t = _time_steps(s, steps)
     timing = s.read_timing()
@@ -64,15 +88,17 @@ def cpu_baseline(cfg, planes):
     initial field, periodic in z (same spacing, same physics)."""
     import torch
     from oracle import Oracle
-    sub = cfg.with_(nz=planes, lz=cfg.dz * planes, q0=cfg.q0[:, :planes].copy())
+    sub = cfg if planes >= cfg.nz else cfg.with_(nz=planes, lz=cfg.dz * planes, q0=cfg.q0[:, :planes].copy())
     o = Oracle(sub)
     t0 = time.perf_counter()
     o.step()
     dt = time.perf_counter() - t0
     return {"value": sub.n_cells / dt, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"1 S2O4 step of the FP64 oracle on {sub.nx}x{sub.ny}x{sub.nz} cells (first {planes} "
-                      f"z-planes of the same field, periodic in z), {dt:.1f} s"}
+            "sample": (f"1 S2O4 step of the FP64 oracle on the whole {sub.nx}x{sub.ny}x{sub.nz} field, {dt:.1f} s"
+                       if sub is cfg else
+                       f"1 S2O4 step of the FP64 oracle on {sub.nx}x{sub.ny}x{sub.nz} cells (first {planes} "
+                       f"z-planes of the same field, periodic in z), {dt:.1f} s")}
 
 
 def main():
@@ -84,7 +110,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-planes", type=int, default=8)
+    ap.add_argument("--cpu-planes", type=int, default=96,
+                    help="z-planes of the field the CPU oracle steps once (all of them by default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -139,7 +166,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'},1> "
                                                 "(stage 1, mean over the x, y, z launches)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "avg_launch_ms": avg_launch_ms,
+                     "traffic": measured_traffic(args.case, args.precision), "avg_launch_ms": avg_launch_ms,
                      "algorithmic_flop_per_launch": flops_launch},
         "per_category_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
         "flop_per_cell_step": FLOP_PER_CELL_STEP,

@@ -496,10 +496,12 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     c->eps = c->cfg.weno_eps;
     c->diag_nblk = diag_blocks(c->g);
     c->flags = cfg->ma > 0.3 ? GKS_WARN_MACH : 0;
+    const int slots = cfg->precision == GKS_FP32 ? face_slots<float>() : face_slots<double>();
     for (int d = 0; d < 3; ++d) {
         const int* ax = kAxes[d];
         const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + TILE2 - 1) / TILE2);
-        c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles) : face_chunk<double>(n[ax[0]], tiles);
+        c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles, slots)
+                                                 : face_chunk<double>(n[ax[0]], tiles, slots);
     }
     hipError_t e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
     if (e != hipSuccess) {

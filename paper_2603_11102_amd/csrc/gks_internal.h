@@ -82,7 +82,9 @@ struct Field4 {
 template <typename real>
 hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s);
 template <typename real>
-int face_chunk(int n_n, int tiles);
+int face_chunk(int n_n, int tiles, int slots);
+template <typename real>
+int face_slots();
 
 // host launchers (gks_aux.hip)
 template <typename real>

@@ -244,14 +244,34 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
 }
 
 template <typename real>
-int face_chunk(int n_n, int tiles) {
-    // enough workgroups to fill 256 CUs several times over, chunks of at least 8 faces
-    int want = 2048;
-    int nchunks = (want + tiles - 1) / tiles;
-    int chunk = (n_n + nchunks - 1) / nchunks;
-    if (chunk < 8) chunk = 8;
-    if (chunk > n_n) chunk = n_n;
-    return chunk;
+int face_slots() {
+    // workgroups of the face kernel that the device holds at once
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1>, FACE_THREADS, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+template <typename real>
+int face_chunk(int n_n, int tiles, int slots) {
+    // Workgroups of one launch run in rounds of `slots`; a workgroup costs about (chunk + 4) face steps
+    // (the column phase primes four planes before the first face). Pick the chunk that minimises
+    // rounds x (chunk + 4); ties go to the longer chunk.
+    if (slots <= 0) slots = 512;
+    int best_chunk = n_n;
+    long long best = -1;
+    for (int nc = 1; nc <= n_n; ++nc) {
+        const int chunk = (n_n + nc - 1) / nc;
+        const long long wgs = (long long)tiles * ((n_n + chunk - 1) / chunk);
+        const long long cost = ((wgs + slots - 1) / slots) * (chunk + 4);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_chunk = chunk;
+        }
+    }
+    return best_chunk;
 }
 
 template <typename real>
@@ -268,7 +288,9 @@ hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
 
 template hipError_t launch_face<float>(const FaceArgs<float>&, int, hipStream_t);
 template hipError_t launch_face<double>(const FaceArgs<double>&, int, hipStream_t);
-template int face_chunk<float>(int, int);
-template int face_chunk<double>(int, int);
+template int face_chunk<float>(int, int, int);
+template int face_chunk<double>(int, int, int);
+template int face_slots<float>();
+template int face_slots<double>();
 
 }  // namespace gks
