@@ -52,6 +52,7 @@ struct gks_ctx {
     void* rx1[4];
     double* diag_partials;
     int diag_nblk;
+    double* umax_part;  // per-workgroup maxima of |U|^2 for the CFL time step
     double lam, c, hmin, eps;
     int chunk[3];
     int flags;
@@ -113,6 +114,7 @@ struct Layout {
     void* rx0[4];
     void* rx1[4];
     double* diag;
+    double* umax_part;
     char* alm;
     char* ibm;
     size_t total;
@@ -154,6 +156,7 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     for (int v = 0; v < 4; ++v) L->rx0[v] = cv.ptr<void>(NB * es);
     for (int v = 0; v < 4; ++v) L->rx1[v] = cv.ptr<void>(NB * es);
     L->diag = cv.ptr<double>(sizeof(double) * 4 * 1024);
+    L->umax_part = cv.ptr<double>(sizeof(double) * UMAX_BLOCKS);
     size_t ab = alm_block_bytes(c->max_act);
     L->alm = ab ? cv.ptr<char>(ab) : nullptr;
     size_t ib = ibm_block_bytes(c->max_ibm);
@@ -369,8 +372,9 @@ int steps(gks_ctx* c, int nsteps) {
         tend(c, tp);
         if (rc) return rc;
         tp = tbeg(c, GKS_TIMER_DT);
-        if (c->cfg.cfl > 0) HIPCHK(c, launch_umax<real>(field<real>(c->q), c->g, c->cfg.rho_ref, &c->st->umax2_bits, c->stream));
-        HIPCHK(c, launch_dt(c->st, c->cfg.cfl, c->hmin, c->c, c->cfg.dt_fixed, c->stream));
+        if (c->cfg.cfl > 0) HIPCHK(c, launch_umax<real>(field<real>(c->q), c->g, c->cfg.rho_ref, c->umax_part, c->stream));
+        HIPCHK(c, launch_dt(c->st, c->umax_part, umax_blocks(c->g), c->cfg.cfl, c->hmin, c->c, c->cfg.dt_fixed,
+                            c->stream));
         tend(c, tp);
         for (int d = 0; d < 3; ++d) {
             tp = tbeg(c, cat1[d]);
@@ -475,6 +479,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         c->rx1[v] = L.rx1[v];
     }
     c->diag_partials = L.diag;
+    c->umax_part = L.umax_part;
     c->alm_mem = reinterpret_cast<double*>(L.alm);
     c->ibm_mem = L.ibm;
     const int n[3] = {cfg->nx, cfg->ny, cfg->nz};
@@ -799,7 +804,7 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
         const char* src = c->ckpt + (size_t)n * slot;
         for (int v = 0; v < 4; ++v) HIPCHK(c, launch_copy_field(src + v * fb, B.qwork[v], (size_t)np * 8, S));
         HIPCHK(c, launch_copy_field(src + slot - 256, &c->st->t, sizeof(double), S));
-        HIPCHK(c, launch_dt(c->st, 0.0, c->hmin, c->c, dt, S));
+        HIPCHK(c, launch_dt(c->st, nullptr, 0, 0.0, c->hmin, c->c, dt, S));
         int rc = ghost_all<double>(c, qwork);
         if (rc) return rc;
         for (int d = 0; d < 3; ++d)

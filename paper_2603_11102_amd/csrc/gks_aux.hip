@@ -88,17 +88,16 @@ hipError_t launch_ghost(Field4<real> f, const GridDesc& gd, int axis, int bc_lo,
 // deterministic)
 // ------------------------------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(256) umax_kernel(Field4<real> f, GridDesc g, double rho_ref,
-                                                   unsigned long long* out) {
+__global__ void __launch_bounds__(256) umax_kernel(Field4<real> f, GridDesc g, double rho_ref, double* part) {
+    // per-workgroup maximum of |U|^2 over the interior cells; dt_kernel reduces the partial maxima
     __shared__ double red[256];
-    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    const unsigned n = (unsigned)g.n[0] * (unsigned)g.n[1] * (unsigned)g.n[2];
+    const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
     double mx = 0.0;
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(c % g.n[0]);
-        const long long r = c / g.n[0];
-        const int j = (int)(r % g.n[1]);
-        const int k = (int)(r / g.n[1]);
-        const long long p = g.pad0 + i * g.st[0] + j * g.st[1] + (long long)k * g.st[2];
+    for (unsigned c = blockIdx.x * 256u + threadIdx.x; c < n; c += gridDim.x * 256u) {
+        const unsigned i = c % nx, r = c / nx;
+        const unsigned j = r % ny, k = r / ny;
+        const long long p = g.pad0 + i + (long long)j * g.st[1] + (long long)k * g.st[2];
         const double rho = rho_ref + (double)f.v[0][p];
         const double u = (double)f.v[1][p] / rho, v = (double)f.v[2][p] / rho, w = (double)f.v[3][p] / rho;
         const double s2 = u * u + v * v + w * w;
@@ -110,35 +109,49 @@ __global__ void __launch_bounds__(256) umax_kernel(Field4<real> f, GridDesc g, d
         if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+int umax_blocks(const GridDesc& g) {
+    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
+    long long blocks = (n + 255) / 256;
+    return (int)(blocks > UMAX_BLOCKS ? UMAX_BLOCKS : blocks);
 }
 
 template <typename real>
-hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, unsigned long long* out, hipStream_t s) {
-    const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
-    long long blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((umax_kernel<real>), dim3((unsigned)blocks), dim3(256), 0, s, f, g, rho_ref, out);
+hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, double* part, hipStream_t s) {
+    hipLaunchKernelGGL((umax_kernel<real>), dim3((unsigned)umax_blocks(g)), dim3(256), 0, s, f, g, rho_ref, part);
     return hipGetLastError();
 }
 
-__global__ void dt_kernel(DevState* st, double cfl, double hmin, double c, double dt_fixed) {
+__global__ void __launch_bounds__(256) dt_kernel(DevState* st, const double* part, int nparts, double cfl,
+                                                 double hmin, double c, double dt_fixed) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) mx = fmax(mx, part[i]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
     if (threadIdx.x != 0) return;
     double dt;
     if (cfl > 0.0) {
-        const double u = sqrt(__longlong_as_double((long long)st->umax2_bits));
+        const double u = sqrt(red[0]);
         dt = cfl * hmin / (u + c);
     } else {
         dt = dt_fixed;
     }
     st->dt = dt;
     st->t_next = st->t + dt;
-    st->umax2_bits = 0ULL;
     st->ibm_res_bits = 0ULL;
 }
 
-hipError_t launch_dt(DevState* st, double cfl, double hmin, double c, double dt_fixed, hipStream_t s) {
-    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(64), 0, s, st, cfl, hmin, c, dt_fixed);
+hipError_t launch_dt(DevState* st, const double* part, int nparts, double cfl, double hmin, double c,
+                     double dt_fixed, hipStream_t s) {
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, s, st, part, cfl > 0.0 ? nparts : 0, cfl, hmin, c,
+                       dt_fixed);
     return hipGetLastError();
 }
 
@@ -278,8 +291,8 @@ hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream
 
 template hipError_t launch_ghost<float>(Field4<float>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
 template hipError_t launch_ghost<double>(Field4<double>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
-template hipError_t launch_umax<float>(Field4<float>, const GridDesc&, double, unsigned long long*, hipStream_t);
-template hipError_t launch_umax<double>(Field4<double>, const GridDesc&, double, unsigned long long*, hipStream_t);
+template hipError_t launch_umax<float>(Field4<float>, const GridDesc&, double, double*, hipStream_t);
+template hipError_t launch_umax<double>(Field4<double>, const GridDesc&, double, double*, hipStream_t);
 template hipError_t launch_diag<float>(Field4<float>, const GridDesc&, double, double*, int, DevState*, hipStream_t);
 template hipError_t launch_diag<double>(Field4<double>, const GridDesc&, double, double*, int, DevState*, hipStream_t);
 

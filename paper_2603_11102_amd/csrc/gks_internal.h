@@ -49,9 +49,10 @@ __host__ __device__ inline long long rx_block_index(int x, int y, int z, int nx,
 }
 
 // Device-resident scalars of a context (lives in the workspace).
+constexpr int UMAX_BLOCKS = 2048;  // partial maxima of |U|^2 per step (one per umax workgroup)
+
 struct DevState {
     double t, dt, t_next;
-    unsigned long long umax2_bits;   // max |U|^2 over Q^n of the current step (bits of a double >= 0)
     long long step;
     double thrust, torque, power, cp, ct;
     double ibm_force[3];
@@ -91,8 +92,10 @@ template <typename real>
 hipError_t launch_ghost(Field4<real> f, const GridDesc& g, int axis, int bc_lo, int bc_hi, const double u_in[3],
                         double c, double rho_ref, hipStream_t s);
 template <typename real>
-hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, unsigned long long* out_bits, hipStream_t s);
-hipError_t launch_dt(DevState* st, double cfl, double hmin, double c, double dt_fixed, hipStream_t s);
+hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, double* part, hipStream_t s);
+int umax_blocks(const GridDesc& g);
+hipError_t launch_dt(DevState* st, const double* part, int nparts, double cfl, double hmin, double c,
+                     double dt_fixed, hipStream_t s);
 hipError_t launch_finish(DevState* st, int has_rotor, double* hist, hipStream_t s);
 hipError_t launch_window_reset(DevState* st, hipStream_t s);
 template <typename real>
