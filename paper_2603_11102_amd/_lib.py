@@ -6,7 +6,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgks.so")
+LIB_PATH = os.environ.get("GKS_LIBRARY") or os.path.join(HERE, "libgks.so")
 
 GKS_OK = 0
 GKS_E_INVALID_ARG = 1

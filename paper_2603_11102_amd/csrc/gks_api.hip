@@ -50,6 +50,7 @@ struct gks_ctx {
     void* r1[4];
     void* rx0[4];
     void* rx1[4];
+    void* qt[4];  // copy of the stage input in the layout [x][z][y], read by the x-direction face pass
     double* diag_partials;
     int diag_nblk;
     double* umax_part;  // per-workgroup maxima of |U|^2 for the CFL time step
@@ -113,6 +114,7 @@ struct Layout {
     void* r1[4];
     void* rx0[4];
     void* rx1[4];
+    void* qt[4];
     double* diag;
     double* umax_part;
     char* alm;
@@ -155,6 +157,8 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     const size_t NB = (size_t)c->nx * ((c->ny + 15) / 16) * 16 * c->nz;
     for (int v = 0; v < 4; ++v) L->rx0[v] = cv.ptr<void>(NB * es);
     for (int v = 0; v < 4; ++v) L->rx1[v] = cv.ptr<void>(NB * es);
+    const size_t NP = (size_t)(c->nx + 6) * (c->ny + 6) * (c->nz + 6);
+    for (int v = 0; v < 4; ++v) L->qt[v] = cv.ptr<void>(NP * es);
     L->diag = cv.ptr<double>(sizeof(double) * 4 * 1024);
     L->umax_part = cv.ptr<double>(sizeof(double) * UMAX_BLOCKS);
     size_t ab = alm_block_bytes(c->max_act);
@@ -168,6 +172,7 @@ bool layout(const gks_config* c, char* base, Layout* L) {
 std::string validate(const gks_config* c) {
     if (!c) return "config is null";
     if (c->nx < 3 || c->ny < 3 || c->nz < 3) return "nx, ny, nz must be >= 3";
+    if (c->nx > 65000 || c->ny > 65000 || c->nz > 65000) return "nx, ny, nz must be <= 65000";
     if ((long long)c->nx * c->ny * c->nz > (1LL << 31)) return "grid too large (more than 2^31 cells)";
     if (c->precision != GKS_FP32 && c->precision != GKS_FP64) return "precision must be GKS_FP32 or GKS_FP64";
     if (!(c->lx > 0 && c->ly > 0 && c->lz > 0)) return "domain lengths must be > 0";
@@ -205,7 +210,7 @@ int ghost_all(gks_ctx* c, void* const p[4]) {
 // q_c = Q^n in the epilogue; stage 2: reads src = Q*, writes out_a = Q^{n+1} from s_in = S.
 template <typename real>
 FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], void* const out_a[4],
-                             void* const out_b[4], void* const q_c[4]) {
+                             void* const out_b[4], void* const q_c[4], void* const xt[4] = nullptr) {
     FaceArgs<real> a;
     std::memset(&a, 0, sizeof(a));
     const int* pm = kPerm[d];
@@ -239,6 +244,15 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.ist_t1 = ist[ax[1]];
     a.ist_t2 = ist[ax[2]];
     a.pad0 = c->g.pad0;
+    if (d == 0 && xt) {
+        // the x pass reads the [x][z][y] copy of src: n = x, t1 = y (unit stride), t2 = z
+        const long long Y = c->cfg.ny + 6, Z = c->cfg.nz + 6;
+        for (int v = 0; v < 4; ++v) a.q[v] = static_cast<const real*>(xt[pm[v]]);
+        a.st_n = Y * Z;
+        a.st_t1 = 1;
+        a.st_t2 = Y;
+        a.pad0 = 3 * (Y * Z + 1 + Y);
+    }
     a.inv_hn = real(1.0 / c->g.h[ax[0]]);
     a.inv_h1 = real(1.0 / c->g.h[ax[1]]);
     a.inv_h2 = real(1.0 / c->g.h[ax[2]]);
@@ -263,8 +277,8 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
 
 template <typename real>
 FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
-    if (stage == 1) return face_args_buf<real>(c, d, 1, src, c->qs, c->qa, c->q);
-    return face_args_buf<real>(c, d, 2, src, c->q, c->qa, nullptr);
+    if (stage == 1) return face_args_buf<real>(c, d, 1, src, c->qs, c->qa, c->q, c->qt);
+    return face_args_buf<real>(c, d, 2, src, c->q, c->qa, nullptr, c->qt);
 }
 
 AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4]) {
@@ -369,6 +383,7 @@ int steps(gks_ctx* c, int nsteps) {
         }
         tp = tbeg(c, GKS_TIMER_GHOST);
         int rc = ghost_all<real>(c, c->q);
+        if (!rc) HIPCHK(c, launch_transpose_xy<real>(field<real>(c->q), field<real>(c->qt), c->g, c->stream));
         tend(c, tp);
         if (rc) return rc;
         tp = tbeg(c, GKS_TIMER_DT);
@@ -383,6 +398,7 @@ int steps(gks_ctx* c, int nsteps) {
         }
         tp = tbeg(c, GKS_TIMER_GHOST);
         rc = ghost_all<real>(c, c->qs);
+        if (!rc) HIPCHK(c, launch_transpose_xy<real>(field<real>(c->qs), field<real>(c->qt), c->g, c->stream));
         tend(c, tp);
         if (rc) return rc;
         for (int d = 0; d < 3; ++d) {
@@ -477,6 +493,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         c->r1[v] = L.r1[v];
         c->rx0[v] = L.rx0[v];
         c->rx1[v] = L.rx1[v];
+        c->qt[v] = L.qt[v];
     }
     c->diag_partials = L.diag;
     c->umax_part = L.umax_part;

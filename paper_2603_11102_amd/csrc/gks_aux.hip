@@ -112,6 +112,39 @@ __global__ void __launch_bounds__(256) umax_kernel(Field4<real> f, GridDesc g, d
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Copy of a padded field in the layout [x][z][y] (y fastest), read by the x-direction face pass so that
+// its column loads are contiguous along y. One 32 x 32 (x, y) tile of one z-plane per workgroup.
+template <typename real>
+__global__ void __launch_bounds__(256) transpose_xy_kernel(Field4<real> in, Field4<real> out, int X, int Y, int Z) {
+    __shared__ real t[4][32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+    // all 16 loads of a thread are issued before the single barrier
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int r = ty; r < 32; r += 8) {
+            const int x = x0 + tx, y = y0 + r;
+            if (x < X && y < Y) t[v][r][tx] = in.v[v][((long long)z * Y + y) * X + x];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int r = ty; r < 32; r += 8) {
+            const int y = y0 + tx, x = x0 + r;
+            if (x < X && y < Y) out.v[v][((long long)x * Z + z) * Y + y] = t[v][tx][r];
+        }
+}
+
+template <typename real>
+hipError_t launch_transpose_xy(Field4<real> in, Field4<real> out, const GridDesc& g, hipStream_t s) {
+    const int X = g.n[0] + 6, Y = g.n[1] + 6, Z = g.n[2] + 6;
+    hipLaunchKernelGGL((transpose_xy_kernel<real>), dim3((X + 31) / 32, (Y + 31) / 32, Z), dim3(256), 0, s, in, out,
+                       X, Y, Z);
+    return hipGetLastError();
+}
+
 int umax_blocks(const GridDesc& g) {
     const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
     long long blocks = (n + 255) / 256;
@@ -291,6 +324,8 @@ hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream
 
 template hipError_t launch_ghost<float>(Field4<float>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
 template hipError_t launch_ghost<double>(Field4<double>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
+template hipError_t launch_transpose_xy<float>(Field4<float>, Field4<float>, const GridDesc&, hipStream_t);
+template hipError_t launch_transpose_xy<double>(Field4<double>, Field4<double>, const GridDesc&, hipStream_t);
 template hipError_t launch_umax<float>(Field4<float>, const GridDesc&, double, double*, hipStream_t);
 template hipError_t launch_umax<double>(Field4<double>, const GridDesc&, double, double*, hipStream_t);
 template hipError_t launch_diag<float>(Field4<float>, const GridDesc&, double, double*, int, DevState*, hipStream_t);

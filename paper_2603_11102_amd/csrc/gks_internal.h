@@ -94,6 +94,8 @@ hipError_t launch_ghost(Field4<real> f, const GridDesc& g, int axis, int bc_lo, 
 template <typename real>
 hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, double* part, hipStream_t s);
 int umax_blocks(const GridDesc& g);
+template <typename real>
+hipError_t launch_transpose_xy(Field4<real> in, Field4<real> out, const GridDesc& g, hipStream_t s);
 hipError_t launch_dt(DevState* st, const double* part, int nparts, double cfl, double hmin, double c,
                      double dt_fixed, hipStream_t s);
 hipError_t launch_finish(DevState* st, int has_rotor, double* hist, hipStream_t s);

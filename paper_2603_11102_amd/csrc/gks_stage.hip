@@ -21,6 +21,11 @@
 
 namespace gks {
 
+template <typename T>
+__device__ __forceinline__ T pick(bool c, T x, T y) {
+    return c ? x : y;
+}
+
 template <typename real, int STAGE>
 __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
     constexpr bool NEED_F0 = (STAGE == 1);
@@ -197,40 +202,51 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                                    (long long)(k0 + fk) * a.ist_t2;
             const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)(j0 + fj) * a.st_t1 +
                                    (long long)(k0 + fk) * a.st_t2;
+            // lane m writes variables 2m and 2m + 1. Pointers and values are picked by value with a per-lane
+            // select between compile-time indices: indexing the argument or register arrays with the
+            // lane-dependent variable index would fetch pointers from memory and move the arrays to scratch.
+            const bool hi = m != 0;
 #pragma unroll
             for (int vv = 0; vv < 2; ++vv) {
-                const int v = 2 * m + vv;  // lane m writes variables 2m, 2m+1
-                real d1 = -(fa1[v] - fprev1[v]) * a.inv_hn;
-                real d0 = NEED_F0 ? -(fa0[v] - fprev0[v]) * a.inv_hn : real(0);
+                real d1 = -(pick(hi, fa1[2 + vv], fa1[vv]) - pick(hi, fprev1[2 + vv], fprev1[vv])) * a.inv_hn;
+                real d0 = NEED_F0 ? -(pick(hi, fa0[2 + vv], fa0[vv]) - pick(hi, fprev0[2 + vv], fprev0[vv])) * a.inv_hn
+                                  : real(0);
+                real* const r1p = pick(hi, a.r1[2 + vv], a.r1[vv]);
+                real* const r0p = pick(hi, a.r0[2 + vv], a.r0[vv]);
                 if (a.mode >= 3) {
                     const long long xidx =
                         a.rx_kind == 1 ? rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb)
                                        : rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+                    real* const x1p = pick(hi, a.rx1[2 + vv], a.rx1[vv]);
+                    real* const x0p = pick(hi, a.rx0[2 + vv], a.rx0[vv]);
                     if (a.mode == 3) {
-                        a.rx1[v][xidx] = d1;
-                        if (NEED_F0) a.rx0[v][xidx] = d0;
+                        x1p[xidx] = d1;
+                        if (NEED_F0) x0p[xidx] = d0;
                         continue;
                     }
-                    d1 += a.rx1[v][xidx];
-                    if (NEED_F0) d0 += a.rx0[v][xidx];
+                    d1 += x1p[xidx];
+                    if (NEED_F0) d0 += x0p[xidx];
                 }
                 if (a.mode == 0) {
-                    a.r1[v][ridx] = d1;
-                    if (NEED_F0) a.r0[v][ridx] = d0;
+                    r1p[ridx] = d1;
+                    if (NEED_F0) r0p[ridx] = d0;
                 } else if (a.mode == 1) {
-                    a.r1[v][ridx] += d1;
-                    if (NEED_F0) a.r0[v][ridx] += d0;
+                    r1p[ridx] += d1;
+                    if (NEED_F0) r0p[ridx] += d0;
                 } else {
-                    const real L1 = a.r1[v][ridx] + d1;
+                    const real L1 = r1p[ridx] + d1;
+                    real* const outa = pick(hi, a.out_a[2 + vv], a.out_a[vv]);
                     if (NEED_F0) {
-                        const real L0 = a.r0[v][ridx] + d0;
-                        const real Q = a.q_c[v][pidx];
-                        a.out_a[v][pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
-                        a.out_b[v][pidx] = Q + dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1;
+                        const real L0 = r0p[ridx] + d0;
+                        const real Q = pick(hi, a.q_c[2 + vv], a.q_c[vv])[pidx];
+                        real* const outb = pick(hi, a.out_b[2 + vv], a.out_b[vv]);
+                        outa[pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
+                        outb[pidx] = Q + dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1;
                     } else {
-                        real add = (dt * dt * real(1.0 / 3.0)) * L1;
-                        if (v > 0) add += dt * a.g_local[v - 1];
-                        a.out_a[v][pidx] = a.s_in[v][pidx] + add;
+                        // body force G on the momenta (variables 1..3); variable 0 (vv = 0, lane 0) has none
+                        const real gv = pick(hi, a.g_local[1 + vv], vv == 1 ? a.g_local[0] : real(0));
+                        const real add = (dt * dt * real(1.0 / 3.0)) * L1 + dt * gv;
+                        outa[pidx] = pick(hi, a.s_in[2 + vv], a.s_in[vv])[pidx] + add;
                     }
                 }
             }
@@ -256,16 +272,16 @@ int face_slots() {
 
 template <typename real>
 int face_chunk(int n_n, int tiles, int slots) {
-    // Workgroups of one launch run in rounds of `slots`; a workgroup costs about (chunk + 4) face steps
-    // (the column phase primes four planes before the first face). Pick the chunk that minimises
-    // rounds x (chunk + 4); ties go to the longer chunk.
+    // Workgroups of one launch run in rounds of `slots`; a workgroup costs about (chunk + 2) face steps
+    // (chunk + 1 faces, and the column phase primes five planes before the first one). Pick the chunk
+    // that minimises rounds x (chunk + 2); ties go to the longer chunk.
     if (slots <= 0) slots = 512;
     int best_chunk = n_n;
     long long best = -1;
     for (int nc = 1; nc <= n_n; ++nc) {
         const int chunk = (n_n + nc - 1) / nc;
         const long long wgs = (long long)tiles * ((n_n + chunk - 1) / chunk);
-        const long long cost = ((wgs + slots - 1) / slots) * (chunk + 4);
+        const long long cost = ((wgs + slots - 1) / slots) * (chunk + 2);
         if (best < 0 || cost < best) {
             best = cost;
             best_chunk = chunk;
