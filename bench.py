@@ -101,6 +101,42 @@ def cpu_baseline(cfg, planes):
                        f"z-planes of the same field, periodic in z), {dt:.1f} s")}
 
 
+def adjoint_ratio(steps_override=None):
+    """Time of the discrete adjoint over the rotor-gradient window (recompute included) divided by the time
+    of the FP64 forward window that stores the checkpoints, on the 128^3 rotor box."""
+    import numpy as np
+    import torch
+    from paper_2603_11102_amd import GksSolver
+    from synth import make_case
+    cfg = make_case("adjoint")
+    nsteps = steps_override or cfg.steps
+    ones = torch.ones(cfg.rotor.n_act, dtype=torch.float64, device="cuda")
+    w = GksSolver(cfg, precision="fp64")  # warm-up of every kernel of the forward and adjoint windows
+    w.set_rotor(cfg.rotor, ones)
+    w.set_checkpoints(1)
+    w.step(1)
+    w.adjoint(1, (1.0, 0.5))
+    w.close()
+    s = GksSolver(cfg, precision="fp64")
+    s.set_rotor(cfg.rotor, ones)
+    s.set_checkpoints(nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g, _ = s.adjoint(nsteps, (1.0, 0.5))
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    ok = bool(torch.isfinite(g).all())
+    return {"metric": "adjoint/forward time ratio", "value": t_adj / t_fwd, "unit": "ratio",
+            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"rotor box {cfg.nx}x{cfg.ny}x{cfg.nz}, {cfg.rotor.n_act} actuator points, "
+                                   f"{nsteps} steps, gradient of mean power and thrust w.r.t. the point scalings"},
+            "forward_s": t_fwd, "adjoint_s": t_adj, "gradient_finite": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,11 +146,21 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=100,
+                    help="steps after which the FP32 field is compared with the FP64 one (at least the timed ones)")
     ap.add_argument("--cpu-planes", type=int, default=96,
                     help="z-planes of the field the CPU oracle steps once (all of them by default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only time the adjoint against its checkpointed forward window and print that line")
     args = ap.parse_args()
+    if args.adjoint:
+        r = adjoint_ratio()
+        print(f"[bench] adjoint/forward: {r['value']:.3f} (forward {r['forward_s']:.3f} s, adjoint "
+              f"{r['adjoint_s']:.3f} s)", flush=True)
+        print(json.dumps(r), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy * (1 << 20) // 4
@@ -173,10 +219,15 @@ def main():
     }
     if args.precision == "fp32" and not args.no_fp64:
         s64, ms64, _, _, _ = run_gpu(cfg, "fp64", args.steps, args.warmup)
+        done = args.warmup + 2 * args.steps
+        if done < args.accuracy_steps:  # compare FP32 with FP64 after the same number of steps
+            s.step(args.accuracy_steps - done)
+            s64.step(args.accuracy_steps - done)
+            done = args.accuracy_steps
         q32, q64 = s.interior(), s64.interior()
         rl2 = [float(torch.linalg.vector_norm(q32[v] - q64[v]) / torch.linalg.vector_norm(q64[v])) for v in range(4)]
         result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
-        result["fp32_vs_fp64_rel_l2"] = {"after_steps": args.steps * 2 + args.warmup, "per_variable": rl2}
+        result["fp32_vs_fp64_rel_l2"] = {"after_steps": done, "per_variable": rl2}
         print(f"[bench] fp64: {ms64 / args.steps:.3f} ms/step; fp32 vs fp64 rel L2 {rl2}", flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample ...", flush=True)

@@ -29,6 +29,8 @@ __device__ __forceinline__ T pick(bool c, T x, T y) {
 template <typename real, int STAGE>
 __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
     constexpr bool NEED_F0 = (STAGE == 1);
+    // FP32: the z pass loads its epilogue operands at the top of the step (FP64 has no registers to spare)
+    constexpr bool EPI_PREFETCH = sizeof(real) == 4;
     constexpr int NT1 = TILE1 * EXT2;             // t1 items per variable (320)
     __shared__ real s_nrm[4][4][EXT2][EXT1];      // [variable][q^L, q^R, D, C]
     __shared__ real s_t1[4][5][EXT2][TILE1][2];   // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
@@ -93,7 +95,30 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
         fprev1[v] = real(0);
     }
 
+    const bool hi = m != 0;
     for (int f = f0; f <= f1; ++f) {
+        // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
+        real e_r0[2] = {0, 0}, e_r1[2] = {0, 0}, e_x0[2] = {0, 0}, e_x1[2] = {0, 0}, e_q[2] = {0, 0};
+        if (EPI_PREFETCH && a.mode == 4 && f > f0 && face_ok) {
+            const int cell = f - 1;
+            const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
+                                   (long long)(k0 + fk) * a.ist_t2;
+            const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)(j0 + fj) * a.st_t1 +
+                                   (long long)(k0 + fk) * a.st_t2;
+            const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+#pragma unroll
+            for (int vv = 0; vv < 2; ++vv) {
+                e_r1[vv] = pick(hi, a.r1[2 + vv], a.r1[vv])[ridx];
+                e_x1[vv] = pick(hi, a.rx1[2 + vv], a.rx1[vv])[xidx];
+                if (NEED_F0) {
+                    e_r0[vv] = pick(hi, a.r0[2 + vv], a.r0[vv])[ridx];
+                    e_x0[vv] = pick(hi, a.rx0[2 + vv], a.rx0[vv])[xidx];
+                    e_q[vv] = pick(hi, a.q_c[2 + vv], a.q_c[vv])[pidx];
+                } else {
+                    e_q[vv] = pick(hi, a.s_in[2 + vv], a.s_in[vv])[pidx];
+                }
+            }
+        }
         // ---- column phase (all variables): window cells f-2 .. f+2, prefetch cell f+3
         if (col) {
 #pragma unroll
@@ -205,7 +230,6 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             // lane m writes variables 2m and 2m + 1. Pointers and values are picked by value with a per-lane
             // select between compile-time indices: indexing the argument or register arrays with the
             // lane-dependent variable index would fetch pointers from memory and move the arrays to scratch.
-            const bool hi = m != 0;
 #pragma unroll
             for (int vv = 0; vv < 2; ++vv) {
                 real d1 = -(pick(hi, fa1[2 + vv], fa1[vv]) - pick(hi, fprev1[2 + vv], fprev1[vv])) * a.inv_hn;
@@ -213,6 +237,22 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                                   : real(0);
                 real* const r1p = pick(hi, a.r1[2 + vv], a.r1[vv]);
                 real* const r0p = pick(hi, a.r0[2 + vv], a.r0[vv]);
+                if (EPI_PREFETCH && a.mode == 4) {
+                    const real L1 = e_r1[vv] + e_x1[vv] + d1;
+                    real* const outa = pick(hi, a.out_a[2 + vv], a.out_a[vv]);
+                    if (NEED_F0) {
+                        const real L0 = e_r0[vv] + e_x0[vv] + d0;
+                        const real Q = e_q[vv];
+                        real* const outb = pick(hi, a.out_b[2 + vv], a.out_b[vv]);
+                        outa[pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
+                        outb[pidx] = Q + dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1;
+                    } else {
+                        const real gv = pick(hi, a.g_local[1 + vv], vv == 1 ? a.g_local[0] : real(0));
+                        const real add = (dt * dt * real(1.0 / 3.0)) * L1 + dt * gv;
+                        outa[pidx] = e_q[vv] + add;
+                    }
+                    continue;
+                }
                 if (a.mode >= 3) {
                     const long long xidx =
                         a.rx_kind == 1 ? rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb)
