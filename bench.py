@@ -36,7 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # "bench.py --steps 2 --warmup 1 --no-fp64 --no-cpu-baseline", each scaled by what the same counter reads
 # for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024": FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
 # The figure belongs to the kernel sources it was measured on; bench reports null once they differ.
-TRAFFIC = {"sources_sha256": None, "fetch_bytes": None, "write_bytes": None}
+TRAFFIC = {"sources_sha256": "e535c7cdb8283fc20c1fcb666383cb9e3eed1acc4a75eb85a8bf6a5a29eb145e",
+           "fetch_bytes": 236_412_382, "write_bytes": 67_674_842}
 KERNEL_SOURCES = ("gks_stage.hip", "gks_device.h", "gks_internal.h")
 
 
