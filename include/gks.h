@@ -158,6 +158,14 @@ int gks_forces(gks_ctx* ctx, gks_forces_out* out);
 /* Reset the window sums of power and thrust (gks_forces_out.window_*). Enqueued on the stream. */
 int gks_reset_window(gks_ctx* ctx);
 
+/* FP32 contexts carry the state as the field q plus a low-order part held in the workspace (the
+ * S2O4 stage updates of Section 2 are applied as error-free sums, so the stored state keeps about
+ * twice the FP32 digits across steps while every flux is still evaluated from q in FP32). A caller
+ * that overwrites q after gks_init must call this before the next gks_step: it clears the low-order
+ * part (enqueued on the stream). FP64 contexts: no effect. Returns GKS_E_INVALID_ARG for a null ctx,
+ * GKS_E_HIP if the clear cannot be enqueued. */
+int gks_field_changed(gks_ctx* ctx);
+
 /* Bytes of device memory one checkpoint slot needs (one field, the time and dt of a step). */
 size_t gks_checkpoint_slot_bytes(const gks_config* cfg);
 

@@ -69,7 +69,7 @@ class gks_forces_out(C.Structure):
 
 EXPORTS = (
     "gks_workspace_bytes", "gks_init", "gks_set_actuators", "gks_set_ibm_points", "gks_step",
-    "gks_forces", "gks_reset_window", "gks_checkpoint_slot_bytes", "gks_set_checkpoints",
+    "gks_forces", "gks_reset_window", "gks_field_changed", "gks_checkpoint_slot_bytes", "gks_set_checkpoints",
     "gks_adjoint_workspace_bytes", "gks_adjoint", "gks_set_timing", "gks_read_timing", "gks_destroy",
     "gks_last_error", "gks_statistics_bytes", "gks_set_statistics", "gks_read_statistics", "gks_set_history",
     "gks_history_count",
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.gks_forces.restype = C.c_int
     lib.gks_reset_window.argtypes = [P]
     lib.gks_reset_window.restype = C.c_int
+    lib.gks_field_changed.argtypes = [P]
+    lib.gks_field_changed.restype = C.c_int
     lib.gks_checkpoint_slot_bytes.argtypes = [C.POINTER(gks_config)]
     lib.gks_checkpoint_slot_bytes.restype = C.c_size_t
     lib.gks_set_checkpoints.argtypes = [P, P, C.c_int32]

@@ -51,6 +51,10 @@ struct gks_ctx {
     void* rx0[4];
     void* rx1[4];
     void* qt[4];  // copy of the stage input in the layout [x][z][y], read by the x-direction face pass
+    // FP32: low-order parts of Q^n / Q^{n+1}, Q* and S (interior layout); the state is field + low part
+    void* lo_q[4];
+    void* lo_qs[4];
+    void* lo_qa[4];
     double* diag_partials;
     int diag_nblk;
     double* umax_part;  // per-workgroup maxima of |U|^2 for the CFL time step
@@ -115,6 +119,7 @@ struct Layout {
     void* rx0[4];
     void* rx1[4];
     void* qt[4];
+    void* lo[3][4];
     double* diag;
     double* umax_part;
     char* alm;
@@ -159,6 +164,8 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     for (int v = 0; v < 4; ++v) L->rx1[v] = cv.ptr<void>(NB * es);
     const size_t NP = (size_t)(c->nx + 6) * (c->ny + 6) * (c->nz + 6);
     for (int v = 0; v < 4; ++v) L->qt[v] = cv.ptr<void>(NP * es);
+    for (int b = 0; b < 3; ++b)
+        for (int v = 0; v < 4; ++v) L->lo[b][v] = c->precision == GKS_FP32 ? cv.ptr<void>(N * es) : nullptr;
     L->diag = cv.ptr<double>(sizeof(double) * 4 * 1024);
     L->umax_part = cv.ptr<double>(sizeof(double) * UMAX_BLOCKS);
     size_t ab = alm_block_bytes(c->max_act);
@@ -210,7 +217,9 @@ int ghost_all(gks_ctx* c, void* const p[4]) {
 // q_c = Q^n in the epilogue; stage 2: reads src = Q*, writes out_a = Q^{n+1} from s_in = S.
 template <typename real>
 FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], void* const out_a[4],
-                             void* const out_b[4], void* const q_c[4], void* const xt[4] = nullptr) {
+                             void* const out_b[4], void* const q_c[4], void* const xt[4] = nullptr,
+                             void* const lo_in[4] = nullptr, void* const lo_a[4] = nullptr,
+                             void* const lo_b[4] = nullptr) {
     FaceArgs<real> a;
     std::memset(&a, 0, sizeof(a));
     const int* pm = kPerm[d];
@@ -224,6 +233,9 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
         a.rx0[v] = static_cast<real*>(c->rx0[gv]);
         a.rx1[v] = static_cast<real*>(c->rx1[gv]);
         a.out_a[v] = static_cast<real*>(out_a[gv]);
+        a.lo_in[v] = lo_in ? static_cast<const real*>(lo_in[gv]) : nullptr;
+        a.lo_a[v] = lo_a ? static_cast<real*>(lo_a[gv]) : nullptr;
+        a.lo_b[v] = lo_b ? static_cast<real*>(lo_b[gv]) : nullptr;
         if (stage == 1) {
             a.out_b[v] = static_cast<real*>(out_b[gv]);
             a.q_c[v] = static_cast<const real*>(q_c[gv]);
@@ -268,7 +280,6 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     // x faces write their own arrays in the blocked layout [z][y/16][x][y%16] so that the x pass
     // stores contiguous runs; the y pass writes the main arrays, the z pass accumulates both and
     // applies the S2O4 combination
-    a.rx_kind = d == 0 ? 1 : (d == 2 ? 2 : 0);
     a.rx_nx = c->cfg.nx;
     a.rx_nyb = (c->cfg.ny + 15) / 16;
     a.mode = d == 0 ? 3 : (d == 1 ? 0 : 4);
@@ -277,8 +288,8 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
 
 template <typename real>
 FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
-    if (stage == 1) return face_args_buf<real>(c, d, 1, src, c->qs, c->qa, c->q, c->qt);
-    return face_args_buf<real>(c, d, 2, src, c->q, c->qa, nullptr, c->qt);
+    if (stage == 1) return face_args_buf<real>(c, d, 1, src, c->qs, c->qa, c->q, c->qt, c->lo_q, c->lo_qs, c->lo_qa);
+    return face_args_buf<real>(c, d, 2, src, c->q, c->qa, nullptr, c->qt, c->lo_qa, c->lo_q, nullptr);
 }
 
 AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4]) {
@@ -361,6 +372,19 @@ int tbeg(gks_ctx* c, int cat) {
 
 void tend(gks_ctx* c, int pair) {
     if (pair >= 0) (void)hipEventRecord(c->ev_pool[2 * pair + 1], c->stream);
+}
+
+// FP32: zero the low-order parts of the compensated state (the state is then the field itself).
+hipError_t clear_low_parts(gks_ctx* c) {
+    if (c->cfg.precision != GKS_FP32) return hipSuccess;
+    const size_t bytes = (size_t)c->cfg.nx * c->cfg.ny * c->cfg.nz * sizeof(float);
+    void* const* sets[3] = {c->lo_q, c->lo_qs, c->lo_qa};
+    for (int b = 0; b < 3; ++b)
+        for (int v = 0; v < 4; ++v) {
+            hipError_t e = hipMemsetAsync(sets[b][v], 0, bytes, c->stream);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 
 template <typename real>
@@ -494,6 +518,9 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         c->rx0[v] = L.rx0[v];
         c->rx1[v] = L.rx1[v];
         c->qt[v] = L.qt[v];
+        c->lo_q[v] = L.lo[0][v];
+        c->lo_qs[v] = L.lo[1][v];
+        c->lo_qa[v] = L.lo[2][v];
     }
     c->diag_partials = L.diag;
     c->umax_part = L.umax_part;
@@ -526,6 +553,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
                                                  : face_chunk<double>(n[ax[0]], tiles, slots);
     }
     hipError_t e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
+    if (e == hipSuccess) e = clear_low_parts(c);
     if (e != hipSuccess) {
         g_init_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
         delete c;
@@ -765,6 +793,12 @@ int gks_forces(gks_ctx* c, gks_forces_out* out) {
 int gks_reset_window(gks_ctx* c) {
     if (!c) return GKS_E_INVALID_ARG;
     HIPCHK(c, launch_window_reset(c->st, c->stream));
+    return GKS_OK;
+}
+
+int gks_field_changed(gks_ctx* c) {
+    if (!c) return fail(nullptr, GKS_E_INVALID_ARG, "ctx is null");
+    HIPCHK(c, clear_low_parts(c));
     return GKS_OK;
 }
 

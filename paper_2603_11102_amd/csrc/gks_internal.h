@@ -22,12 +22,16 @@ struct FaceArgs {
     real* r1[4];             // accumulator of L_t (interior layout)
     real* rx0[4];            // x-direction contributions of L in the blocked layout [z][y/16][x][y%16]
     real* rx1[4];            // x-direction contributions of L_t, same layout
-    int rx_kind;             // 1: x faces (n, t1, t2) = (x, y, z); 2: z faces (n, t1, t2) = (z, x, y)
     int rx_nx, rx_nyb;       // nx and ceil(ny / 16) of the blocked layout
     real* out_a[4];          // epilogue: stage 1 -> Q*, stage 2 -> Q^{n+1} (padded)
     real* out_b[4];          // epilogue: stage 1 -> S (padded)
     const real* s_in[4];     // epilogue: stage 2 reads S (padded)
     const real* q_c[4];      // epilogue: stage 1 reads Q^n at the cell (padded)
+    // FP32 compensated state (interior layout): the low-order parts of the stage input of the epilogue
+    // (Q^n in stage 1, S in stage 2) and of its outputs (Q* and S; Q^{n+1}); null in FP64
+    const real* lo_in[4];
+    real* lo_a[4];
+    real* lo_b[4];
     int n_n, n_t1, n_t2;     // interior cells along normal, t1, t2
     int chunk, tiles_t1, tiles_t2;
     long long st_n, st_t1, st_t2;     // padded strides
@@ -38,8 +42,8 @@ struct FaceArgs {
     FluxConst<real> fc;
     real g_local[3];                  // constant body force in local momentum order (stage 2 epilogue)
     const double* dt_ptr;             // device dt of the current step
-    int mode;  // 0: write, 1: accumulate, 2: accumulate + S2O4 epilogue,
-               // 3: write the transposed x-direction arrays, 4: accumulate + add them + epilogue
+    int mode;  // 3: x pass (write the blocked x arrays), 0: y pass (write the main arrays),
+               // 4: z pass (add both, S2O4 stage update)
 };
 
 // Index of cell (x, y, z) in the blocked layout [z][y/16][x][y%16]: the x pass stores 16 consecutive y

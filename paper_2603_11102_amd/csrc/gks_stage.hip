@@ -26,10 +26,21 @@ __device__ __forceinline__ T pick(bool c, T x, T y) {
     return c ? x : y;
 }
 
-template <typename real, int STAGE>
+// Error-free sum (Knuth): s + e == a + b exactly, s = fl(a + b).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// MODE (the direction's role): 3 = x pass, writes its residual to the blocked arrays; 0 = y pass,
+// writes the main residual arrays; 4 = z pass, adds both and applies the S2O4 stage update.
+template <typename real, int STAGE, int MODE>
 __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
+    static_assert(MODE == 0 || MODE == 3 || MODE == 4, "face pass mode");
     constexpr bool NEED_F0 = (STAGE == 1);
-    // FP32: the z pass loads its epilogue operands at the top of the step (FP64 has no registers to spare)
+    // FP32: the z pass loads its epilogue operands at the top of the step (FP64 has no registers to
+    // spare) and updates the compensated state (high part in the field, low part in lo_in / lo_a / lo_b)
     constexpr bool EPI_PREFETCH = sizeof(real) == 4;
     constexpr int NT1 = TILE1 * EXT2;             // t1 items per variable (320)
     __shared__ real s_nrm[4][4][EXT2][EXT1];      // [variable][q^L, q^R, D, C]
@@ -99,7 +110,8 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     for (int f = f0; f <= f1; ++f) {
         // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
         real e_r0[2] = {0, 0}, e_r1[2] = {0, 0}, e_x0[2] = {0, 0}, e_x1[2] = {0, 0}, e_q[2] = {0, 0};
-        if (EPI_PREFETCH && a.mode == 4 && f > f0 && face_ok) {
+        real e_lo[2] = {0, 0};
+        if (EPI_PREFETCH && MODE == 4 && f > f0 && face_ok) {
             const int cell = f - 1;
             const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
                                    (long long)(k0 + fk) * a.ist_t2;
@@ -117,6 +129,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                 } else {
                     e_q[vv] = pick(hi, a.s_in[2 + vv], a.s_in[vv])[pidx];
                 }
+                e_lo[vv] = pick(hi, a.lo_in[2 + vv], a.lo_in[vv])[ridx];
             }
         }
         // ---- column phase (all variables): window cells f-2 .. f+2, prefetch cell f+3
@@ -237,47 +250,46 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                                   : real(0);
                 real* const r1p = pick(hi, a.r1[2 + vv], a.r1[vv]);
                 real* const r0p = pick(hi, a.r0[2 + vv], a.r0[vv]);
-                if (EPI_PREFETCH && a.mode == 4) {
+                if constexpr (EPI_PREFETCH && MODE == 4) {
+                    // FP32: the state is carried as hi + lo; each update is an error-free sum of the
+                    // stored high part and (low part + increment)
                     const real L1 = e_r1[vv] + e_x1[vv] + d1;
                     real* const outa = pick(hi, a.out_a[2 + vv], a.out_a[vv]);
+                    real* const loa = pick(hi, a.lo_a[2 + vv], a.lo_a[vv]);
+                    float sh, sl;
                     if (NEED_F0) {
                         const real L0 = e_r0[vv] + e_x0[vv] + d0;
-                        const real Q = e_q[vv];
                         real* const outb = pick(hi, a.out_b[2 + vv], a.out_b[vv]);
-                        outa[pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
-                        outb[pidx] = Q + dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1;
+                        real* const lob = pick(hi, a.lo_b[2 + vv], a.lo_b[vv]);
+                        two_sum(e_q[vv], e_lo[vv] + (real(0.5) * dt * L0 + real(0.125) * dt * dt * L1), sh, sl);
+                        outa[pidx] = sh;
+                        loa[ridx] = sl;
+                        two_sum(e_q[vv], e_lo[vv] + (dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1), sh, sl);
+                        outb[pidx] = sh;
+                        lob[ridx] = sl;
                     } else {
                         const real gv = pick(hi, a.g_local[1 + vv], vv == 1 ? a.g_local[0] : real(0));
                         const real add = (dt * dt * real(1.0 / 3.0)) * L1 + dt * gv;
-                        outa[pidx] = e_q[vv] + add;
+                        two_sum(e_q[vv], e_lo[vv] + add, sh, sl);
+                        outa[pidx] = sh;
+                        loa[ridx] = sl;
                     }
                     continue;
                 }
-                if (a.mode >= 3) {
-                    const long long xidx =
-                        a.rx_kind == 1 ? rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb)
-                                       : rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
-                    real* const x1p = pick(hi, a.rx1[2 + vv], a.rx1[vv]);
-                    real* const x0p = pick(hi, a.rx0[2 + vv], a.rx0[vv]);
-                    if (a.mode == 3) {
-                        x1p[xidx] = d1;
-                        if (NEED_F0) x0p[xidx] = d0;
-                        continue;
-                    }
-                    d1 += x1p[xidx];
-                    if (NEED_F0) d0 += x0p[xidx];
-                }
-                if (a.mode == 0) {
+                if constexpr (MODE == 3) {
+                    const long long xidx = rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb);
+                    pick(hi, a.rx1[2 + vv], a.rx1[vv])[xidx] = d1;
+                    if (NEED_F0) pick(hi, a.rx0[2 + vv], a.rx0[vv])[xidx] = d0;
+                } else if constexpr (MODE == 0) {
                     r1p[ridx] = d1;
                     if (NEED_F0) r0p[ridx] = d0;
-                } else if (a.mode == 1) {
-                    r1p[ridx] += d1;
-                    if (NEED_F0) r0p[ridx] += d0;
-                } else {
-                    const real L1 = r1p[ridx] + d1;
+                } else if constexpr (!EPI_PREFETCH) {
+                    // z pass without prefetch (FP64): add both other directions and update the stage
+                    const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+                    const real L1 = r1p[ridx] + (d1 + pick(hi, a.rx1[2 + vv], a.rx1[vv])[xidx]);
                     real* const outa = pick(hi, a.out_a[2 + vv], a.out_a[vv]);
                     if (NEED_F0) {
-                        const real L0 = r0p[ridx] + d0;
+                        const real L0 = r0p[ridx] + (d0 + pick(hi, a.rx0[2 + vv], a.rx0[vv])[xidx]);
                         const real Q = pick(hi, a.q_c[2 + vv], a.q_c[vv])[pidx];
                         real* const outb = pick(hi, a.out_b[2 + vv], a.out_b[vv]);
                         outa[pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
@@ -305,7 +317,7 @@ int face_slots() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1>, FACE_THREADS, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1, 4>, FACE_THREADS, 0) != hipSuccess)
         return 0;
     return cus * per_cu;
 }
@@ -335,10 +347,20 @@ hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
     const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (stage == 1)
-        hipLaunchKernelGGL((face_kernel<real, 1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
-    else
-        hipLaunchKernelGGL((face_kernel<real, 2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
+    const dim3 grid((unsigned)blocks), block(FACE_THREADS);
+#define GKS_FACE_LAUNCH(ST, MD) hipLaunchKernelGGL((face_kernel<real, ST, MD>), grid, block, 0, s, a)
+    if (stage == 1) {
+        if (a.mode == 0) GKS_FACE_LAUNCH(1, 0);
+        else if (a.mode == 3) GKS_FACE_LAUNCH(1, 3);
+        else if (a.mode == 4) GKS_FACE_LAUNCH(1, 4);
+        else return hipErrorInvalidValue;
+    } else {
+        if (a.mode == 0) GKS_FACE_LAUNCH(2, 0);
+        else if (a.mode == 3) GKS_FACE_LAUNCH(2, 3);
+        else if (a.mode == 4) GKS_FACE_LAUNCH(2, 4);
+        else return hipErrorInvalidValue;
+    }
+#undef GKS_FACE_LAUNCH
     return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ class GksSolver:
         q = torch.as_tensor(np.asarray(q0), dtype=torch.float64).clone()
         q[0] -= self.cfg.rho_ref
         self.q[:, NG:-NG, NG:-NG, NG:-NG] = q.to(self.dtype).to(self.device)
+        if getattr(self, "ctx", None):
+            L.check(self.lib, self.ctx, self.lib.gks_field_changed(self.ctx))
 
     def interior(self) -> torch.Tensor:
         """Interior cell averages [4, nz, ny, nx]: (rho - rho_ref, rho U, rho V, rho W), float64 on the host."""
