@@ -230,12 +230,17 @@ struct FluxConst {
 // Gas-kinetic flux at one Gauss point, in the face's local frame: variables (rho', m_n, m_t1, m_t2),
 // derivative directions (n, t1, t2). qL, qR: reconstructed left/right states; g[d][v]: dQ_v/dx_d.
 // Adds w * F0 (if NEED_F0) and w * F1 to f0, f1.
-template <typename real, bool NEED_F0>
+// SHIFT: qL[1], qR[1] hold m_n - cm for a constant cm, and the mass-flux part of f0 receives F0 - cm
+// (the constant cancels in the flux difference of a cell). The half-space weights satisfy
+// hL + hR - 1 = (erf(aL) - erf(aR)) / 2, so the shifted mass flux carries no O(cm) rounding.
+template <typename real, bool NEED_F0, bool SHIFT = false>
 __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], const real g[3][4],
-                                        const FluxConst<real>& k, real w, real f0[4], real f1[4]) {
+                                        const FluxConst<real>& k, real w, real f0[4], real f1[4],
+                                        real cm = real(0)) {
     // kinetic (half-space) average of the left and right Maxwellians, in deviation form
     real rL = k.rho_ref + qL[0], rR = k.rho_ref + qR[0];
-    real uL = qL[1] * rcp<real>(rL), uR = qR[1] * rcp<real>(rR);
+    const real mL = SHIFT ? cm + qL[1] : qL[1], mR = SHIFT ? cm + qR[1] : qR[1];
+    real uL = mL * rcp<real>(rL), uR = mR * rcp<real>(rR);
     real aL = k.sl * uL, aR = k.sl * uR;
     real eaL, eaR, ead;
     KinTrans<real>::erfs(aL, aR, eaL, eaR, ead);
@@ -246,7 +251,15 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
     real dE = eR * KinTrans<real>::expm1_(k.lam * (uR - uL) * (uR + uL));  // eL - eR
     real rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * real(0.5) * ead;
     real m0[3];
-    m0[0] = qL[1] * hL + qR[1] * hR + k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
+    real mass_flux;  // F0 of the density: m0[0], or m0[0] - cm when shifted
+    if (SHIFT) {
+        mass_flux = qL[1] * hL + qR[1] * hR + real(0.5) * cm * ead +
+                    k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
+        m0[0] = cm + mass_flux;
+    } else {
+        m0[0] = qL[1] * hL + qR[1] * hR + k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
+        mass_flux = m0[0];
+    }
     m0[1] = qL[2] * hL + qR[2] * hR;
     m0[2] = qL[3] * hL + qR[3] * hR;
     real r0 = k.rho_ref + rho0p;
@@ -259,7 +272,7 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
 #pragma unroll
         for (int j = 0; j < 3; ++j) dU[d][j] = (g[d][1 + j] - U[j] * g[d][0]) * ir;
     if (NEED_F0) {
-        f0[0] += w * m0[0];
+        f0[0] += w * mass_flux;
         f0[1] += w * (m0[0] * U[0] + k.c2 * rho0p - k.mu * real(2) * dU[0][0]);
         f0[2] += w * (m0[0] * U[1] - k.mu * (dU[0][1] + dU[1][0]));
         f0[3] += w * (m0[0] * U[2] - k.mu * (dU[0][2] + dU[2][0]));

@@ -68,6 +68,13 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
     const bool face_ok = (j0 + fj < a.n_t1) && (k0 + fk < a.n_t2);
 
+    // FP32: inside the kernel the normal momentum is carried as its deviation from a workgroup constant
+    // cm (the midrange of its values in the first window of the tile), so that the O(1) part of the
+    // mass flux cancels exactly between the two faces of a cell and FP32 rounding acts on the deviation
+    // only. The WENO and linear stencils commute with the shift (their weights sum to one and the
+    // smoothness indicators use differences); the derivatives are unchanged.
+    constexpr bool SHIFT = sizeof(real) == 4;
+    real cm = real(0);
     real ring[4][5];
     real carry[4];
 #pragma unroll
@@ -84,6 +91,37 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
 #pragma unroll
             for (int v = 0; v < 4; ++v) ring[v][r] = a.q[v][idx];
         }
+    }
+    if constexpr (SHIFT) {
+        __shared__ float s_range[2][FACE_THREADS / 64];
+        float lo = col_ld ? float(ring[1][0]) : 3.0e38f, up = col_ld ? float(ring[1][0]) : -3.0e38f;
+#pragma unroll
+        for (int r = 1; r < 5; ++r) {
+            lo = col_ld ? fminf(lo, float(ring[1][r])) : lo;
+            up = col_ld ? fmaxf(up, float(ring[1][r])) : up;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, o));
+            up = fmaxf(up, __shfl_xor(up, o));
+        }
+        if ((tid & 63) == 0) {
+            s_range[0][tid >> 6] = lo;
+            s_range[1][tid >> 6] = up;
+        }
+        __syncthreads();
+        lo = s_range[0][0];
+        up = s_range[1][0];
+#pragma unroll
+        for (int w = 1; w < FACE_THREADS / 64; ++w) {
+            lo = fminf(lo, s_range[0][w]);
+            up = fmaxf(up, s_range[1][w]);
+        }
+        cm = lo <= up ? real(0.5f * (lo + up)) : real(0);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) ring[1][r] -= cm;
+    }
+    if (col_ld) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             real right, left;
@@ -138,7 +176,8 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             for (int v = 0; v < 4; ++v) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
-                ring[v][4] = nxt[v];
+                // the shift is applied here, a step after the load, so that the prefetch stays in flight
+                ring[v][4] = (SHIFT && v == 1) ? nxt[v] - cm : nxt[v];
             }
             if (col_ld && f < f1) {
                 const long long idx = cbase + (long long)(f + 3) * a.st_n;
@@ -227,7 +266,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                 g[1][v] = gp[v][n][3];
                 g[2][v] = gp[v][n][4];
             }
-            gp_flux<real, NEED_F0>(qL, qR, g, a.fc, real(0.25), fa0, fa1);
+            gp_flux<real, NEED_F0, SHIFT>(qL, qR, g, a.fc, real(0.25), fa0, fa1, cm);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
