@@ -43,8 +43,12 @@ R12 Tip correction (Section 4.4, Eq. (tip-correction)): applied to F_x with (c1,
     forces; the exponential is capped at 1 so that sin(phi) <= 0 gives f = 0 instead of NaN.
 R13 Statistics: the printed RMS <sqrt((phi - <phi>)^2)> is read as sqrt(<(phi - <phi>)^2>); time
     averages over samples taken after every `interval`-th step.
-R10 IBM: Peskin 4-point delta, tensor product, in both directions; fixed iteration count; stationary
-    points (v_p = 0); residual reported after the last iteration.
+R10 IBM: Peskin 4-point delta, tensor product, in both directions; fixed iteration count; points at
+    fixed positions (the paper's bodies are stationary; prescribed point velocities v_p are allowed);
+    residual max_p |v_p - U_p| reported after the last iteration.
+R14 IBM velocity at the cells: the printed v-bar = sum_p W v_p is read with the volume weighting of
+    V-bar, v-bar = sum_p W V_p v_p / V-bar, so that it is a velocity (a uniform v_p gives v-bar = v_p;
+    stationary points give 0 as in the paper).
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
     momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
     U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).
@@ -608,19 +612,21 @@ def phi4(r):
 
 
 class IbmCache:
-    """Static data of stationary Lagrangian points: per point the 4x4x4 support cells and weights,
-    and per cell the interpolated volume V-bar (with v-bar = 0)."""
+    """Static data of Lagrangian points at fixed positions: per point the 4x4x4 support cells and
+    weights and its prescribed velocity, per cell the interpolated volume V-bar and velocity v-bar."""
 
-    def __init__(self, cells, weights, vbar_index, vbar):
+    def __init__(self, cells, weights, vbar_index, vbar, vel, vbar_vel):
         self.cells = cells        # [n, 64, 3] integer (i, j, k)
         self.weights = weights    # [n, 64]
         self.vbar_index = vbar_index  # [m, 3] cells with V-bar > 0
         self.vbar = vbar          # [m]
+        self.vel = vel            # [n, 3] point velocities v_p (zeros when stationary)
+        self.vbar_vel = vbar_vel  # [m, 3] v-bar at those cells
 
 
 def ibm_setup(cfg, ibm):
     """W_{p->ijk} = phi4((x_i-X)/dx) phi4((y_j-Y)/dy) phi4((z_k-Z)/dz); V_p = dx dS_p;
-    V-bar_ijk = sum_p W V_p (Section 3.2)."""
+    V-bar_ijk = sum_p W V_p (Section 3.2); v-bar_ijk = sum_p W V_p v_p / V-bar_ijk (reading R14)."""
     X = np.asarray(ibm.xyz, dtype=np.float64)
     n = X.shape[0]
     org = np.array([cfg.x0, cfg.y0, cfg.z0])
@@ -648,7 +654,13 @@ def ibm_setup(cfg, ibm):
     np.add.at(vb, flat.reshape(-1), (weights * vp[:, None]).reshape(-1))
     nz_idx = np.nonzero(vb > 0)[0]
     vbar_index = np.stack([nz_idx % cfg.nx, (nz_idx // cfg.nx) % cfg.ny, nz_idx // (cfg.nx * cfg.ny)], 1)
-    return IbmCache(cells, weights, vbar_index, vb[nz_idx])
+    vel = np.zeros((n, 3)) if getattr(ibm, "vel", None) is None else np.asarray(ibm.vel, dtype=np.float64)
+    vbar_vel = np.zeros((nz_idx.size, 3))
+    for d in range(3):
+        mv = np.zeros(cfg.nx * cfg.ny * cfg.nz)
+        np.add.at(mv, flat.reshape(-1), (weights * (vp * vel[:, d])[:, None]).reshape(-1))
+        vbar_vel[:, d] = mv[nz_idx] / vb[nz_idx]
+    return IbmCache(cells, weights, vbar_index, vb[nz_idx], vel, vbar_vel)
 
 
 def ibm_apply(Q, dt, cfg, cache, iters):
@@ -661,10 +673,11 @@ def ibm_apply(Q, dt, cfg, cache, iters):
     rho = Q[0, k, j, i]
     m = Q[1:, k, j, i]
     vbar = torch.tensor(cache.vbar, dtype=F64)
+    vv = torch.tensor(cache.vbar_vel.T.copy(), dtype=F64)  # [3, m]
     facc = torch.zeros_like(m)
     for _ in range(iters):
         U = m / rho
-        F = rho * vbar * (0.0 - U) / dt
+        F = rho * vbar * (vv - U) / dt
         m = m + dt * F / vol
         facc = facc + F
     mom = Q[1:].clone()
@@ -675,7 +688,8 @@ def ibm_apply(Q, dt, cfg, cache, iters):
     Uc = Qn[1:, c[..., 2], c[..., 1], c[..., 0]] / Qn[0, c[..., 2], c[..., 1], c[..., 0]]  # [3, n, 64]
     w = torch.tensor(cache.weights, dtype=F64)
     Up = (Uc * w).sum(-1)
-    res = torch.sqrt((Up * Up).sum(0)).max() if Up.shape[1] > 0 else torch.tensor(0.0, dtype=F64)
+    dv = torch.tensor(cache.vel.T.copy(), dtype=F64) - Up
+    res = torch.sqrt((dv * dv).sum(0)).max() if Up.shape[1] > 0 else torch.tensor(0.0, dtype=F64)
     total = facc.sum(1)
     return Qn, {"force_on_fluid": total, "body_force": -total, "residual": res, "facc": facc}
 

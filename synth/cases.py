@@ -66,6 +66,7 @@ class RotorSpec:
 class IbmSpec:
     xyz: np.ndarray  # [n, 3]
     dS: np.ndarray   # [n]
+    vel: Optional[np.ndarray] = None  # [n, 3] prescribed point velocities (None: stationary)
 
     @property
     def n(self) -> int:

@@ -197,3 +197,58 @@ def test_tip_correction_reduces_tip_loads():
     n = rot.n_per_blade
     assert float(b["fx"][n - 1]) < 0.5 * float(a["fx"][n - 1])
     assert abs(float(b["fx"][0]) / float(a["fx"][0]) - 1.0) < 1e-3
+
+
+def test_ibm_uniform_point_velocity_closed_form():
+    # every point moves with the same V: v-bar = V at each forced cell, and per cell
+    # U^S = V + (U^0 - V)(1 - V-bar/|Omega|)^S, sum_s F^s = rho |Omega| (V - U^0)(1 - (1 - V-bar/|Omega|)^S)/dt
+    cfg = _ibm_case()
+    V = np.array([0.3, -0.2, 0.1])
+    ib = IbmSpec(xyz=cfg.ibm.xyz, dS=cfg.ibm.dS, vel=np.tile(V, (cfg.ibm.n, 1)))
+    cache = ibm_setup(cfg, ib)
+    assert np.allclose(cache.vbar_vel, V[None, :], rtol=0, atol=1e-15)
+    Q = torch.tensor(cfg.q0)
+    dt, S = 0.02, 3
+    Qn, out = ibm_apply(Q, dt, cfg, cache, S)
+    vol = cfg.dx * cfg.dy * cfg.dz
+    i, j, k = cache.vbar_index.T
+    fac = (1.0 - cache.vbar / vol) ** S
+    U0 = (Q[1:, k, j, i] / Q[0, k, j, i]).numpy()
+    US = (Qn[1:, k, j, i] / Qn[0, k, j, i]).numpy()
+    assert np.allclose(US, V[:, None] + (U0 - V[:, None]) * fac, rtol=1e-12, atol=1e-15)
+    rho = Q[0, k, j, i].numpy()
+    Fsum = (rho * vol * (V[:, None] - U0) * (1.0 - fac) / dt).sum(1)
+    assert np.allclose(out["force_on_fluid"].numpy(), Fsum, rtol=1e-11)
+
+
+def test_ibm_body_moving_with_the_fluid_feels_no_force():
+    cfg = _ibm_case()
+    V = np.array([0.25, 0.1, -0.05])
+    q = np.zeros_like(cfg.q0)
+    q[0] = 1.1
+    for d in range(3):
+        q[1 + d] = 1.1 * V[d]
+    ib = IbmSpec(xyz=cfg.ibm.xyz, dS=cfg.ibm.dS, vel=np.tile(V, (cfg.ibm.n, 1)))
+    cache = ibm_setup(cfg, ib)
+    Q = torch.tensor(q)
+    Qn, out = ibm_apply(Q, 0.01, cfg, cache, 3)
+    assert float((Qn - Q).abs().max()) < 1e-15
+    assert float(out["force_on_fluid"].abs().max()) < 1e-12
+    assert float(out["residual"]) < 1e-14  # sum_c W = 1: the interpolated U equals V
+
+
+def test_ibm_point_velocity_is_volume_weighted():
+    # one cell in the support of two points with different areas and velocities
+    cfg = make_case("tgv", grid=(16, 16, 16)).with_(bc=("periodic",) * 6)
+    h = cfg.dx
+    xyz = np.array([[8.3 * h, 8.1 * h, 7.6 * h], [8.9 * h, 7.7 * h, 8.4 * h]])
+    dS = np.array([0.02, 0.05]) * h * h
+    vel = np.array([[1.0, 0.0, -0.5], [0.0, 2.0, 0.5]])
+    cache = ibm_setup(cfg, IbmSpec(xyz=xyz, dS=dS, vel=vel))
+    c = np.array([8, 8, 8])  # cell (i, j, k) = (8, 8, 8), centre (8.5 h, 8.5 h, 8.5 h)
+    row = int(np.nonzero((cache.vbar_index == c).all(1))[0][0])
+    w = [phi4(8.5 - xyz[p, 0] / h) * phi4(8.5 - xyz[p, 1] / h) * phi4(8.5 - xyz[p, 2] / h) for p in range(2)]
+    Vp = h * dS
+    expect = (w[0] * Vp[0] * vel[0] + w[1] * Vp[1] * vel[1]) / (w[0] * Vp[0] + w[1] * Vp[1])
+    assert np.allclose(cache.vbar_vel[row], expect, rtol=1e-13, atol=0)
+    assert abs(cache.vbar[row] - (w[0] * Vp[0] + w[1] * Vp[1])) < 1e-15 * cache.vbar[row] + 1e-30
