@@ -140,10 +140,12 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
  * and its 3 eps projection sphere must lie inside the interior cells. */
 int gks_set_actuators(gks_ctx* ctx, const gks_rotor* rotor);
 
-/* Set stationary Lagrangian points of the immersed bodies (Section 3.2): n points, host xyz [n][3]
- * and surface areas dS [n]; vel must be NULL (moving points are not supported). Each point's 4x4x4
- * discrete-delta support must lie inside the interior cells. Computes the static interpolated
- * volumes V-bar on the device. */
+/* Set the Lagrangian points of the immersed bodies (Section 3.2): n points at fixed positions, host
+ * xyz [n][3], surface areas dS [n] and velocities vel [n][3] (NULL: stationary points, the paper's
+ * nacelle and tower). Each point's 4x4x4 discrete-delta support must lie inside the interior cells.
+ * Computes on the device the interpolated volumes V-bar = sum W V_p (V_p = dx dS_p) and cell
+ * velocities v-bar = sum W V_p v_p / V-bar that the forcing drives the fluid towards. Host arrays
+ * are copied; GKS_E_INVALID_ARG for bad sizes, points or values. */
 int gks_set_ibm_points(gks_ctx* ctx, int64_t n, const double* xyz, const double* dS, const double* vel);
 
 /* Enqueue nsteps S2O4 steps (Section 2) with the body-force update of Section 3.3 on the stream and

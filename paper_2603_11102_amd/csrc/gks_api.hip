@@ -149,6 +149,8 @@ size_t ibm_block_bytes(long long n) {
     cv.take(sizeof(int) * nc);
     cv.take(sizeof(double) * nc);
     cv.take(sizeof(double) * 3 * ((nc + 255) / 256));
+    cv.take(sizeof(double) * 3 * n);   // point velocities
+    cv.take(sizeof(double) * 3 * nc);  // v-bar
     return cv.off;
 }
 
@@ -664,7 +666,6 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
 
 int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* dS, const double* vel) {
     if (!c) return GKS_E_INVALID_ARG;
-    if (vel) return fail(c, GKS_E_UNSUPPORTED, "moving Lagrangian points are not supported (vel must be NULL)");
     if (n <= 0 || !xyz || !dS) return fail(c, GKS_E_INVALID_ARG, "need n > 0 points with xyz and dS");
     if (n > c->cfg.max_ibm) return fail(c, GKS_E_INVALID_ARG, "more Lagrangian points than config.max_ibm");
     // host-side binning (index work only): every (cell, point) pair of the 4x4x4 supports, sorted by
@@ -674,6 +675,8 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     const long long nx = c->g.n[0], ny = c->g.n[1];
     for (long long p = 0; p < n; ++p) {
         if (!(dS[p] >= 0)) return fail(c, GKS_E_INVALID_ARG, "negative surface element");
+        if (vel && !(std::isfinite(vel[3 * p]) && std::isfinite(vel[3 * p + 1]) && std::isfinite(vel[3 * p + 2])))
+            return fail(c, GKS_E_INVALID_ARG, "non-finite point velocity");
         int i0[3];
         for (int d = 0; d < 3; ++d) {
             const double f = (xyz[3 * p + d] - c->g.x0[d]) / c->g.h[d] - 0.5;
@@ -718,6 +721,9 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     int* dent = cv.ptr<int>(sizeof(int) * nc);
     a.vbar = cv.ptr<double>(sizeof(double) * nc);
     a.partials = cv.ptr<double>(sizeof(double) * 3 * ((nc + 255) / 256));
+    double* dvel = cv.ptr<double>(sizeof(double) * 3 * cap);
+    a.vbar_vel = cv.ptr<double>(sizeof(double) * 3 * nc);
+    a.vel = vel ? dvel : nullptr;
     a.xyz = dx;
     a.dS = ds;
     a.cell = dcell;
@@ -731,6 +737,7 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     a.st = c->st;
     HIPCHK(c, hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(ds, dS, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    if (vel) HIPCHK(c, hipMemcpyAsync(dvel, vel, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(dcell, cells.data(), sizeof(int) * cells.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(dcsr, csr.data(), sizeof(int) * csr.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(dent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, c->stream));

@@ -38,6 +38,8 @@ struct IbmArgs {
     const int* csr;       // device, ncell + 1
     const int* ent;       // device, point indices per cell (ascending)
     double* vbar;         // device, ncell
+    const double* vel;    // device, 3 npts prescribed point velocities, or null (stationary points)
+    double* vbar_vel;     // device, 3 ncell: v-bar = sum W V_p v_p / V-bar (zero when vel is null)
     double* partials;     // device, 3 * ceil(ncell / 256)
     GridDesc g;
     DevState* st;

@@ -201,20 +201,25 @@ __device__ __forceinline__ double ibm_weight(const GridDesc& g, const double* X,
     return phi4d(rx) * phi4d(ry) * phi4d(rz);
 }
 
-// static V-bar_c = sum over the points whose support holds c of W V_p (fixed point order)
+// static V-bar_c = sum over the points whose support holds c of W V_p, and the cell velocity
+// v-bar_c = sum W V_p v_p / V-bar_c (fixed point order)
 __global__ void __launch_bounds__(256) ibm_vbar_kernel(IbmArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     const int i = a.cell[3 * c], j = a.cell[3 * c + 1], k = a.cell[3 * c + 2];
-    double v = 0.0;
+    double v = 0.0, mv[3] = {0.0, 0.0, 0.0};
     for (int e = a.csr[c]; e < a.csr[c + 1]; ++e) {
         const int p = a.ent[e];
-        v += ibm_weight(a.g, a.xyz + 3 * p, i, j, k) * a.g.h[0] * a.dS[p];
+        const double wv = ibm_weight(a.g, a.xyz + 3 * p, i, j, k) * (a.g.h[0] * a.dS[p]);
+        v += wv;
+        if (a.vel)
+            for (int d = 0; d < 3; ++d) mv[d] += wv * a.vel[3 * p + d];
     }
     a.vbar[c] = v;
+    for (int d = 0; d < 3; ++d) a.vbar_vel[3 * c + d] = (a.vel && v > 0.0) ? mv[d] / v : 0.0;
 }
 
-// per cell: S direct-forcing iterations (stationary points, v-bar = 0); FP64 block partials of sum F
+// per cell: S direct-forcing iterations towards v-bar; FP64 block partials of sum F
 template <typename real>
 __global__ void __launch_bounds__(256) ibm_cells_kernel(Field4<real> f, IbmArgs a) {
     __shared__ double red[3][256];
@@ -226,13 +231,14 @@ __global__ void __launch_bounds__(256) ibm_cells_kernel(Field4<real> f, IbmArgs 
         const double dt = a.st->dt;
         const double rho = a.rho_ref + (double)f.v[0][q];
         const double vb = a.vbar[c];
+        const double vv[3] = {a.vbar_vel[3 * c], a.vbar_vel[3 * c + 1], a.vbar_vel[3 * c + 2]};
         const double vol = a.g.h[0] * a.g.h[1] * a.g.h[2];
         double m[3] = {(double)f.v[1][q], (double)f.v[2][q], (double)f.v[3][q]};
         for (int s = 0; s < a.iters; ++s) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double U = m[d] / rho;
-                const double Fs = rho * vb * (0.0 - U) / dt;
+                const double Fs = rho * vb * (vv[d] - U) / dt;
                 m[d] = m[d] + dt * Fs / vol;
                 F[d] += Fs;
             }
@@ -289,6 +295,8 @@ __global__ void __launch_bounds__(256) ibm_resid_kernel(Field4<real> f, IbmArgs 
 #pragma unroll
                 for (int d = 0; d < 3; ++d) U[d] += w * ((double)f.v[1 + d][q] / rho);
             }
+    if (a.vel)
+        for (int d = 0; d < 3; ++d) U[d] -= a.vel[3 * p + d];
     const double r = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
     atomicMax(&a.st->ibm_res_bits, (unsigned long long)__double_as_longlong(r));
 }

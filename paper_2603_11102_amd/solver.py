@@ -133,9 +133,12 @@ class GksSolver:
     def set_ibm(self, ibm):
         xyz = np.ascontiguousarray(np.asarray(ibm.xyz, dtype=np.float64))
         ds = np.ascontiguousarray(np.asarray(ibm.dS, dtype=np.float64))
+        vel = getattr(ibm, "vel", None)
+        vel = None if vel is None else np.ascontiguousarray(np.asarray(vel, dtype=np.float64).reshape(-1, 3))
         dp = C.POINTER(C.c_double)
         L.check(self.lib, self.ctx, self.lib.gks_set_ibm_points(self.ctx, xyz.shape[0], xyz.ctypes.data_as(dp),
-                                                                ds.ctypes.data_as(dp), None))
+                                                                ds.ctypes.data_as(dp),
+                                                                None if vel is None else vel.ctypes.data_as(dp)))
 
     # ------------------------------------------------------------------ stepping
     def step(self, n: int = 1):
