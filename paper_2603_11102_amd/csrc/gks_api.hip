@@ -46,15 +46,17 @@ struct gks_ctx {
     size_t ws_bytes;
     hipStream_t stream;
     DevState* st;
-    void* r0[4];
-    void* r1[4];
-    void* rx0[4];
-    void* rx1[4];
+    // residual contributions of the y pass (r0: L, r1: L_t) and of the x pass (rx0, rx1, blocked
+    // layout), four variables per cell
+    void* r0;
+    void* r1;
+    void* rx0;
+    void* rx1;
     void* qt[4];  // copy of the stage input in the layout [x][z][y], read by the x-direction face pass
-    // FP32: low-order parts of Q^n / Q^{n+1}, Q* and S (interior layout); the state is field + low part
-    void* lo_q[4];
-    void* lo_qs[4];
-    void* lo_qa[4];
+    // FP32: low-order parts of Q^n / Q^{n+1}, Q* and S ([cell][4]); the state is field + low part
+    void* lo_q;
+    void* lo_qs;
+    void* lo_qa;
     double* diag_partials;
     int diag_nblk;
     double* umax_part;  // per-workgroup maxima of |U|^2 for the CFL time step
@@ -114,12 +116,12 @@ size_t elem_size(const gks_config* c) { return c->precision == GKS_FP32 ? 4 : 8;
 // workspace layout; base == nullptr only measures
 struct Layout {
     DevState* st;
-    void* r0[4];
-    void* r1[4];
-    void* rx0[4];
-    void* rx1[4];
+    void* r0;
+    void* r1;
+    void* rx0;
+    void* rx1;
     void* qt[4];
-    void* lo[3][4];
+    void* lo[3];
     double* diag;
     double* umax_part;
     char* alm;
@@ -159,15 +161,14 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     Carver cv{base, 0};
     L->st = cv.ptr<DevState>(sizeof(DevState));
-    for (int v = 0; v < 4; ++v) L->r0[v] = cv.ptr<void>(N * es);
-    for (int v = 0; v < 4; ++v) L->r1[v] = cv.ptr<void>(N * es);
+    L->r0 = cv.ptr<void>(4 * N * es);
+    L->r1 = cv.ptr<void>(4 * N * es);
     const size_t NB = (size_t)c->nx * ((c->ny + 15) / 16) * 16 * c->nz;
-    for (int v = 0; v < 4; ++v) L->rx0[v] = cv.ptr<void>(NB * es);
-    for (int v = 0; v < 4; ++v) L->rx1[v] = cv.ptr<void>(NB * es);
+    L->rx0 = cv.ptr<void>(4 * NB * es);
+    L->rx1 = cv.ptr<void>(4 * NB * es);
     const size_t NP = (size_t)(c->nx + 6) * (c->ny + 6) * (c->nz + 6);
     for (int v = 0; v < 4; ++v) L->qt[v] = cv.ptr<void>(NP * es);
-    for (int b = 0; b < 3; ++b)
-        for (int v = 0; v < 4; ++v) L->lo[b][v] = c->precision == GKS_FP32 ? cv.ptr<void>(N * es) : nullptr;
+    for (int b = 0; b < 3; ++b) L->lo[b] = c->precision == GKS_FP32 ? cv.ptr<void>(4 * N * es) : nullptr;
     L->diag = cv.ptr<double>(sizeof(double) * 4 * 1024);
     L->umax_part = cv.ptr<double>(sizeof(double) * UMAX_BLOCKS);
     size_t ab = alm_block_bytes(c->max_act);
@@ -220,8 +221,7 @@ int ghost_all(gks_ctx* c, void* const p[4]) {
 template <typename real>
 FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], void* const out_a[4],
                              void* const out_b[4], void* const q_c[4], void* const xt[4] = nullptr,
-                             void* const lo_in[4] = nullptr, void* const lo_a[4] = nullptr,
-                             void* const lo_b[4] = nullptr) {
+                             void* lo_in = nullptr, void* lo_a = nullptr, void* lo_b = nullptr) {
     FaceArgs<real> a;
     std::memset(&a, 0, sizeof(a));
     const int* pm = kPerm[d];
@@ -230,14 +230,9 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     for (int v = 0; v < 4; ++v) {
         const int gv = pm[v];
         a.q[v] = static_cast<const real*>(src[gv]);
-        a.r0[v] = static_cast<real*>(c->r0[gv]);
-        a.r1[v] = static_cast<real*>(c->r1[gv]);
-        a.rx0[v] = static_cast<real*>(c->rx0[gv]);
-        a.rx1[v] = static_cast<real*>(c->rx1[gv]);
+
         a.out_a[v] = static_cast<real*>(out_a[gv]);
-        a.lo_in[v] = lo_in ? static_cast<const real*>(lo_in[gv]) : nullptr;
-        a.lo_a[v] = lo_a ? static_cast<real*>(lo_a[gv]) : nullptr;
-        a.lo_b[v] = lo_b ? static_cast<real*>(lo_b[gv]) : nullptr;
+
         if (stage == 1) {
             a.out_b[v] = static_cast<real*>(out_b[gv]);
             a.q_c[v] = static_cast<const real*>(q_c[gv]);
@@ -245,6 +240,13 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
             a.s_in[v] = static_cast<const real*>(out_b[gv]);
         }
     }
+    a.r0 = static_cast<real*>(c->r0);
+    a.r1 = static_cast<real*>(c->r1);
+    a.rx0 = static_cast<real*>(c->rx0);
+    a.rx1 = static_cast<real*>(c->rx1);
+    a.lo_in = static_cast<const real*>(lo_in);
+    a.lo_a = static_cast<real*>(lo_a);
+    a.lo_b = static_cast<real*>(lo_b);
     a.n_n = c->g.n[ax[0]];
     a.n_t1 = c->g.n[ax[1]];
     a.n_t2 = c->g.n[ax[2]];
@@ -277,7 +279,7 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.fc.c2 = real(1.0 / (2.0 * c->lam));
     a.fc.mu = real(c->cfg.mu);
     a.fc.rho_ref = real(c->cfg.rho_ref);
-    for (int j = 0; j < 3; ++j) a.g_local[j] = real(c->cfg.body_force[pm[1 + j] - 1]);
+    for (int j = 0; j < 3; ++j) a.g_global[j] = real(c->cfg.body_force[j]);
     a.dt_ptr = &c->st->dt;
     // x faces write their own arrays in the blocked layout [z][y/16][x][y%16] so that the x pass
     // stores contiguous runs; the y pass writes the main arrays, the z pass accumulates both and
@@ -379,13 +381,12 @@ void tend(gks_ctx* c, int pair) {
 // FP32: zero the low-order parts of the compensated state (the state is then the field itself).
 hipError_t clear_low_parts(gks_ctx* c) {
     if (c->cfg.precision != GKS_FP32) return hipSuccess;
-    const size_t bytes = (size_t)c->cfg.nx * c->cfg.ny * c->cfg.nz * sizeof(float);
-    void* const* sets[3] = {c->lo_q, c->lo_qs, c->lo_qa};
-    for (int b = 0; b < 3; ++b)
-        for (int v = 0; v < 4; ++v) {
-            hipError_t e = hipMemsetAsync(sets[b][v], 0, bytes, c->stream);
-            if (e != hipSuccess) return e;
-        }
+    const size_t bytes = (size_t)4 * c->cfg.nx * c->cfg.ny * c->cfg.nz * sizeof(float);
+    void* const sets[3] = {c->lo_q, c->lo_qs, c->lo_qa};
+    for (int b = 0; b < 3; ++b) {
+        hipError_t e = hipMemsetAsync(sets[b], 0, bytes, c->stream);
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -514,16 +515,14 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     c->stream = static_cast<hipStream_t>(hip_stream);
     layout(cfg, c->ws, &L);
     c->st = L.st;
-    for (int v = 0; v < 4; ++v) {
-        c->r0[v] = L.r0[v];
-        c->r1[v] = L.r1[v];
-        c->rx0[v] = L.rx0[v];
-        c->rx1[v] = L.rx1[v];
-        c->qt[v] = L.qt[v];
-        c->lo_q[v] = L.lo[0][v];
-        c->lo_qs[v] = L.lo[1][v];
-        c->lo_qa[v] = L.lo[2][v];
-    }
+    for (int v = 0; v < 4; ++v) c->qt[v] = L.qt[v];
+    c->r0 = L.r0;
+    c->r1 = L.r1;
+    c->rx0 = L.rx0;
+    c->rx1 = L.rx1;
+    c->lo_q = L.lo[0];
+    c->lo_qs = L.lo[1];
+    c->lo_qa = L.lo[2];
     c->diag_partials = L.diag;
     c->umax_part = L.umax_part;
     c->alm_mem = reinterpret_cast<double*>(L.alm);

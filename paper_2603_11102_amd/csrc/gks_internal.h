@@ -18,20 +18,22 @@ constexpr int FACE_THREADS = 512;        // 8 wave64 per workgroup
 template <typename real>
 struct FaceArgs {
     const real* q[4];        // reconstructed field (padded layout)
-    real* r0[4];             // accumulator of L (interior layout), stage 1
-    real* r1[4];             // accumulator of L_t (interior layout)
-    real* rx0[4];            // x-direction contributions of L in the blocked layout [z][y/16][x][y%16]
-    real* rx1[4];            // x-direction contributions of L_t, same layout
+    // residual contributions, four variables per cell in the global order (rho', rho U, rho V, rho W):
+    real* r0;                // y pass: L (stage 1), interior layout [cell][4]
+    real* r1;                // y pass: L_t, same layout
+    real* rx0;               // x pass: L in the blocked layout [z][y/16][x][y%16][4]
+    real* rx1;               // x pass: L_t, same layout
     int rx_nx, rx_nyb;       // nx and ceil(ny / 16) of the blocked layout
     real* out_a[4];          // epilogue: stage 1 -> Q*, stage 2 -> Q^{n+1} (padded)
     real* out_b[4];          // epilogue: stage 1 -> S (padded)
     const real* s_in[4];     // epilogue: stage 2 reads S (padded)
     const real* q_c[4];      // epilogue: stage 1 reads Q^n at the cell (padded)
-    // FP32 compensated state (interior layout): the low-order parts of the stage input of the epilogue
-    // (Q^n in stage 1, S in stage 2) and of its outputs (Q* and S; Q^{n+1}); null in FP64
-    const real* lo_in[4];
-    real* lo_a[4];
-    real* lo_b[4];
+    // FP32 compensated state, interior layout [cell][4] in the global order: the low-order parts of the
+    // stage input of the epilogue (Q^n in stage 1, S in stage 2) and of its outputs (Q* and S; Q^{n+1});
+    // null in FP64
+    const real* lo_in;
+    real* lo_a;
+    real* lo_b;
     int n_n, n_t1, n_t2;     // interior cells along normal, t1, t2
     int chunk, tiles_t1, tiles_t2;
     long long st_n, st_t1, st_t2;     // padded strides
@@ -40,7 +42,7 @@ struct FaceArgs {
     real inv_hn, inv_h1, inv_h2;
     real eps;
     FluxConst<real> fc;
-    real g_local[3];                  // constant body force in local momentum order (stage 2 epilogue)
+    real g_global[3];                 // constant body force (x, y, z) for the stage-2 epilogue
     const double* dt_ptr;             // device dt of the current step
     int mode;  // 3: x pass (write the blocked x arrays), 0: y pass (write the main arrays),
                // 4: z pass (add both, S2O4 stage update)

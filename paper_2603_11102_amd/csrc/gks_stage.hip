@@ -26,6 +26,44 @@ __device__ __forceinline__ T pick(bool c, T x, T y) {
     return c ? x : y;
 }
 
+template <typename real>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
+// The pair of variables (2m, 2m + 1) of cell i in an array that holds four variables per cell.
+template <typename real>
+__device__ __forceinline__ typename Vec2<real>::type ld2(const real* p, long long i, int m) {
+    return *reinterpret_cast<const typename Vec2<real>::type*>(p + 4 * i + 2 * m);
+}
+template <typename real>
+__device__ __forceinline__ void st2(real* p, long long i, int m, typename Vec2<real>::type v) {
+    *reinterpret_cast<typename Vec2<real>::type*>(p + 4 * i + 2 * m) = v;
+}
+
+// Local index (the pass's variable order: density, normal momentum, t1, t2 momenta) of each global
+// variable (density, x, y, z momenta) for the x (MODE 3), y (MODE 0) and z (MODE 4) passes.
+template <int MODE>
+struct LocalOrder;
+template <>
+struct LocalOrder<3> {
+    static constexpr int v[4] = {0, 1, 2, 3};
+};
+template <>
+struct LocalOrder<0> {
+    static constexpr int v[4] = {0, 2, 1, 3};
+};
+template <>
+struct LocalOrder<4> {
+    static constexpr int v[4] = {0, 2, 3, 1};
+};
+
 // Error-free sum (Knuth): s + e == a + b exactly, s = fl(a + b).
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     s = a + b;
@@ -42,6 +80,9 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     // FP32: the z pass loads its epilogue operands at the top of the step (FP64 has no registers to
     // spare) and updates the compensated state (high part in the field, low part in lo_in / lo_a / lo_b)
     constexpr bool EPI_PREFETCH = sizeof(real) == 4;
+    using real2 = typename Vec2<real>::type;
+    constexpr int LOC[4] = {LocalOrder<MODE>::v[0], LocalOrder<MODE>::v[1], LocalOrder<MODE>::v[2],
+                            LocalOrder<MODE>::v[3]};
     constexpr int NT1 = TILE1 * EXT2;             // t1 items per variable (320)
     __shared__ real s_nrm[4][4][EXT2][EXT1];      // [variable][q^L, q^R, D, C]
     __shared__ real s_t1[4][5][EXT2][TILE1][2];   // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
@@ -147,8 +188,8 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     const bool hi = m != 0;
     for (int f = f0; f <= f1; ++f) {
         // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
-        real e_r0[2] = {0, 0}, e_r1[2] = {0, 0}, e_x0[2] = {0, 0}, e_x1[2] = {0, 0}, e_q[2] = {0, 0};
-        real e_lo[2] = {0, 0};
+        real2 e_r0 = {0, 0}, e_r1 = {0, 0}, e_x0 = {0, 0}, e_x1 = {0, 0}, e_lo = {0, 0};
+        real e_q[2] = {0, 0};
         if (EPI_PREFETCH && MODE == 4 && f > f0 && face_ok) {
             const int cell = f - 1;
             const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
@@ -156,18 +197,18 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)(j0 + fj) * a.st_t1 +
                                    (long long)(k0 + fk) * a.st_t2;
             const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+            e_r1 = ld2(a.r1, ridx, m);
+            e_x1 = ld2(a.rx1, xidx, m);
+            e_lo = ld2(a.lo_in, ridx, m);
+            if (NEED_F0) {
+                e_r0 = ld2(a.r0, ridx, m);
+                e_x0 = ld2(a.rx0, xidx, m);
+            }
 #pragma unroll
             for (int vv = 0; vv < 2; ++vv) {
-                e_r1[vv] = pick(hi, a.r1[2 + vv], a.r1[vv])[ridx];
-                e_x1[vv] = pick(hi, a.rx1[2 + vv], a.rx1[vv])[xidx];
-                if (NEED_F0) {
-                    e_r0[vv] = pick(hi, a.r0[2 + vv], a.r0[vv])[ridx];
-                    e_x0[vv] = pick(hi, a.rx0[2 + vv], a.rx0[vv])[xidx];
-                    e_q[vv] = pick(hi, a.q_c[2 + vv], a.q_c[vv])[pidx];
-                } else {
-                    e_q[vv] = pick(hi, a.s_in[2 + vv], a.s_in[vv])[pidx];
-                }
-                e_lo[vv] = pick(hi, a.lo_in[2 + vv], a.lo_in[vv])[ridx];
+                const real* const src = NEED_F0 ? pick(hi, a.q_c[LOC[2 + vv]], a.q_c[LOC[vv]])
+                                                : pick(hi, a.s_in[LOC[2 + vv]], a.s_in[LOC[vv]]);
+                e_q[vv] = src[pidx];
             }
         }
         // ---- column phase (all variables): window cells f-2 .. f+2, prefetch cell f+3
@@ -279,65 +320,87 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                                    (long long)(k0 + fk) * a.ist_t2;
             const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)(j0 + fj) * a.st_t1 +
                                    (long long)(k0 + fk) * a.st_t2;
-            // lane m writes variables 2m and 2m + 1. Pointers and values are picked by value with a per-lane
-            // select between compile-time indices: indexing the argument or register arrays with the
-            // lane-dependent variable index would fetch pointers from memory and move the arrays to scratch.
-#pragma unroll
-            for (int vv = 0; vv < 2; ++vv) {
-                real d1 = -(pick(hi, fa1[2 + vv], fa1[vv]) - pick(hi, fprev1[2 + vv], fprev1[vv])) * a.inv_hn;
-                real d0 = NEED_F0 ? -(pick(hi, fa0[2 + vv], fa0[vv]) - pick(hi, fprev0[2 + vv], fprev0[vv])) * a.inv_hn
-                                  : real(0);
-                real* const r1p = pick(hi, a.r1[2 + vv], a.r1[vv]);
-                real* const r0p = pick(hi, a.r0[2 + vv], a.r0[vv]);
-                if constexpr (EPI_PREFETCH && MODE == 4) {
+            // lane m owns the global variables 2m and 2m + 1 (local indices LOC[2m], LOC[2m + 1]); the
+            // residual and low-order arrays hold the four variables of a cell together, so the lane moves
+            // them as one pair. Per-variable pointers and values are picked by value with a per-lane select
+            // between compile-time indices: indexing the argument or register arrays with the
+            // lane-dependent index would fetch pointers from memory and move the arrays to scratch.
+            real2 d1, d0;
+            d1.x = -(pick(hi, fa1[LOC[2]], fa1[LOC[0]]) - pick(hi, fprev1[LOC[2]], fprev1[LOC[0]])) * a.inv_hn;
+            d1.y = -(pick(hi, fa1[LOC[3]], fa1[LOC[1]]) - pick(hi, fprev1[LOC[3]], fprev1[LOC[1]])) * a.inv_hn;
+            if (NEED_F0) {
+                d0.x = -(pick(hi, fa0[LOC[2]], fa0[LOC[0]]) - pick(hi, fprev0[LOC[2]], fprev0[LOC[0]])) * a.inv_hn;
+                d0.y = -(pick(hi, fa0[LOC[3]], fa0[LOC[1]]) - pick(hi, fprev0[LOC[3]], fprev0[LOC[1]])) * a.inv_hn;
+            } else {
+                d0.x = d0.y = real(0);
+            }
+            if constexpr (MODE == 3) {
+                const long long xidx = rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb);
+                st2(a.rx1, xidx, m, d1);
+                if (NEED_F0) st2(a.rx0, xidx, m, d0);
+            } else if constexpr (MODE == 0) {
+                st2(a.r1, ridx, m, d1);
+                if (NEED_F0) st2(a.r0, ridx, m, d0);
+            } else {
+                real2 r1v, x1v, r0v = {0, 0}, x0v = {0, 0};
+                if constexpr (EPI_PREFETCH) {
+                    r1v = e_r1;
+                    x1v = e_x1;
+                    r0v = e_r0;
+                    x0v = e_x0;
+                } else {
+                    const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+                    r1v = ld2(a.r1, ridx, m);
+                    x1v = ld2(a.rx1, xidx, m);
+                    if (NEED_F0) {
+                        r0v = ld2(a.r0, ridx, m);
+                        x0v = ld2(a.rx0, xidx, m);
+                    }
+                }
+                const real L1[2] = {r1v.x + (d1.x + x1v.x), r1v.y + (d1.y + x1v.y)};
+                const real L0[2] = {r0v.x + (d0.x + x0v.x), r0v.y + (d0.y + x0v.y)};
+                if constexpr (EPI_PREFETCH) {
                     // FP32: the state is carried as hi + lo; each update is an error-free sum of the
                     // stored high part and (low part + increment)
-                    const real L1 = e_r1[vv] + e_x1[vv] + d1;
-                    real* const outa = pick(hi, a.out_a[2 + vv], a.out_a[vv]);
-                    real* const loa = pick(hi, a.lo_a[2 + vv], a.lo_a[vv]);
-                    float sh, sl;
-                    if (NEED_F0) {
-                        const real L0 = e_r0[vv] + e_x0[vv] + d0;
-                        real* const outb = pick(hi, a.out_b[2 + vv], a.out_b[vv]);
-                        real* const lob = pick(hi, a.lo_b[2 + vv], a.lo_b[vv]);
-                        two_sum(e_q[vv], e_lo[vv] + (real(0.5) * dt * L0 + real(0.125) * dt * dt * L1), sh, sl);
-                        outa[pidx] = sh;
-                        loa[ridx] = sl;
-                        two_sum(e_q[vv], e_lo[vv] + (dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1), sh, sl);
-                        outb[pidx] = sh;
-                        lob[ridx] = sl;
-                    } else {
-                        const real gv = pick(hi, a.g_local[1 + vv], vv == 1 ? a.g_local[0] : real(0));
-                        const real add = (dt * dt * real(1.0 / 3.0)) * L1 + dt * gv;
-                        two_sum(e_q[vv], e_lo[vv] + add, sh, sl);
-                        outa[pidx] = sh;
-                        loa[ridx] = sl;
+                    const real lo[2] = {e_lo.x, e_lo.y};
+                    real2 la = {0, 0}, lb = {0, 0};
+#pragma unroll
+                    for (int vv = 0; vv < 2; ++vv) {
+                        real* const outa = pick(hi, a.out_a[LOC[2 + vv]], a.out_a[LOC[vv]]);
+                        float sh, sl;
+                        if (NEED_F0) {
+                            real* const outb = pick(hi, a.out_b[LOC[2 + vv]], a.out_b[LOC[vv]]);
+                            two_sum(e_q[vv], lo[vv] + (real(0.5) * dt * L0[vv] + real(0.125) * dt * dt * L1[vv]), sh, sl);
+                            outa[pidx] = sh;
+                            if (vv == 0) la.x = sl; else la.y = sl;
+                            two_sum(e_q[vv], lo[vv] + (dt * L0[vv] + (dt * dt * real(1.0 / 6.0)) * L1[vv]), sh, sl);
+                            outb[pidx] = sh;
+                            if (vv == 0) lb.x = sl; else lb.y = sl;
+                        } else {
+                            // body force G on the momenta (global variables 1..3)
+                            const real gv = pick(hi, a.g_global[1 + vv], vv == 1 ? a.g_global[0] : real(0));
+                            const real add = (dt * dt * real(1.0 / 3.0)) * L1[vv] + dt * gv;
+                            two_sum(e_q[vv], lo[vv] + add, sh, sl);
+                            outa[pidx] = sh;
+                            if (vv == 0) la.x = sl; else la.y = sl;
+                        }
                     }
-                    continue;
-                }
-                if constexpr (MODE == 3) {
-                    const long long xidx = rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb);
-                    pick(hi, a.rx1[2 + vv], a.rx1[vv])[xidx] = d1;
-                    if (NEED_F0) pick(hi, a.rx0[2 + vv], a.rx0[vv])[xidx] = d0;
-                } else if constexpr (MODE == 0) {
-                    r1p[ridx] = d1;
-                    if (NEED_F0) r0p[ridx] = d0;
-                } else if constexpr (!EPI_PREFETCH) {
-                    // z pass without prefetch (FP64): add both other directions and update the stage
-                    const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
-                    const real L1 = r1p[ridx] + (d1 + pick(hi, a.rx1[2 + vv], a.rx1[vv])[xidx]);
-                    real* const outa = pick(hi, a.out_a[2 + vv], a.out_a[vv]);
-                    if (NEED_F0) {
-                        const real L0 = r0p[ridx] + (d0 + pick(hi, a.rx0[2 + vv], a.rx0[vv])[xidx]);
-                        const real Q = pick(hi, a.q_c[2 + vv], a.q_c[vv])[pidx];
-                        real* const outb = pick(hi, a.out_b[2 + vv], a.out_b[vv]);
-                        outa[pidx] = Q + real(0.5) * dt * L0 + real(0.125) * dt * dt * L1;
-                        outb[pidx] = Q + dt * L0 + (dt * dt * real(1.0 / 6.0)) * L1;
-                    } else {
-                        // body force G on the momenta (variables 1..3); variable 0 (vv = 0, lane 0) has none
-                        const real gv = pick(hi, a.g_local[1 + vv], vv == 1 ? a.g_local[0] : real(0));
-                        const real add = (dt * dt * real(1.0 / 3.0)) * L1 + dt * gv;
-                        outa[pidx] = pick(hi, a.s_in[2 + vv], a.s_in[vv])[pidx] + add;
+                    st2(a.lo_a, ridx, m, la);
+                    if (NEED_F0) st2(a.lo_b, ridx, m, lb);
+                } else {
+#pragma unroll
+                    for (int vv = 0; vv < 2; ++vv) {
+                        real* const outa = pick(hi, a.out_a[LOC[2 + vv]], a.out_a[LOC[vv]]);
+                        if (NEED_F0) {
+                            const real Q = pick(hi, a.q_c[LOC[2 + vv]], a.q_c[LOC[vv]])[pidx];
+                            real* const outb = pick(hi, a.out_b[LOC[2 + vv]], a.out_b[LOC[vv]]);
+                            outa[pidx] = Q + real(0.5) * dt * L0[vv] + real(0.125) * dt * dt * L1[vv];
+                            outb[pidx] = Q + dt * L0[vv] + (dt * dt * real(1.0 / 6.0)) * L1[vv];
+                        } else {
+                            const real gv = pick(hi, a.g_global[1 + vv], vv == 1 ? a.g_global[0] : real(0));
+                            const real add = (dt * dt * real(1.0 / 3.0)) * L1[vv] + dt * gv;
+                            outa[pidx] = pick(hi, a.s_in[LOC[2 + vv]], a.s_in[LOC[vv]])[pidx] + add;
+                        }
                     }
                 }
             }
