@@ -409,10 +409,9 @@ int steps(gks_ctx* c, int nsteps) {
             c->ckpt_n++;
         }
         tp = tbeg(c, GKS_TIMER_GHOST);
-        int rc = ghost_all<real>(c, c->q);
-        if (!rc) HIPCHK(c, launch_transpose_xy<real>(field<real>(c->q), field<real>(c->qt), c->g, c->stream));
+        HIPCHK(c, launch_ghost_transpose<real>(field<real>(c->q), field<real>(c->qt), c->g, c->cfg.bc, c->cfg.u_in,
+                                               c->c, c->cfg.rho_ref, c->stream));
         tend(c, tp);
-        if (rc) return rc;
         tp = tbeg(c, GKS_TIMER_DT);
         if (c->cfg.cfl > 0) HIPCHK(c, launch_umax<real>(field<real>(c->q), c->g, c->cfg.rho_ref, c->umax_part, c->stream));
         HIPCHK(c, launch_dt(c->st, c->umax_part, umax_blocks(c->g), c->cfg.cfl, c->hmin, c->c, c->cfg.dt_fixed,
@@ -424,10 +423,9 @@ int steps(gks_ctx* c, int nsteps) {
             tend(c, tp);
         }
         tp = tbeg(c, GKS_TIMER_GHOST);
-        rc = ghost_all<real>(c, c->qs);
-        if (!rc) HIPCHK(c, launch_transpose_xy<real>(field<real>(c->qs), field<real>(c->qt), c->g, c->stream));
+        HIPCHK(c, launch_ghost_transpose<real>(field<real>(c->qs), field<real>(c->qt), c->g, c->cfg.bc, c->cfg.u_in,
+                                               c->c, c->cfg.rho_ref, c->stream));
         tend(c, tp);
-        if (rc) return rc;
         for (int d = 0; d < 3; ++d) {
             tp = tbeg(c, cat2[d]);
             HIPCHK(c, launch_face<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream));

@@ -6,6 +6,7 @@
 // isothermal Riemann invariant U -+ C ln rho; zero-gradient outflow. Axes are filled x, then y, then z
 // over the full padded extent of the other axes, so edges and corners are consistent.
 // Time step: dt = CFL min(dx, dy, dz) / (|U|_max + C), C = sqrt(1/(2 lambda)) (Section 2).
+#include "gks.h"
 #include "gks_internal.h"
 
 namespace gks {
@@ -110,6 +111,107 @@ __global__ void __launch_bounds__(256) umax_kernel(Field4<real> f, GridDesc g, d
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// One launch for the ghost cells of all three axes and the [x][z][y] copy of the padded field.
+// A ghost cell takes the value the axis-by-axis fill (x, then y, then z, over the full padded extent
+// of the other axes) leaves there: the interior source cell is found per axis, then the boundary
+// transforms of the ghost axes are applied in the order x, y, z, with the same arithmetic and the same
+// rounding to the field's precision after each transform.
+struct GhostAll {
+    int n[3];
+    int bc_lo[3], bc_hi[3];
+    double u_in[3];
+    double c, rho_ref;
+};
+
+// interior source index along one axis and the transform to apply (-1: none, else side 0 / 1)
+__device__ __forceinline__ int ghost_source(int i, int n, int lo, int hi, int& side) {
+    if (i >= 0 && i < n) {
+        side = -1;
+        return i;
+    }
+    side = i < 0 ? 0 : 1;
+    const int kind = side == 0 ? lo : hi;
+    if (kind == GKS_BC_PERIODIC) return side == 0 ? n + i : i - n;
+    if (kind == GKS_BC_NOSLIP_WALL || kind == GKS_BC_SLIP_WALL) return side == 0 ? -1 - i : 2 * n - 1 - i;
+    return side == 0 ? 0 : n - 1;  // inflow, outflow: the adjacent interior cell
+}
+
+template <typename real>
+__device__ __forceinline__ void ghost_transform(real v[4], int axis, int side, int kind, const GhostAll& G) {
+    if (kind == GKS_BC_NOSLIP_WALL) {
+        for (int j = 1; j < 4; ++j) v[j] = -v[j];
+    } else if (kind == GKS_BC_SLIP_WALL) {
+        v[1 + axis] = -v[1 + axis];
+    } else if (kind == GKS_BC_INFLOW) {
+        const double rp = (double)v[0];
+        const double rho_i = G.rho_ref + rp;
+        const double un = (double)v[1 + axis] / rho_i;
+        const double x = side == 0 ? (G.u_in[axis] - un) / G.c : (un - G.u_in[axis]) / G.c;
+        const double rho_g = rho_i * exp(x);
+        v[0] = (real)(rp * exp(x) + G.rho_ref * expm1(x));
+        for (int j = 0; j < 3; ++j) v[1 + j] = (real)(rho_g * G.u_in[j]);
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) ghost_transpose_kernel(Field4<real> q, Field4<real> qt, GhostAll G) {
+    __shared__ real t[4][32][33];
+    const int X = G.n[0] + 6, Y = G.n[1] + 6, Z = G.n[2] + 6;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+#pragma unroll
+    for (int r = ty; r < 32; r += 8) {
+        const int x = x0 + tx, y = y0 + r;
+        if (x >= X || y >= Y) continue;
+        const long long dst = ((long long)z * Y + y) * X + x;
+        int sd[3];
+        const int si = ghost_source(x - 3, G.n[0], G.bc_lo[0], G.bc_hi[0], sd[0]);
+        const int sj = ghost_source(y - 3, G.n[1], G.bc_lo[1], G.bc_hi[1], sd[1]);
+        const int sk = ghost_source(z - 3, G.n[2], G.bc_lo[2], G.bc_hi[2], sd[2]);
+        real v[4];
+        if (sd[0] < 0 && sd[1] < 0 && sd[2] < 0) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v[w] = q.v[w][dst];
+        } else {
+            const long long src = ((long long)(sk + 3) * Y + (sj + 3)) * X + (si + 3);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v[w] = q.v[w][src];
+            for (int a = 0; a < 3; ++a)
+                if (sd[a] >= 0) ghost_transform(v, a, sd[a], sd[a] == 0 ? G.bc_lo[a] : G.bc_hi[a], G);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) q.v[w][dst] = v[w];
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) t[w][r][tx] = v[w];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int r = ty; r < 32; r += 8) {
+            const int y = y0 + tx, x = x0 + r;
+            if (x < X && y < Y) qt.v[w][((long long)x * Z + z) * Y + y] = t[w][tx][r];
+        }
+}
+
+template <typename real>
+hipError_t launch_ghost_transpose(Field4<real> q, Field4<real> qt, const GridDesc& gd, const int bc[6],
+                                  const double u_in[3], double c, double rho_ref, hipStream_t s) {
+    GhostAll G;
+    for (int a = 0; a < 3; ++a) {
+        G.n[a] = gd.n[a];
+        G.bc_lo[a] = bc[2 * a];
+        G.bc_hi[a] = bc[2 * a + 1];
+        G.u_in[a] = u_in[a];
+    }
+    G.c = c;
+    G.rho_ref = rho_ref;
+    const int X = gd.n[0] + 6, Y = gd.n[1] + 6, Z = gd.n[2] + 6;
+    hipLaunchKernelGGL((ghost_transpose_kernel<real>), dim3((X + 31) / 32, (Y + 31) / 32, Z), dim3(256), 0, s, q,
+                       qt, G);
+    return hipGetLastError();
 }
 
 // Copy of a padded field in the layout [x][z][y] (y fastest), read by the x-direction face pass so that
@@ -324,6 +426,8 @@ hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream
 
 template hipError_t launch_ghost<float>(Field4<float>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
 template hipError_t launch_ghost<double>(Field4<double>, const GridDesc&, int, int, int, const double*, double, double, hipStream_t);
+template hipError_t launch_ghost_transpose<float>(Field4<float>, Field4<float>, const GridDesc&, const int[6], const double[3], double, double, hipStream_t);
+template hipError_t launch_ghost_transpose<double>(Field4<double>, Field4<double>, const GridDesc&, const int[6], const double[3], double, double, hipStream_t);
 template hipError_t launch_transpose_xy<float>(Field4<float>, Field4<float>, const GridDesc&, hipStream_t);
 template hipError_t launch_transpose_xy<double>(Field4<double>, Field4<double>, const GridDesc&, hipStream_t);
 template hipError_t launch_umax<float>(Field4<float>, const GridDesc&, double, double*, hipStream_t);

@@ -102,6 +102,9 @@ hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, double
 int umax_blocks(const GridDesc& g);
 template <typename real>
 hipError_t launch_transpose_xy(Field4<real> in, Field4<real> out, const GridDesc& g, hipStream_t s);
+template <typename real>
+hipError_t launch_ghost_transpose(Field4<real> q, Field4<real> qt, const GridDesc& gd, const int bc[6],
+                                  const double u_in[3], double c, double rho_ref, hipStream_t s);
 hipError_t launch_dt(DevState* st, const double* part, int nparts, double cfl, double hmin, double c,
                      double dt_fixed, hipStream_t s);
 hipError_t launch_finish(DevState* st, int has_rotor, double* hist, hipStream_t s);
