@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # "bench.py --steps 2 --warmup 1 --no-fp64 --no-cpu-baseline", each scaled by what the same counter reads
 # for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024": FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
 # The figure belongs to the kernel sources it was measured on; bench reports null once they differ.
-TRAFFIC = {"sources_sha256": "e535c7cdb8283fc20c1fcb666383cb9e3eed1acc4a75eb85a8bf6a5a29eb145e",
-           "fetch_bytes": 236_412_382, "write_bytes": 67_674_842}
+TRAFFIC = {"sources_sha256": "bb647efd0c5564b0064bee578867c8736829c712a2dc760b7bcea70b7dc5a335",
+           "fetch_bytes": 225_849_719, "write_bytes": 84_934_656}
 KERNEL_SOURCES = ("gks_stage.hip", "gks_device.h", "gks_internal.h")
 
 
@@ -210,8 +210,8 @@ def main():
         "config": {"workload": f"{args.case} {cfg.nx}x{cfg.ny}x{cfg.nz} ({n} cells), "
                                f"{'FP32, density as deviation from rho_ref' if args.precision == 'fp32' else 'FP64'}",
                    "cells": n, "bc": list(cfg.bc), "ma": cfg.ma},
-        "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'},1> "
-                                                "(stage 1, mean over the x, y, z launches)",
+        "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'}, 1, "
+                                                "3 | 0 | 4> (stage 1: mean over the x, y, z launches)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.case, args.precision), "avg_launch_ms": avg_launch_ms,
                      "algorithmic_flop_per_launch": flops_launch},
