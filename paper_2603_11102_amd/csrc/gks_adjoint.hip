@@ -220,18 +220,18 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
 // pass B: transpose of the t2 sweep -> adjoints of the t1 line values (q^L_m, q^R_m, D_m, Ct1_m, C_m)
 // ------------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
-    const long long total = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 2;
+    // one thread per (t1 line position, variable, Gauss line m, t2 position incl. halo, face);
+    // the t1 position is the fastest index so that a wave reads contiguous runs of every plane
+    const long long total = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 8 * a.n_t1;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int m = (int)(t & 1);
-    long long r_ = t >> 1;
-    const int j = (int)(r_ % a.n_t1);
-    r_ /= a.n_t1;
+    const int j = (int)(t % a.n_t1);
+    long long r_ = t / a.n_t1;
+    const int vm = (int)(r_ % 8);  // v * 2 + m
+    r_ /= 8;
     const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
     const int f = (int)(r_ / (a.n_t2 + 4));
-    double bar[4][5];
-    for (int v = 0; v < 4; ++v)
-        for (int q = 0; q < 5; ++q) bar[v][q] = 0.0;
+    double bar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = max(0, kx - 2); k <= min(a.n_t2 - 1, kx + 2); ++k) {
         const int r = kx - k + 2;
         const long long fi = face_ix(a, f, j, k);
@@ -239,24 +239,21 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
             const int side = n == 0 ? 2 : 3;
             const int s = n == 0 ? -1 : 1;
             const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h2;
-            for (int v = 0; v < 4; ++v) {
-                const long long gbase = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
-                double wL[3], wR[3];
-                for (int kk = 0; kk < 3; ++kk) {
-                    wL[kk] = a.w_t2[((((v * 2 + m) * 2 + 0) * 2 + n) * 3 + kk) * a.nface + fi];
-                    wR[kk] = a.w_t2[((((v * 2 + m) * 2 + 1) * 2 + n) * 3 + kk) * a.nface + fi];
-                }
-                bar[v][0] += weno_eff(side, wL, r) * a.gpbar[gbase];
-                bar[v][1] += weno_eff(side, wR, r) * a.gpbar[gbase + a.nface];
-                bar[v][2] += cv * a.gpbar[gbase + 2 * a.nface];
-                bar[v][3] += cv * a.gpbar[gbase + 3 * a.nface];
-                bar[v][4] += cd * a.gpbar[gbase + 4 * a.nface];
+            const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
+            double wL[3], wR[3];
+            for (int kk = 0; kk < 3; ++kk) {
+                wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * 3 + kk) * a.nface + fi];
+                wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * 3 + kk) * a.nface + fi];
             }
+            bar[0] += weno_eff(side, wL, r) * a.gpbar[gbase];
+            bar[1] += weno_eff(side, wR, r) * a.gpbar[gbase + a.nface];
+            bar[2] += cv * a.gpbar[gbase + 2 * a.nface];
+            bar[3] += cv * a.gpbar[gbase + 3 * a.nface];
+            bar[4] += cd * a.gpbar[gbase + 4 * a.nface];
         }
     }
     const long long p = t1_ix(a, f, j, kx);
-    for (int v = 0; v < 4; ++v)
-        for (int q = 0; q < 5; ++q) a.t1bar[(long long)((v * 2 + m) * 5 + q) * a.nt1pos + p] = bar[v][q];
+    for (int q = 0; q < 5; ++q) a.t1bar[(long long)(vm * 5 + q) * a.nt1pos + p] = bar[q];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -264,18 +261,17 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
 // position (tangential halo included)
 // ------------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
-    const long long total = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    // one thread per (t1 position incl. halo, variable, t2 position incl. halo, face)
+    const long long total = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 4 * (a.n_t1 + 4);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int jx = (int)(t % (a.n_t1 + 4)) - 2;
     long long r_ = t / (a.n_t1 + 4);
+    const int v = (int)(r_ % 4);
+    r_ /= 4;
     const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
     const int f = (int)(r_ / (a.n_t2 + 4));
-    double bar[4][3], Cb[4];
-    for (int v = 0; v < 4; ++v) {
-        Cb[v] = 0.0;
-        for (int q = 0; q < 3; ++q) bar[v][q] = 0.0;
-    }
+    double bar[3] = {0.0, 0.0, 0.0}, Cb = 0.0;
     for (int j = max(0, jx - 2); j <= min(a.n_t1 - 1, jx + 2); ++j) {
         const int r = jx - j + 2;
         const long long p = t1_ix(a, f, j, kx);
@@ -283,27 +279,23 @@ __global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
             const int side = m == 0 ? 2 : 3;
             const int s = m == 0 ? -1 : 1;
             const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h1;
-            for (int v = 0; v < 4; ++v) {
-                const long long tb = (long long)((v * 2 + m) * 5) * a.nt1pos + p;
-                double wL[3], wR[3];
-                for (int kk = 0; kk < 3; ++kk) {
-                    wL[kk] = a.w_t1[(((v * 2 + 0) * 2 + m) * 3 + kk) * a.nt1pos + p];
-                    wR[kk] = a.w_t1[(((v * 2 + 1) * 2 + m) * 3 + kk) * a.nt1pos + p];
-                }
-                bar[v][0] += weno_eff(side, wL, r) * a.t1bar[tb];
-                bar[v][1] += weno_eff(side, wR, r) * a.t1bar[tb + a.nt1pos];
-                bar[v][2] += cv * a.t1bar[tb + 2 * a.nt1pos];
-                Cb[v] += cd * a.t1bar[tb + 3 * a.nt1pos];
-                Cb[v] += cv * a.t1bar[tb + 4 * a.nt1pos];
+            const long long tb = (long long)((v * 2 + m) * 5) * a.nt1pos + p;
+            double wL[3], wR[3];
+            for (int kk = 0; kk < 3; ++kk) {
+                wL[kk] = a.w_t1[(((v * 2 + 0) * 2 + m) * 3 + kk) * a.nt1pos + p];
+                wR[kk] = a.w_t1[(((v * 2 + 1) * 2 + m) * 3 + kk) * a.nt1pos + p];
             }
+            bar[0] += weno_eff(side, wL, r) * a.t1bar[tb];
+            bar[1] += weno_eff(side, wR, r) * a.t1bar[tb + a.nt1pos];
+            bar[2] += cv * a.t1bar[tb + 2 * a.nt1pos];
+            Cb += cd * a.t1bar[tb + 3 * a.nt1pos];
+            Cb += cv * a.t1bar[tb + 4 * a.nt1pos];
         }
     }
     const long long p = n_ix(a, f, jx, kx);
-    for (int v = 0; v < 4; ++v) {
-        a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[v][0] + 0.5 * Cb[v];
-        a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[v][1] + 0.5 * Cb[v];
-        a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[v][2];
-    }
+    a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[0] + 0.5 * Cb;
+    a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[1] + 0.5 * Cb;
+    a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[2];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -356,9 +348,9 @@ hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) 
         hipLaunchKernelGGL((adj_face_kernel<1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL((adj_face_kernel<2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
-    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 2;
+    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 8;
     hipLaunchKernelGGL(adj_t2_kernel, dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
-    const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4) * 4;
     hipLaunchKernelGGL(adj_t1_kernel, dim3((unsigned)((nC + 255) / 256)), dim3(256), 0, s, a);
     const long long nD = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
     hipLaunchKernelGGL(adj_normal_kernel, dim3((unsigned)((nD + 255) / 256)), dim3(256), 0, s, a);

@@ -102,3 +102,20 @@ def test_solver_refuses_without_gpu():
     from synth import make_case
     with pytest.raises(RuntimeError):
         GksSolver(make_case("tgv", grid=(8, 8, 8)))
+
+
+def test_field_changed_null_rejected():
+    lib = L.load()
+    assert lib.gks_field_changed(None) == L.GKS_E_INVALID_ARG
+
+
+def test_oversized_axis_rejected():
+    lib = L.load()
+    assert lib.gks_workspace_bytes(C.byref(_cfg(nx=70000, ny=3, nz=3))) == 0
+
+
+def test_fp32_workspace_holds_the_low_order_state():
+    # FP32 carries Q^n, Q* and S with a low-order part of four variables per cell each
+    lib = L.load()
+    a = lib.gks_workspace_bytes(C.byref(_cfg()))
+    assert a >= (2 + 3) * 4 * 16 ** 3 * 4

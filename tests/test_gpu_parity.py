@@ -175,3 +175,32 @@ def test_ibm_moving_points_fp64_vs_oracle():
         ref_f = b["ibm"]["body_force"].numpy()
         assert np.allclose(g["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())
         assert abs(g["ibm_residual"] - float(b["ibm"]["residual"])) < 1e-12 * max(1.0, float(b["ibm"]["residual"]))
+
+
+def test_field_changed_resets_the_compensated_state():
+    # overwriting the field through the binding clears the FP32 low-order part: the run that restarts
+    # from q0 must reproduce a fresh run bitwise
+    cfg = make_case("channel", grid=(24, 20, 18))
+    print_case("field-changed", grid=(24, 20, 18))
+    from paper_2603_11102_amd import GksSolver
+    a = GksSolver(cfg, precision="fp32")
+    a.step(3)
+    a.set_interior(cfg.q0)
+    a.reset_window()
+    a.step(3)
+    b = GksSolver(cfg, precision="fp32")
+    b.step(3)
+    assert torch.equal(a.interior(), b.interior())
+
+
+def test_ibm_rejects_non_finite_velocity():
+    from synth.cases import IbmSpec
+    from paper_2603_11102_amd import GksSolver
+    from paper_2603_11102_amd._lib import GksError
+    cfg = make_case("alm_ibm", grid=(64, 32, 32))
+    print_case("ibm-bad-velocity")
+    s = GksSolver(cfg.with_(ibm=None), precision="fp32", max_ibm=cfg.ibm.n)
+    vel = np.zeros((cfg.ibm.n, 3))
+    vel[5, 1] = np.nan
+    with pytest.raises(GksError):
+        s.set_ibm(IbmSpec(xyz=cfg.ibm.xyz, dS=cfg.ibm.dS, vel=vel))
