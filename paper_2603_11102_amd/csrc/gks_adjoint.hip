@@ -28,7 +28,8 @@ __device__ __forceinline__ long long n_ix(const AdjFaceArgs& a, int f, int jx, i
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
-// pass A: recompute the face pipeline of one direction, store frozen weights and Gauss-point adjoints
+// pass A: recompute the face pipeline of one direction, store the frozen weights and the Gauss-point
+// states (in the gpbar slots)
 // ------------------------------------------------------------------------------------------------
 template <int STAGE>
 __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArgs a) {
@@ -90,7 +91,11 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                 ring[v][4] = a.q[v][idx];
             }
         }
-        double gp[4][2][5];
+        // Gauss-point states of this face go to the gpbar slots; adj_gp_kernel turns them into adjoints
+        const long long fi_own = face_ok ? face_ix(a, f, j0 + fj, k0 + fk) : 0;
+        auto put = [&](int v, int n, int q, double val) {
+            if (face_ok) a.gpbar[(long long)(((v * 2 + m) * 2 + n) * 5 + q) * a.nface + fi_own] = val;
+        };
 
         auto column = [&](int v) {
             if (col) {
@@ -153,8 +158,8 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                 const long long fi = face_ok ? face_ix(a, f, j0 + fj, k0 + fk) : 0;
                 for (int side = 0; side < 2; ++side) {
                     weno_gauss_w<double>(y[side][0], y[side][1], y[side][2], y[side][3], y[side][4], eps, vm, vp, wm, wp);
-                    gp[v][0][side] = vm;
-                    gp[v][1][side] = vp;
+                    put(v, 0, side, vm);
+                    put(v, 1, side, vp);
                     if (face_ok)
                         for (int kk = 0; kk < 3; ++kk) {
                             a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 0) * 3 + kk) * a.nface + fi] = wm[kk];
@@ -162,57 +167,71 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                         }
                 }
                 quartic_gauss_value<double>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
-                gp[v][0][2] = vm;
-                gp[v][1][2] = vp;
+                put(v, 0, 2, vm);
+                put(v, 1, 2, vp);
                 quartic_gauss_value<double>(y[3][0], y[3][1], y[3][2], y[3][3], y[3][4], vm, vp);
-                gp[v][0][3] = vm;
-                gp[v][1][3] = vp;
+                put(v, 0, 3, vm);
+                put(v, 1, 3, vp);
                 quartic_gauss_deriv<double>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
-                gp[v][0][4] = vm * a.inv_h2;
-                gp[v][1][4] = vp * a.inv_h2;
+                put(v, 0, 4, vm * a.inv_h2);
+                put(v, 1, 4, vp * a.inv_h2);
             }
             if (v < 3) column(v + 1);
             __syncthreads();
         }
 
-        if (face_ok) {
-            // seeds of the face flux: L(i) = -(F(i+1/2) - F(i-1/2))/h  =>  Fbar(f) = (mu(f) - mu(f-1))/h
-            const long long jk = (long long)(j0 + fj) * a.ist_t1 + (long long)(k0 + fk) * a.ist_t2;
-            double b0[4], b1[4];
-            for (int v = 0; v < 4; ++v) {
-                const double hi1 = f < a.n_n ? a.mu1[v][(long long)f * a.ist_n + jk] : 0.0;
-                const double lo1 = f >= 1 ? a.mu1[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
-                b1[v] = (hi1 - lo1) * a.inv_hn;
-                if (NEED_F0) {
-                    const double hi0 = f < a.n_n ? a.mu0[v][(long long)f * a.ist_n + jk] : 0.0;
-                    const double lo0 = f >= 1 ? a.mu0[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
-                    b0[v] = (hi0 - lo0) * a.inv_hn;
-                } else {
-                    b0[v] = 0.0;
-                }
-            }
-            const long long fi = face_ix(a, f, j0 + fj, k0 + fk);
-            for (int n = 0; n < 2; ++n) {
-                double qL[4], qR[4], g[3][4], qLb[4] = {0, 0, 0, 0}, qRb[4] = {0, 0, 0, 0};
-                double gb[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-                for (int v = 0; v < 4; ++v) {
-                    qL[v] = gp[v][n][0];
-                    qR[v] = gp[v][n][1];
-                    g[0][v] = gp[v][n][2];
-                    g[1][v] = gp[v][n][3];
-                    g[2][v] = gp[v][n][4];
-                }
-                gp_flux_adj<NEED_F0>(qL, qR, g, a.fc, 0.25, b0, b1, qLb, qRb, gb);
-                for (int v = 0; v < 4; ++v) {
-                    const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
-                    a.gpbar[base] = qLb[v];
-                    a.gpbar[base + a.nface] = qRb[v];
-                    a.gpbar[base + 2 * a.nface] = gb[0][v];
-                    a.gpbar[base + 3 * a.nface] = gb[1][v];
-                    a.gpbar[base + 4 * a.nface] = gb[2][v];
-                }
-            }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// pass A2: adjoint of the gas-kinetic flux at one Gauss point per thread. Reads the point's state from
+// its gpbar slots (written by pass A) and overwrites them with the adjoints of that state.
+// ------------------------------------------------------------------------------------------------
+template <int STAGE>
+__global__ void __launch_bounds__(256) adj_gp_kernel(const AdjFaceArgs a) {
+    constexpr bool NEED_F0 = (STAGE == 1);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * a.nface) return;
+    const long long fi = t % a.nface;
+    const int mn = (int)(t / a.nface);
+    const int m = mn & 1, n = mn >> 1;
+    const int j = (int)(fi % a.n_t1);
+    const long long r_ = fi / a.n_t1;
+    const int k = (int)(r_ % a.n_t2);
+    const int f = (int)(r_ / a.n_t2);
+    // seeds of the face flux: L(i) = -(F(i+1/2) - F(i-1/2))/h  =>  Fbar(f) = (mu(f) - mu(f-1))/h
+    const long long jk = (long long)j * a.ist_t1 + (long long)k * a.ist_t2;
+    double b0[4], b1[4];
+    for (int v = 0; v < 4; ++v) {
+        const double hi1 = f < a.n_n ? a.mu1[v][(long long)f * a.ist_n + jk] : 0.0;
+        const double lo1 = f >= 1 ? a.mu1[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
+        b1[v] = (hi1 - lo1) * a.inv_hn;
+        if (NEED_F0) {
+            const double hi0 = f < a.n_n ? a.mu0[v][(long long)f * a.ist_n + jk] : 0.0;
+            const double lo0 = f >= 1 ? a.mu0[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
+            b0[v] = (hi0 - lo0) * a.inv_hn;
+        } else {
+            b0[v] = 0.0;
         }
+    }
+    double qL[4], qR[4], g[3][4], qLb[4] = {0, 0, 0, 0}, qRb[4] = {0, 0, 0, 0};
+    double gb[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int v = 0; v < 4; ++v) {
+        const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
+        qL[v] = a.gpbar[base];
+        qR[v] = a.gpbar[base + a.nface];
+        g[0][v] = a.gpbar[base + 2 * a.nface];
+        g[1][v] = a.gpbar[base + 3 * a.nface];
+        g[2][v] = a.gpbar[base + 4 * a.nface];
+    }
+    gp_flux_adj<NEED_F0>(qL, qR, g, a.fc, 0.25, b0, b1, qLb, qRb, gb);
+    for (int v = 0; v < 4; ++v) {
+        const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
+        a.gpbar[base] = qLb[v];
+        a.gpbar[base + a.nface] = qRb[v];
+        a.gpbar[base + 2 * a.nface] = gb[0][v];
+        a.gpbar[base + 3 * a.nface] = gb[1][v];
+        a.gpbar[base + 4 * a.nface] = gb[2][v];
     }
 }
 
@@ -344,10 +363,14 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
 hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
     const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
-    if (stage == 1)
+    const long long nA = 4 * a.nface;
+    if (stage == 1) {
         hipLaunchKernelGGL((adj_face_kernel<1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
-    else
+        hipLaunchKernelGGL((adj_gp_kernel<1>), dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, s, a);
+    } else {
         hipLaunchKernelGGL((adj_face_kernel<2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
+        hipLaunchKernelGGL((adj_gp_kernel<2>), dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, s, a);
+    }
     const long long nB = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 8;
     hipLaunchKernelGGL(adj_t2_kernel, dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
     const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4) * 4;
