@@ -46,6 +46,13 @@ R13 Statistics: the printed RMS <sqrt((phi - <phi>)^2)> is read as sqrt(<(phi - 
 R10 IBM: Peskin 4-point delta, tensor product, in both directions; fixed iteration count; points at
     fixed positions (the paper's bodies are stationary; prescribed point velocities v_p are allowed);
     residual max_p |v_p - U_p| reported after the last iteration.
+R15 Second-order GKS (the comparison scheme of Section 4.3.3; the paper defers its definition to
+    earlier work): the same gas-kinetic flux and S2O4 stages with a second-order reconstruction,
+    component-wise on the conservative variables: face states from van Leer-limited slopes,
+    q^L = q_{i} + s_i/2, q^R = q_{i+1} - s_{i+1}/2, s = vL(q_i - q_{i-1}, q_{i+1} - q_i) with
+    vL(a, b) = 2ab/(a + b) for ab > 0 and 0 otherwise; equilibrium-state gradients from central
+    differences: normal (q_{i+1} - q_i)/h, tangential of the face average C = (q_i + q_{i+1})/2 over
+    the neighbouring faces, (C_{j+1} - C_{j-1})/(2h); one flux evaluation at the face centre.
 R14 IBM velocity at the cells: the printed v-bar = sum_p W v_p is read with the volume weighting of
     V-bar, v-bar = sum_p W V_p v_p / V-bar, so that it is a velocity (a uniform v_p gives v-bar = v_p;
     stationary points give 0 as in the paper).
@@ -69,7 +76,7 @@ __all__ = [
     "linear_point", "constants", "ghost_fill", "kinetic_average", "maxwellian_moment",
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
-    "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics",
+    "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics", "van_leer", "muscl_faces",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -446,6 +453,48 @@ def _direction(P, d, cfg, lam, need_f0, ctl, chunk):
     return L0, L1
 
 
+def van_leer(dm, dp):
+    """van Leer's limited slope of two one-sided differences: 2 dm dp / (dm + dp) when they have the same
+    sign, else 0 (reading R15)."""
+    prod = dm * dp
+    den = torch.where(prod > 0, dm + dp, torch.ones_like(dm))
+    return torch.where(prod > 0, 2.0 * prod / den, torch.zeros_like(dm))
+
+
+def muscl_faces(qm2, qm1, q0, qp1):
+    """Left and right states at the face between cells -1 and 0 from the limited linear profiles of
+    cells -1 and 0 (reading R15)."""
+    qL = qm1 + 0.5 * van_leer(qm1 - qm2, q0 - qm1)
+    qR = q0 - 0.5 * van_leer(q0 - qm1, qp1 - q0)
+    return qL, qR
+
+
+def _direction_order2(P, d, cfg, lam, need_f0):
+    """Second-order variant (reading R15): limited linear face states, central-difference gradients,
+    one flux evaluation at the face centre."""
+    hn, h1, h2 = _spacings(cfg, d)
+    A = _local(P, d)
+    T2, T1, N = A.shape[1] - 2 * NG, A.shape[2] - 2 * NG, A.shape[3] - 2 * NG
+
+    def cell(rel, dj=0, dk=0):
+        # cells f + rel for the faces f = 0..N (face f lies between cells f - 1 and f), shifted in t1, t2
+        return A[:, NG + dk:NG + dk + T2, NG + dj:NG + dj + T1, NG + rel:NG + rel + N + 1]
+
+    qL, qR = muscl_faces(cell(-2), cell(-1), cell(0), cell(1))
+    dn = (cell(0) - cell(-1)) / hn
+
+    def face_avg(dj, dk):
+        return 0.5 * (cell(-1, dj, dk) + cell(0, dj, dk))
+
+    dt1 = (face_avg(1, 0) - face_avg(-1, 0)) / (2.0 * h1)
+    dt2 = (face_avg(0, 1) - face_avg(0, -1)) / (2.0 * h2)
+    Q0 = kinetic_average(qL, qR, d, lam)
+    F0, F1 = gks_point_flux(Q0, _grads_global(d, dn, dt1, dt2), d, lam, cfg.mu, need_f0)
+    L1 = _global(-(F1[..., 1:] - F1[..., :-1]) / hn, d)
+    L0 = _global(-(F0[..., 1:] - F0[..., :-1]) / hn, d) if need_f0 else None
+    return L0, L1
+
+
 def operator(Q, cfg, need_f0=True, ctl=None, chunk=64):
     """L(Q) = -(1/|Omega|) sum over the six faces of the face flux at t (Eq. (finite)) and its time
     derivative; with f linear in t these are the face averages of F0 and F1."""
@@ -453,8 +502,12 @@ def operator(Q, cfg, need_f0=True, ctl=None, chunk=64):
     P = ghost_fill(Q, cfg)
     L0 = 0.0 if need_f0 else None
     L1 = 0.0
+    order = getattr(cfg, "order", 5)
     for d in range(3):
-        a, b = _direction(P, d, cfg, lam, need_f0, ctl, chunk)
+        if order == 2:
+            a, b = _direction_order2(P, d, cfg, lam, need_f0)
+        else:
+            a, b = _direction(P, d, cfg, lam, need_f0, ctl, chunk)
         L1 = L1 + b
         if need_f0:
             L0 = L0 + a

@@ -96,6 +96,7 @@ class CaseConfig:
     body_force: tuple = (0.0, 0.0, 0.0)
     weno_eps: float = 1e-6
     ibm_iters: int = 3
+    order: int = 5  # 5: WENO-JS to 2x2 Gauss points (the high-order GKS); 2: the second-order variant
     steps: int = 10
     rotor: Optional[RotorSpec] = None
     ibm: Optional[IbmSpec] = None
