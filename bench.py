@@ -153,6 +153,8 @@ def main():
                     help="z-planes of the field the CPU oracle steps once (all of them by default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--order", type=int, default=5, choices=(2, 5),
+                    help="5: the high-order GKS (default); 2: the second-order variant (own JSON line)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the adjoint against its checkpointed forward window and print that line")
     args = ap.parse_args()
@@ -179,8 +181,8 @@ def main():
         sys.exit(2)
     import torch
     from synth import make_case
-    cfg = make_case(args.case)
-    print(f"[bench] case={args.case} grid={cfg.nx}x{cfg.ny}x{cfg.nz} precision={args.precision} "
+    cfg = make_case(args.case).with_(order=args.order)
+    print(f"[bench] case={args.case} order={args.order} grid={cfg.nx}x{cfg.ny}x{cfg.nz} precision={args.precision} "
           f"steps={args.steps} warmup={args.warmup}", flush=True)
     s, ms, ms_t, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup)
     n = cfg.n_cells
@@ -194,6 +196,7 @@ def main():
     flops_launch = FLOP_STAGE1_PER_CELL_DIR * n
     achieved = flops_launch / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    es = 4 if args.precision == "fp32" else 8
     result = {
         "metric": "cell-updates/s per S2O4 step",
         "value": value,
@@ -218,6 +221,22 @@ def main():
         "per_category_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
         "flop_per_cell_step": FLOP_PER_CELL_STEP,
     }
+    if args.order == 2:
+        # second-order variant: a few hundred flops per cell and direction against the same memory
+        # traffic as the high-order pass, so the HBM roofline is the reference. Algorithmic bytes per
+        # cell of a stage-1 launch (FP32): x and y read the field (16) and write L, L_t (32); z reads
+        # the field, both residuals (64), Q^n and its low-order part (32) and writes Q*, S and their
+        # low-order parts (64); FP64 has no low-order parts.
+        per_cell = ((48 + 48 + 176) / 3.0) if args.precision == "fp32" else ((96 + 96 + 288) / 3.0)
+        bytes_launch = per_cell * n
+        result["metric"] = "cell-updates/s per S2O4 step (second-order variant)"
+        result["config"]["workload"] += ", second-order GKS"
+        result["roofline"] = {"bound": "hbm", "kernel": f"face2_kernel<{'float' if es == 4 else 'double'}, 1, "
+                                                        "3 | 0 | 4> (stage 1: mean over the x, y, z launches)",
+                              "achieved": bytes_launch / (avg_launch_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                              "unit": "GB/s", "frac": bytes_launch / (avg_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                              "traffic": None, "avg_launch_ms": avg_launch_ms,
+                              "algorithmic_bytes_per_launch": bytes_launch}
     if args.precision == "fp32" and not args.no_fp64:
         s64, ms64, _, _, _ = run_gpu(cfg, "fp64", args.steps, args.warmup)
         done = args.warmup + 2 * args.steps

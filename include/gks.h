@@ -74,6 +74,9 @@ typedef struct gks_config {
     int32_t ibm_iters;           /* direct-forcing iterations per step (fixed count, >= 1) */
     int32_t max_act;             /* capacity of the workspace for actuator points (0 = no rotor), <= 1024 */
     int64_t max_ibm;             /* capacity of the workspace for Lagrangian points (0 = no bodies) */
+    int32_t order;               /* 5 (or 0): the high-order GKS (fifth-order WENO-JS to 2x2 Gauss points,
+                                    Section 2); 2: the second-order GKS of the comparison in Section 4.3.3
+                                    (van Leer-limited linear face states, one flux point per face) */
 } gks_config;
 
 typedef struct gks_field {
@@ -185,8 +188,8 @@ size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
  * nx*ny*nz doubles back to back, interior cells, x fastest; variable 0 is the density). The WENO
  * nonlinear weights are frozen at their forward values (differentiated as constants); everything else
  * (flux, kinetic average, S2O4 combination, ghost cells, actuator-line sampling, forces and projection)
- * is linearised exactly. Requires an FP64 context with a rotor, no immersed bodies, a fixed dt and
- * periodic, wall or outflow boundaries. The stage buffers q_stage and q_acc are overwritten; q is not.
+ * is linearised exactly. Requires an FP64 context of the high-order scheme (order 5) with a rotor, no
+ * immersed bodies, a fixed dt and periodic, wall or outflow boundaries. The stage buffers q_stage and q_acc are overwritten; q is not.
  * adj_ws: device scratch of gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
 int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0,
                 void* adj_ws, size_t adj_ws_bytes);

@@ -32,6 +32,7 @@ class gks_config(C.Structure):
         ("u_in", C.c_double * 3), ("body_force", C.c_double * 3),
         ("weno_eps", C.c_double),
         ("ibm_iters", C.c_int32), ("max_act", C.c_int32), ("max_ibm", C.c_int64),
+        ("order", C.c_int32),
     ]
 
 

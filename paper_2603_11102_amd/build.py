@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgks.so")
 
-SOURCES = ["gks_api.hip", "gks_stage.hip", "gks_aux.hip", "gks_body.hip", "gks_adjoint.hip", "gks_stats.hip"]
+SOURCES = ["gks_api.hip", "gks_stage.hip", "gks_stage2.hip", "gks_aux.hip", "gks_body.hip", "gks_adjoint.hip",
+           "gks_stats.hip"]
 
 # Packed FP32 instructions are kept out of the code objects (the target feature is switched off).
 HIP_FLAGS = [

@@ -197,6 +197,7 @@ std::string validate(const gks_config* c) {
     if (c->max_act < 0 || c->max_act > 1024) return "max_act must be in [0, 1024]";
     if (c->max_ibm < 0 || c->max_ibm > (1LL << 24)) return "max_ibm must be in [0, 2^24]";
     if (c->max_ibm > 0 && c->ibm_iters < 1) return "ibm_iters must be >= 1";
+    if (c->order != 0 && c->order != 2 && c->order != 5) return "order must be 5 (or 0) or 2";
     return "";
 }
 
@@ -419,7 +420,8 @@ int steps(gks_ctx* c, int nsteps) {
         tend(c, tp);
         for (int d = 0; d < 3; ++d) {
             tp = tbeg(c, cat1[d]);
-            HIPCHK(c, launch_face<real>(face_args<real>(c, d, 1, c->q), 1, c->stream));
+            HIPCHK(c, c->cfg.order == 2 ? launch_face2<real>(face_args<real>(c, d, 1, c->q), 1, c->stream)
+                                        : launch_face<real>(face_args<real>(c, d, 1, c->q), 1, c->stream));
             tend(c, tp);
         }
         tp = tbeg(c, GKS_TIMER_GHOST);
@@ -428,7 +430,8 @@ int steps(gks_ctx* c, int nsteps) {
         tend(c, tp);
         for (int d = 0; d < 3; ++d) {
             tp = tbeg(c, cat2[d]);
-            HIPCHK(c, launch_face<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream));
+            HIPCHK(c, c->cfg.order == 2 ? launch_face2<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream)
+                                        : launch_face<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream));
             tend(c, tp);
         }
         if (c->has_rotor) {
@@ -544,7 +547,8 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     c->eps = c->cfg.weno_eps;
     c->diag_nblk = diag_blocks(c->g);
     c->flags = cfg->ma > 0.3 ? GKS_WARN_MACH : 0;
-    const int slots = cfg->precision == GKS_FP32 ? face_slots<float>() : face_slots<double>();
+    const int slots = cfg->order == 2 ? (cfg->precision == GKS_FP32 ? face2_slots<float>() : face2_slots<double>())
+                                      : (cfg->precision == GKS_FP32 ? face_slots<float>() : face_slots<double>());
     for (int d = 0; d < 3; ++d) {
         const int* ax = kAxes[d];
         const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + TILE2 - 1) / TILE2);
@@ -827,6 +831,7 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
     if (!c) return GKS_E_INVALID_ARG;
     if (!w || !grad_s || !adj_ws) return fail(c, GKS_E_INVALID_ARG, "null argument");
     if (c->cfg.precision != GKS_FP64) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs an FP64 context");
+    if (c->cfg.order == 2) return fail(c, GKS_E_UNSUPPORTED, "the adjoint covers the high-order scheme only");
     if (c->cfg.cfl > 0) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a fixed dt (cfl <= 0)");
     if (!c->has_rotor) return fail(c, GKS_E_STATE, "the adjoint needs a rotor (gks_set_actuators)");
     if (c->has_ibm) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover immersed bodies");

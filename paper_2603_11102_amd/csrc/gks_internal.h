@@ -92,6 +92,11 @@ template <typename real>
 int face_chunk(int n_n, int tiles, int slots);
 template <typename real>
 int face_slots();
+// second-order variant (gks_stage2.hip)
+template <typename real>
+hipError_t launch_face2(const FaceArgs<real>& a, int stage, hipStream_t s);
+template <typename real>
+int face2_slots();
 
 // host launchers (gks_aux.hip)
 template <typename real>

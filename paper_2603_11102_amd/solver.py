@@ -57,6 +57,7 @@ class GksSolver:
             c.body_force[j] = cfg.body_force[j]
         c.weno_eps = cfg.weno_eps
         c.ibm_iters = cfg.ibm_iters
+        c.order = int(getattr(cfg, "order", 5))
         c.max_act = max_act
         c.max_ibm = max_ibm
         self.c_cfg = c
