@@ -31,29 +31,36 @@ FLOP_PER_CELL_STEP = 3 * (FLOP_STAGE1_PER_CELL_DIR + FLOP_STAGE2_PER_CELL_DIR) +
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per stage-1 face-kernel launch (mean over the x, y, z launches) of the FP32 channel workload,
+# HBM bytes per stage-1 face-pass launch (mean over the x, y, z launches) of the FP32 channel workload,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-# "bench.py --steps 2 --warmup 1 --no-fp64 --no-cpu-baseline", each scaled by what the same counter reads
-# for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024": FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
-# The figure belongs to the kernel sources it was measured on; bench reports null once they differ.
-TRAFFIC = {"sources_sha256": "bb647efd0c5564b0064bee578867c8736829c712a2dc760b7bcea70b7dc5a335",
-           "fetch_bytes": 225_849_719, "write_bytes": 84_934_656}
-KERNEL_SOURCES = ("gks_stage.hip", "gks_device.h", "gks_internal.h")
+# "bench.py [--order 2] --steps 2 --warmup 1 --no-fp64 --no-cpu-baseline", each scaled by what the same
+# counter reads for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024": FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0). A figure belongs to the kernel sources it was measured on; bench reports null once
+# they differ.
+TRAFFIC = {
+    5: {"sources": ("gks_stage.hip", "gks_device.h", "gks_internal.h"),
+         "sources_sha256": "c9383f65c1b59e43ef3a35bfe45f8b6578f4210178653d8c86b9e8541cc956e5",
+         "fetch_bytes": 225_836_032, "write_bytes": 84_934_656},
+    2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
+         "sources_sha256": "e554501d1dc3bc6df0e683fd5e217f810bac171766cef01fcbbc18d022338a7a",
+         "fetch_bytes": 197_935_147, "write_bytes": 84_934_656},
+}
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(order=5):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in TRAFFIC[order]["sources"]:
         with open(os.path.join(ROOT, "paper_2603_11102_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(case, precision):
-    if case != "channel" or precision != "fp32" or TRAFFIC["sources_sha256"] != kernel_sources_sha256():
+def measured_traffic(case, precision, order=5):
+    t = TRAFFIC[order]
+    if case != "channel" or precision != "fp32" or t["sources_sha256"] != kernel_sources_sha256(order):
         return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
 def _time_steps(s, steps):
@@ -216,7 +223,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'}, 1, "
                                                 "3 | 0 | 4> (stage 1: mean over the x, y, z launches)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(args.case, args.precision), "avg_launch_ms": avg_launch_ms,
+                     "traffic": measured_traffic(args.case, args.precision, 5), "avg_launch_ms": avg_launch_ms,
                      "algorithmic_flop_per_launch": flops_launch},
         "per_category_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
         "flop_per_cell_step": FLOP_PER_CELL_STEP,
@@ -235,8 +242,8 @@ def main():
                                                         "3 | 0 | 4> (stage 1: mean over the x, y, z launches)",
                               "achieved": bytes_launch / (avg_launch_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                               "unit": "GB/s", "frac": bytes_launch / (avg_launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                              "traffic": None, "avg_launch_ms": avg_launch_ms,
-                              "algorithmic_bytes_per_launch": bytes_launch}
+                              "traffic": measured_traffic(args.case, args.precision, 2),
+                              "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_launch}
     if args.precision == "fp32" and not args.no_fp64:
         s64, ms64, _, _, _ = run_gpu(cfg, "fp64", args.steps, args.warmup)
         done = args.warmup + 2 * args.steps
