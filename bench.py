@@ -156,8 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-steps", type=int, default=100,
                     help="steps after which the FP32 field is compared with the FP64 one (at least the timed ones)")
-    ap.add_argument("--cpu-planes", type=int, default=96,
-                    help="z-planes of the field the CPU oracle steps once (all of them by default)")
+    ap.add_argument("--cpu-planes", type=int, default=64,
+                    help="z-planes of the field (from z = 0, periodic in z) the CPU oracle steps once")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--order", type=int, default=5, choices=(2, 5),

@@ -38,7 +38,9 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
     __shared__ double s_t1[5][EXT2][TILE1][2];
 
     const int tid = threadIdx.x;
-    int b = blockIdx.x;
+    // consecutive logical workgroups on the same XCD (grid padded to a multiple of 8), as in the forward
+    int b = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+    if (b >= a.tiles_t1 * a.tiles_t2 * ((a.n_n + a.chunk - 1) / a.chunk)) return;
     const int tile1 = b % a.tiles_t1;
     b /= a.tiles_t1;
     const int tile2 = b % a.tiles_t2;
@@ -362,7 +364,7 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
 
 hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
-    const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
+    const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     const long long nA = 4 * a.nface;
     if (stage == 1) {
         hipLaunchKernelGGL((adj_face_kernel<1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);

@@ -88,7 +88,11 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     __shared__ real s_t1[4][5][EXT2][TILE1][2];   // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
 
     const int tid = threadIdx.x;
-    int b = blockIdx.x;
+    // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
+    // the 8 XCDs; the grid is padded to a multiple of 8), so neighbouring tiles share that XCD's L2 for
+    // their halo columns
+    int b = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+    if (b >= a.tiles_t1 * a.tiles_t2 * ((a.n_n + a.chunk - 1) / a.chunk)) return;
     const int tile1 = b % a.tiles_t1;
     b /= a.tiles_t1;
     const int tile2 = b % a.tiles_t2;
@@ -447,7 +451,7 @@ int face_chunk(int n_n, int tiles, int slots) {
 template <typename real>
 hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
-    const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
+    const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(FACE_THREADS);
 #define GKS_FACE_LAUNCH(ST, MD) hipLaunchKernelGGL((face_kernel<real, ST, MD>), grid, block, 0, s, a)

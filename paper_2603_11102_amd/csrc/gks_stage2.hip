@@ -88,7 +88,11 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     __shared__ real s_face[4][4][T2O_EXT][T2O_EXT];  // [variable][q^L, q^R, D, C][t2][t1]
 
     const int tid = threadIdx.x;
-    int b = blockIdx.x;
+    // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
+    // the 8 XCDs; the grid is padded to a multiple of 8), so neighbouring tiles share that XCD's L2 for
+    // their halo columns
+    int b = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+    if (b >= a.tiles_t1 * a.tiles_t2 * ((a.n_n + a.chunk - 1) / a.chunk)) return;
     const int tile1 = b % a.tiles_t1;
     b /= a.tiles_t1;
     const int tile2 = b % a.tiles_t2;
@@ -296,7 +300,7 @@ int face2_slots() {
 template <typename real>
 hipError_t launch_face2(const FaceArgs<real>& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
-    const long long blocks = (long long)a.tiles_t1 * a.tiles_t2 * nchunks;
+    const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(T2O_THREADS);
 #define GKS_FACE2_LAUNCH(ST, MD) hipLaunchKernelGGL((face2_kernel<real, ST, MD>), grid, block, 0, s, a)
