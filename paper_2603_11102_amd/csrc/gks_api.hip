@@ -385,7 +385,7 @@ hipError_t clear_low_parts(gks_ctx* c) {
     const size_t bytes = (size_t)4 * c->cfg.nx * c->cfg.ny * c->cfg.nz * sizeof(float);
     void* const sets[3] = {c->lo_q, c->lo_qs, c->lo_qa};
     for (int b = 0; b < 3; ++b) {
-        hipError_t e = hipMemsetAsync(sets[b], 0, bytes, c->stream);
+        hipError_t e = launch_zero_words(sets[b], bytes, c->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -558,7 +558,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     hipError_t e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
     if (e == hipSuccess) e = clear_low_parts(c);
     if (e != hipSuccess) {
-        g_init_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+        g_init_error = std::string("clearing the device state: ") + hipGetErrorString(e);
         delete c;
         return GKS_E_HIP;
     }

@@ -420,6 +420,20 @@ hipError_t launch_diag(Field4<real> f, const GridDesc& g, double rho_ref, double
     return hipGetLastError();
 }
 
+// zero-fill of device memory by a kernel (usable inside a captured graph, unlike a memset node)
+__global__ void __launch_bounds__(256) zero_words_kernel(unsigned* p, long long n) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s) {
+    const long long n = (long long)(bytes / 4);
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<unsigned*>(p), n);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream_t s) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
 }

@@ -105,6 +105,7 @@ hipError_t launch_ghost(Field4<real> f, const GridDesc& g, int axis, int bc_lo, 
 template <typename real>
 hipError_t launch_umax(Field4<real> f, const GridDesc& g, double rho_ref, double* part, hipStream_t s);
 int umax_blocks(const GridDesc& g);
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t s);
 template <typename real>
 hipError_t launch_transpose_xy(Field4<real> in, Field4<real> out, const GridDesc& g, hipStream_t s);
 template <typename real>

@@ -204,3 +204,30 @@ def test_ibm_rejects_non_finite_velocity():
     vel[5, 1] = np.nan
     with pytest.raises(GksError):
         s.set_ibm(IbmSpec(xyz=cfg.ibm.xyz, dS=cfg.ibm.dS, vel=vel))
+
+
+def test_step_in_a_hip_graph_replays_like_eager_steps():
+    # gks_step enqueues kernels only (no memset, no host synchronisation; time and dt live on the
+    # device), so one step captured in a graph and replayed advances the solution exactly like eager
+    # steps. Each replay is checked, with eager work and synchronisations in between.
+    from paper_2603_11102_amd import GksSolver
+    cfg = make_case("alm", grid=(48, 24, 24))
+    print_case("graph-replay", grid=(48, 24, 24))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = GksSolver(cfg, precision="fp32")
+        b = GksSolver(cfg, precision="fp32")
+    a.step(1)
+    b.step(1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        a.step(1)
+    for _ in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        b.step(1)
+        torch.cuda.synchronize()
+        assert torch.equal(a.interior(), b.interior())
+    fa, fb = a.forces(), b.forces()
+    assert fa["t"] == fb["t"] and fa["power"] == fb["power"]
