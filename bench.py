@@ -75,13 +75,35 @@ def _time_steps(s, steps):
     return e0.elapsed_time(e1)
 
 
-def run_gpu(cfg, precision, steps, warmup):
+def _time_graph(s, steps, side):
+    """Capture `steps` steps in one HIP graph and time a replay of it on the solver's stream."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        s.step(steps)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(side):  # a replay runs on the current stream
+        e0.record(side)
+        g.replay()
+        e1.record(side)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def run_gpu(cfg, precision, steps, warmup, graph=False):
     import torch
     from paper_2603_11102_amd import GksSolver
-    s = GksSolver(cfg, precision=precision)
+    side = torch.cuda.Stream() if graph else None
+    if graph:
+        with torch.cuda.stream(side):
+            s = GksSolver(cfg, precision=precision)
+    else:
+        s = GksSolver(cfg, precision=precision)
     s.step(warmup)
     torch.cuda.synchronize()
-    ms = _time_steps(s, steps)
+    ms = _time_graph(s, steps, side) if graph else _time_steps(s, steps)
     torch.cuda.synchronize()
     s.set_timing(True)
     ms_t = _time_steps(s, steps)
@@ -162,6 +184,8 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--order", type=int, default=5, choices=(2, 5),
                     help="5: the high-order GKS (default); 2: the second-order variant (own JSON line)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the steps as one captured HIP graph replay (launch overheads removed)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the adjoint against its checkpointed forward window and print that line")
     args = ap.parse_args()
@@ -191,7 +215,7 @@ def main():
     cfg = make_case(args.case).with_(order=args.order)
     print(f"[bench] case={args.case} order={args.order} grid={cfg.nx}x{cfg.ny}x{cfg.nz} precision={args.precision} "
           f"steps={args.steps} warmup={args.warmup}", flush=True)
-    s, ms, ms_t, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    s, ms, ms_t, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup, graph=args.graph)
     n = cfg.n_cells
     value = n * args.steps / (ms * 1e-3)
     print(f"[bench] {args.precision}: {ms / args.steps:.3f} ms/step, {value:.4e} cell-updates/s", flush=True)
@@ -219,7 +243,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.case} {cfg.nx}x{cfg.ny}x{cfg.nz} ({n} cells), "
                                f"{'FP32, density as deviation from rho_ref' if args.precision == 'fp32' else 'FP64'}",
-                   "cells": n, "bc": list(cfg.bc), "ma": cfg.ma},
+                   "cells": n, "bc": list(cfg.bc), "ma": cfg.ma,
+                   "launch": "one HIP graph replay of the timed steps" if args.graph else "eager"},
         "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'}, 1, "
                                                 "3 | 0 | 4> (stage 1: mean over the x, y, z launches)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
