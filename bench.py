@@ -39,11 +39,11 @@ PEAK_HBM_GBS = 8000.0
 # they differ.
 TRAFFIC = {
     5: {"sources": ("gks_stage.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "c9383f65c1b59e43ef3a35bfe45f8b6578f4210178653d8c86b9e8541cc956e5",
-         "fetch_bytes": 225_836_032, "write_bytes": 84_934_656},
+         "sources_sha256": "4f521f7d950c299594ced0725fd0cafb2bfe1b9d2eb51e8344267322d470758a",
+         "fetch_bytes": 103_966_899, "write_bytes": 76_417_007},
     2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "e554501d1dc3bc6df0e683fd5e217f810bac171766cef01fcbbc18d022338a7a",
-         "fetch_bytes": 197_935_147, "write_bytes": 84_934_656},
+         "sources_sha256": "71396458cef051c7477cac120e883dc5ced1891d5e74fc1ad04b4fb828664fae",
+         "fetch_bytes": 97_877_009, "write_bytes": 77_149_220},
 }
 
 
