@@ -56,6 +56,12 @@ R15 Second-order GKS (the comparison scheme of Section 4.3.3; the paper defers i
 R14 IBM velocity at the cells: the printed v-bar = sum_p W v_p is read with the volume weighting of
     V-bar, v-bar = sum_p W V_p v_p / V-bar, so that it is a velocity (a uniform v_p gives v-bar = v_p;
     stationary points give 0 as in the paper).
+R16 Moving immersed bodies (the introduction has the Lagrangian points follow the body's translation
+    and rotation; the paper's own bodies are stationary): rigid motion with constant translation
+    velocity V and angular velocity omega about the moving centre, c(t) = c0 + V (t - t0),
+    X_p(t) = c(t) + R(omega (t - t0)) (X_p(t0) - c0), v_p(t) = V + omega x (X_p(t) - c(t)). The
+    forcing that closes the step from t^n to t^{n+1} uses X_p(t^{n+1}) and v_p(t^{n+1}); supports,
+    weights, V-bar and v-bar are rebuilt from them every step.
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
     momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
     U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).
@@ -77,6 +83,7 @@ __all__ = [
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
     "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics", "van_leer", "muscl_faces",
+    "rotation_matrix", "ibm_motion_state",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -664,6 +671,15 @@ def phi4(r):
     return out
 
 
+class IbmPoints:
+    """Lagrangian points of one step: positions [n, 3], surface elements [n], velocities [n, 3]."""
+
+    def __init__(self, xyz, dS, vel=None):
+        self.xyz = xyz
+        self.dS = dS
+        self.vel = vel
+
+
 class IbmCache:
     """Static data of Lagrangian points at fixed positions: per point the 4x4x4 support cells and
     weights and its prescribed velocity, per cell the interpolated volume V-bar and velocity v-bar."""
@@ -714,6 +730,34 @@ def ibm_setup(cfg, ibm):
         np.add.at(mv, flat.reshape(-1), (weights * (vp * vel[:, d])[:, None]).reshape(-1))
         vbar_vel[:, d] = mv[nz_idx] / vb[nz_idx]
     return IbmCache(cells, weights, vbar_index, vb[nz_idx], vel, vbar_vel)
+
+
+def rotation_matrix(rotvec):
+    """Rotation by the angle theta = |rotvec| about the unit axis k = rotvec / theta, by Rodrigues'
+    formula R = I + sin(theta) K + (1 - cos(theta)) K^2 with K the cross-product matrix of k."""
+    w = np.asarray(rotvec, dtype=np.float64)
+    theta = float(np.linalg.norm(w))
+    if theta == 0.0:
+        return np.eye(3)
+    k = w / theta
+    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+    return np.eye(3) + math.sin(theta) * K + (1.0 - math.cos(theta)) * (K @ K)
+
+
+def ibm_motion_state(ibm, t):
+    """Positions and velocities of the Lagrangian points of a rigidly moving body at time t (reading
+    R16): c(t) = c0 + V (t - t0), X_p(t) = c(t) + R(omega (t - t0)) (X_p(t0) - c0),
+    v_p(t) = V + omega x (X_p(t) - c(t))."""
+    m = ibm.motion
+    tau = t - m.t0
+    c0 = np.asarray(m.center, dtype=np.float64)
+    V = np.asarray(m.velocity, dtype=np.float64)
+    w = np.asarray(m.omega, dtype=np.float64)
+    X0 = np.asarray(ibm.xyz, dtype=np.float64)
+    ct = c0 + V * tau
+    X = ct + (X0 - c0) @ rotation_matrix(w * tau).T
+    v = V + np.cross(w, X - ct)
+    return X, v
 
 
 def ibm_apply(Q, dt, cfg, cache, iters):
@@ -769,7 +813,8 @@ class Oracle:
         self.scales = scales
         self.ctl = weno_ctl
         self.chunk = chunk
-        self.ibm_cache = ibm_setup(cfg, cfg.ibm) if cfg.ibm is not None else None
+        moving = cfg.ibm is not None and getattr(cfg.ibm, "motion", None) is not None
+        self.ibm_cache = ibm_setup(cfg, cfg.ibm) if cfg.ibm is not None and not moving else None
         self.history = []
 
     def step(self, dt=None):
@@ -789,8 +834,12 @@ class Oracle:
         if cfg.rotor is not None:
             Qn, alm = alm_apply(Qn, t_new, dt, cfg, cfg.rotor, self.scales)
             out["alm"] = alm
-        if self.ibm_cache is not None:
-            Qn, ib = ibm_apply(Qn, dt, cfg, self.ibm_cache, cfg.ibm_iters)
+        if cfg.ibm is not None:
+            cache = self.ibm_cache
+            if cache is None:  # moving body: supports of the positions at t^{n+1} (reading R16)
+                X, v = ibm_motion_state(cfg.ibm, t_new)
+                cache = ibm_setup(cfg, IbmPoints(X, cfg.ibm.dS, v))
+            Qn, ib = ibm_apply(Qn, dt, cfg, cache, cfg.ibm_iters)
             out["ibm"] = ib
         self.Q = Qn
         self.t = t_new

@@ -63,10 +63,21 @@ class RotorSpec:
 
 
 @dataclass
+class IbmMotion:
+    """Rigid motion of an immersed body: centre c0 at time t0, constant translation velocity and
+    constant angular velocity (rad per unit time, about the moving centre)."""
+    center: Sequence[float]
+    velocity: Sequence[float] = (0.0, 0.0, 0.0)
+    omega: Sequence[float] = (0.0, 0.0, 0.0)
+    t0: float = 0.0
+
+
+@dataclass
 class IbmSpec:
-    xyz: np.ndarray  # [n, 3]
+    xyz: np.ndarray  # [n, 3] (positions at time motion.t0 when the body moves)
     dS: np.ndarray   # [n]
     vel: Optional[np.ndarray] = None  # [n, 3] prescribed point velocities (None: stationary)
+    motion: Optional[IbmMotion] = None  # rigid motion (point velocities then follow from it)
 
     @property
     def n(self) -> int:
