@@ -186,6 +186,9 @@ def main():
                     help="5: the high-order GKS (default); 2: the second-order variant (own JSON line)")
     ap.add_argument("--graph", action="store_true",
                     help="time the steps as one captured HIP graph replay (launch overheads removed)")
+    ap.add_argument("--ibm-yaw", type=float, default=0.0, metavar="OMEGA",
+                    help="turn the immersed tower and nacelle about the tower axis at OMEGA rad per unit time "
+                         "(their supports are then rebuilt on the device every step)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the adjoint against its checkpointed forward window and print that line")
     args = ap.parse_args()
@@ -213,6 +216,14 @@ def main():
     import torch
     from synth import make_case
     cfg = make_case(args.case).with_(order=args.order)
+    if args.ibm_yaw:
+        if cfg.ibm is None or cfg.rotor is None:
+            sys.exit("--ibm-yaw needs a workload with a rotor and immersed bodies (alm_ibm)")
+        from synth.cases import IbmMotion, IbmSpec
+        hub = cfg.rotor.hub
+        axis = (hub[0] + 0.16 * 2.0 * cfg.rotor.radius, hub[1], 0.0)  # tower axis 0.16 D behind the rotor plane
+        cfg = cfg.with_(ibm=IbmSpec(xyz=cfg.ibm.xyz, dS=cfg.ibm.dS,
+                                    motion=IbmMotion(center=axis, omega=(0.0, 0.0, args.ibm_yaw))))
     print(f"[bench] case={args.case} order={args.order} grid={cfg.nx}x{cfg.ny}x{cfg.nz} precision={args.precision} "
           f"steps={args.steps} warmup={args.warmup}", flush=True)
     s, ms, ms_t, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup, graph=args.graph)
@@ -244,7 +255,8 @@ def main():
         "config": {"workload": f"{args.case} {cfg.nx}x{cfg.ny}x{cfg.nz} ({n} cells), "
                                f"{'FP32, density as deviation from rho_ref' if args.precision == 'fp32' else 'FP64'}",
                    "cells": n, "bc": list(cfg.bc), "ma": cfg.ma,
-                   "launch": "one HIP graph replay of the timed steps" if args.graph else "eager"},
+                   "launch": "one HIP graph replay of the timed steps" if args.graph else "eager",
+                   **({"ibm_yaw_rad_per_time": args.ibm_yaw} if args.ibm_yaw else {})},
         "roofline": {"bound": "alu", "kernel": f"face_kernel<{'float' if args.precision == 'fp32' else 'double'}, 1, "
                                                 "3 | 0 | 4> (stage 1: mean over the x, y, z launches)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,

@@ -42,6 +42,7 @@ extern "C" {
 #define GKS_E_NONFINITE 4     /* a non-finite value was found in the field (reported by gks_forces) */
 #define GKS_E_UNSTABLE 5      /* |U|_max reached the sound speed (reported by gks_forces) */
 #define GKS_E_UNSUPPORTED 6   /* valid request this build does not implement */
+#define GKS_E_BODY_LEFT 7     /* a moving body's point support left the interior (reported by gks_forces) */
 
 /* boundary kinds, per side, order x-, x+, y-, y+, z-, z+ */
 #define GKS_BC_PERIODIC 0
@@ -124,6 +125,16 @@ typedef struct gks_forces_out {
     double* urel;
 } gks_forces_out;
 
+/* Rigid motion of an immersed body: the body's points are at their given positions at time t0; the
+ * centre c0 moves with the constant translation velocity, the body turns about the moving centre with
+ * the constant angular velocity omega (rad per unit time, right-handed about omega). */
+typedef struct gks_motion {
+    double center[3];
+    double velocity[3];
+    double omega[3];
+    double t0;
+} gks_motion;
+
 typedef struct gks_ctx gks_ctx;
 
 /* Bytes of device workspace the caller must provide to gks_init for this configuration (including
@@ -150,6 +161,18 @@ int gks_set_actuators(gks_ctx* ctx, const gks_rotor* rotor);
  * velocities v-bar = sum W V_p v_p / V-bar that the forcing drives the fluid towards. Host arrays
  * are copied; GKS_E_INVALID_ARG for bad sizes, points or values. */
 int gks_set_ibm_points(gks_ctx* ctx, int64_t n, const double* xyz, const double* dS, const double* vel);
+
+/* Move the body of the last gks_set_ibm_points rigidly (the introduction and Section 3.2 have the
+ * Lagrangian points follow the body's translation and rotation; the paper's own bodies are at rest).
+ * The points given there are the positions at motion->t0. From the next step on, every step from t^n
+ * to t^{n+1} places each point at X_p = c + R(omega (t^{n+1} - t0)) (X_p(t0) - c0), c = c0 +
+ * velocity (t^{n+1} - t0), gives it the velocity v_p = velocity + omega x (X_p - c) (replacing the
+ * velocities of gks_set_ibm_points) and rebuilds the supports, V-bar and v-bar on the device before
+ * the forcing; nothing is synchronised and nothing allocated. The motion lasts until the next
+ * gks_set_ibm_points. If a point's 4x4x4 support leaves the interior cells the forcing stops for that
+ * and every later step and gks_forces returns GKS_E_BODY_LEFT. Returns GKS_E_STATE without points,
+ * GKS_E_INVALID_ARG for a null or non-finite motion. */
+int gks_set_ibm_motion(gks_ctx* ctx, const gks_motion* motion);
 
 /* Enqueue nsteps S2O4 steps (Section 2) with the body-force update of Section 3.3 on the stream and
  * return without synchronising. dt stays on the device. */

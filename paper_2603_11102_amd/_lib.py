@@ -15,6 +15,7 @@ GKS_E_HIP = 3
 GKS_E_NONFINITE = 4
 GKS_E_UNSTABLE = 5
 GKS_E_UNSUPPORTED = 6
+GKS_E_BODY_LEFT = 7
 
 BC = {"periodic": 0, "noslip": 1, "slip": 2, "inflow": 3, "outflow": 4}
 GKS_FP32 = 0
@@ -54,6 +55,11 @@ class gks_rotor(C.Structure):
     ]
 
 
+class gks_motion(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("velocity", C.c_double * 3), ("omega", C.c_double * 3),
+                ("t0", C.c_double)]
+
+
 class gks_forces_out(C.Structure):
     _fields_ = [
         ("t", C.c_double), ("dt", C.c_double), ("step", C.c_int64),
@@ -69,7 +75,7 @@ class gks_forces_out(C.Structure):
 
 
 EXPORTS = (
-    "gks_workspace_bytes", "gks_init", "gks_set_actuators", "gks_set_ibm_points", "gks_step",
+    "gks_workspace_bytes", "gks_init", "gks_set_actuators", "gks_set_ibm_points", "gks_set_ibm_motion", "gks_step",
     "gks_forces", "gks_reset_window", "gks_field_changed", "gks_checkpoint_slot_bytes", "gks_set_checkpoints",
     "gks_adjoint_workspace_bytes", "gks_adjoint", "gks_set_timing", "gks_read_timing", "gks_destroy",
     "gks_last_error", "gks_statistics_bytes", "gks_set_statistics", "gks_read_statistics", "gks_set_history",
@@ -97,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.gks_set_actuators.restype = C.c_int
     lib.gks_set_ibm_points.argtypes = [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), P]
     lib.gks_set_ibm_points.restype = C.c_int
+    lib.gks_set_ibm_motion.argtypes = [P, C.POINTER(gks_motion)]
+    lib.gks_set_ibm_motion.restype = C.c_int
     lib.gks_step.argtypes = [P, C.c_int32]
     lib.gks_step.restype = C.c_int
     lib.gks_forces.argtypes = [P, C.POINTER(gks_forces_out)]

@@ -71,6 +71,8 @@ struct gks_ctx {
     int has_ibm;
     IbmArgs ibm;
     char* ibm_mem;
+    int ibm_moving;    // rigid motion set: supports rebuilt on the device every step
+    IbmMoveArgs ibm_mv;
     // checkpoints
     char* ckpt;
     int ckpt_cap;
@@ -140,7 +142,10 @@ size_t alm_block_bytes(int n) {
     return cv.off;
 }
 
-size_t ibm_block_bytes(long long n) {
+int bin_blocks(long long ncells) { return (int)((ncells + BIN_CELLS - 1) / BIN_CELLS); }
+
+// Lagrangian-point block of the workspace; the carving order here and in gks_set_ibm_points agree
+size_t ibm_block_bytes(long long n, long long ncells) {
     if (n <= 0) return 0;
     const long long nc = 64 * n;
     Carver cv{nullptr, 0};
@@ -153,6 +158,12 @@ size_t ibm_block_bytes(long long n) {
     cv.take(sizeof(double) * 3 * ((nc + 255) / 256));
     cv.take(sizeof(double) * 3 * n);   // point velocities
     cv.take(sizeof(double) * 3 * nc);  // v-bar
+    // rebinning of a moving body
+    cv.take(sizeof(double) * 3 * n);   // positions at t0
+    cv.take(sizeof(int) * 3 * n);      // lowest support cell
+    cv.take(sizeof(int) * ncells);     // per-cell counters
+    cv.take(sizeof(int) * 2 * bin_blocks(ncells));
+    cv.take(sizeof(int) * 2);
     return cv.off;
 }
 
@@ -173,7 +184,7 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     L->umax_part = cv.ptr<double>(sizeof(double) * UMAX_BLOCKS);
     size_t ab = alm_block_bytes(c->max_act);
     L->alm = ab ? cv.ptr<char>(ab) : nullptr;
-    size_t ib = ibm_block_bytes(c->max_ibm);
+    size_t ib = ibm_block_bytes(c->max_ibm, (long long)N);
     L->ibm = ib ? cv.ptr<char>(ib) : nullptr;
     L->total = cv.off;
     return true;
@@ -441,6 +452,7 @@ int steps(gks_ctx* c, int nsteps) {
         }
         if (c->has_ibm) {
             tp = tbeg(c, GKS_TIMER_IBM);
+            if (c->ibm_moving) HIPCHK(c, launch_ibm_move(c->ibm, c->ibm_mv, c->stream));
             HIPCHK(c, launch_ibm<real>(field<real>(c->q), c->ibm, c->stream));
             tend(c, tp);
         }
@@ -726,6 +738,22 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     a.vbar_vel = cv.ptr<double>(sizeof(double) * 3 * nc);
     a.vel = vel ? dvel : nullptr;
     a.xyz = dx;
+    IbmMoveArgs& m = c->ibm_mv;
+    std::memset(&m, 0, sizeof(m));
+    const long long ncells = (long long)c->g.n[0] * c->g.n[1] * c->g.n[2];
+    double* dx0 = cv.ptr<double>(sizeof(double) * 3 * cap);
+    m.base = cv.ptr<int>(sizeof(int) * 3 * cap);
+    m.dcnt = cv.ptr<int>(sizeof(int) * ncells);
+    m.blk = cv.ptr<int>(sizeof(int) * 2 * bin_blocks(ncells));
+    m.counts = cv.ptr<int>(sizeof(int) * 2);
+    m.nblk = bin_blocks(ncells);
+    m.xyz0 = dx0;
+    m.xyz = dx;
+    m.pvel = dvel;
+    m.cell = dcell;
+    m.csr = dcsr;
+    m.ent = dent;
+    c->ibm_moving = 0;
     a.dS = ds;
     a.cell = dcell;
     a.csr = dcsr;
@@ -737,6 +765,8 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     a.g = c->g;
     a.st = c->st;
     HIPCHK(c, hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dx0, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_zero_words(&c->st->ibm_outside, sizeof(int), c->stream));
     HIPCHK(c, hipMemcpyAsync(ds, dS, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
     if (vel) HIPCHK(c, hipMemcpyAsync(dvel, vel, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(dcell, cells.data(), sizeof(int) * cells.size(), hipMemcpyHostToDevice, c->stream));
@@ -745,6 +775,33 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     HIPCHK(c, launch_ibm_vbar(a, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->has_ibm = 1;
+    return GKS_OK;
+}
+
+int gks_set_ibm_motion(gks_ctx* c, const gks_motion* mo) {
+    if (!c) return GKS_E_INVALID_ARG;
+    if (!mo) return fail(c, GKS_E_INVALID_ARG, "motion is null");
+    if (!c->has_ibm) return fail(c, GKS_E_STATE, "no Lagrangian points: call gks_set_ibm_points first");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(mo->center[d]) || !std::isfinite(mo->velocity[d]) || !std::isfinite(mo->omega[d]))
+            return fail(c, GKS_E_INVALID_ARG, "non-finite motion");
+    if (!std::isfinite(mo->t0)) return fail(c, GKS_E_INVALID_ARG, "non-finite motion");
+    IbmMoveArgs& m = c->ibm_mv;
+    for (int d = 0; d < 3; ++d) {
+        m.c0[d] = mo->center[d];
+        m.vel[d] = mo->velocity[d];
+        m.omega[d] = mo->omega[d];
+    }
+    m.t0 = mo->t0;
+    const long long ncells = (long long)c->g.n[0] * c->g.n[1] * c->g.n[2];
+    HIPCHK(c, launch_zero_words(m.dcnt, sizeof(int) * (size_t)ncells, c->stream));
+    HIPCHK(c, launch_zero_words(&c->st->ibm_outside, sizeof(int), c->stream));
+    IbmArgs& a = c->ibm;
+    a.vel = m.pvel;
+    a.ncell = 64 * a.npts;
+    a.ncell_dev = m.counts;
+    a.moving = 1;
+    c->ibm_moving = 1;
     return GKS_OK;
 }
 
@@ -793,6 +850,8 @@ int gks_forces(gks_ctx* c, gks_forces_out* out) {
         if (out->ftheta) HIPCHK(c, hipMemcpy(out->ftheta, c->alm.out_ft, sizeof(double) * n, hipMemcpyDeviceToHost));
         if (out->urel) HIPCHK(c, hipMemcpy(out->urel, c->alm.out_urel, sizeof(double) * n, hipMemcpyDeviceToHost));
     }
+    if (c->has_ibm && c->ibm_moving && h.ibm_outside)
+        return fail(c, GKS_E_BODY_LEFT, "a moving Lagrangian point's support left the interior cells");
     if (h.nonfinite || !std::isfinite(out->mass)) return fail(c, GKS_E_NONFINITE, "non-finite value in the field");
     if (!(out->umax < c->c)) return fail(c, GKS_E_UNSTABLE, "|U|max reached the sound speed");
     return GKS_OK;

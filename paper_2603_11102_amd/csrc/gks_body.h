@@ -41,9 +41,29 @@ struct IbmArgs {
     const double* vel;    // device, 3 npts prescribed point velocities, or null (stationary points)
     double* vbar_vel;     // device, 3 ncell: v-bar = sum W V_p v_p / V-bar (zero when vel is null)
     double* partials;     // device, 3 * ceil(ncell / 256)
+    const int* ncell_dev; // device cell count when the supports are rebuilt on the device (moving body),
+                          // else null; ncell is then the capacity 64 npts
+    int moving;
     GridDesc g;
     DevState* st;
 };
+
+// Rigid motion of the immersed body and the buffers of the per-step rebinning on the device.
+struct IbmMoveArgs {
+    double c0[3], vel[3], omega[3], t0;
+    const double* xyz0;  // device, 3 npts: positions at t0
+    double* xyz;         // device, 3 npts: positions of the step (IbmArgs::xyz)
+    double* pvel;        // device, 3 npts: velocities of the step (IbmArgs::vel)
+    int* base;           // device, 3 npts: lowest support cell per axis (clamped into the interior)
+    int* dcnt;           // device, one counter per interior cell; all zero between steps
+    int* blk;            // device, 2 per block of BIN_CELLS cells: cells and entries, then their offsets
+    int* counts;         // device, [0] cells, [1] entries
+    int* cell;           // device, 3 * 64 npts (IbmArgs::cell)
+    int* csr;            // device, 64 npts + 1
+    int* ent;            // device, 64 npts
+    int nblk;            // ceil(cells / BIN_CELLS)
+};
+constexpr int BIN_CELLS = 4096;  // dense cells per workgroup of the compaction (256 threads x 16)
 
 // Tip-correction factor f = (2/pi) acos(min(1, exp(-g1 N (R - r) / (2 r sin phi)))) and df/dphi.
 __device__ __forceinline__ double tip_factor(double g1, int N, double R, double r, double phi, double* dfdphi) {
@@ -61,6 +81,7 @@ __device__ __forceinline__ double tip_factor(double g1, int N, double R, double 
 template <typename real>
 hipError_t launch_alm(Field4<real> f, const AlmArgs& a, hipStream_t s);
 hipError_t launch_ibm_vbar(const IbmArgs& a, hipStream_t s);
+hipError_t launch_ibm_move(const IbmArgs& a, const IbmMoveArgs& m, hipStream_t s);
 hipError_t launch_alm_points_only(Field4<double> f, const AlmArgs& a, hipStream_t s);
 template <typename real>
 hipError_t launch_ibm(Field4<real> f, const IbmArgs& a, hipStream_t s);

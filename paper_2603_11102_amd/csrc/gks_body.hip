@@ -205,7 +205,7 @@ __device__ __forceinline__ double ibm_weight(const GridDesc& g, const double* X,
 // v-bar_c = sum W V_p v_p / V-bar_c (fixed point order)
 __global__ void __launch_bounds__(256) ibm_vbar_kernel(IbmArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.ncell) return;
+    if (c >= (a.ncell_dev ? *a.ncell_dev : a.ncell)) return;
     const int i = a.cell[3 * c], j = a.cell[3 * c + 1], k = a.cell[3 * c + 2];
     double v = 0.0, mv[3] = {0.0, 0.0, 0.0};
     for (int e = a.csr[c]; e < a.csr[c + 1]; ++e) {
@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(256) ibm_cells_kernel(Field4<real> f, IbmArgs 
     __shared__ double red[3][256];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     double F[3] = {0.0, 0.0, 0.0};
-    if (c < a.ncell) {
+    const bool stopped = a.moving && a.st->ibm_outside;  // a moving body left the interior: no forcing
+    if (c < (a.ncell_dev ? *a.ncell_dev : a.ncell) && !stopped) {
         const int i = a.cell[3 * c], j = a.cell[3 * c + 1], k = a.cell[3 * c + 2];
         const long long q = pidx(a.g, i, j, k);
         const double dt = a.st->dt;
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(256) ibm_final_kernel(IbmArgs a, int nblk) {
 template <typename real>
 __global__ void __launch_bounds__(256) ibm_resid_kernel(Field4<real> f, IbmArgs a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.npts) return;
+    if (p >= a.npts || (a.moving && a.st->ibm_outside)) return;
     const double* X = a.xyz + 3 * p;
     int i0[3];
 #pragma unroll
@@ -299,6 +300,214 @@ __global__ void __launch_bounds__(256) ibm_resid_kernel(Field4<real> f, IbmArgs 
         for (int d = 0; d < 3; ++d) U[d] -= a.vel[3 * p + d];
     const double r = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
     atomicMax(&a.st->ibm_res_bits, (unsigned long long)__double_as_longlong(r));
+}
+
+// ------------------------------------------------------------------------------------------------
+// moving body: the positions of the step and its supports rebuilt on the device, in the order of
+// the host binning (cells ascending, x fastest; points ascending within a cell)
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ long long flat_cell(const GridDesc& g, int i, int j, int k) {
+    return ((long long)k * g.n[1] + j) * g.n[0] + i;
+}
+
+// Rigid motion to t^{n+1}: X_p = X_p(t0) + V tau + (R - I) r with r = X_p(t0) - c0 and
+// (R - I) r = sin(theta) k x r + (1 - cos theta) k x (k x r) (Rodrigues), v_p = V + omega x R r.
+// Lowest support cell per axis, clamped into the interior when the support leaves it (then the
+// flag stops the forcing); one count per support cell.
+__global__ void __launch_bounds__(256) ibm_move_kernel(IbmArgs a, IbmMoveArgs m) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npts) return;
+    const double tau = a.st->t_next - m.t0;
+    double r[3], d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int x = 0; x < 3; ++x) r[x] = m.xyz0[3 * p + x] - m.c0[x];
+    const double wn = sqrt(m.omega[0] * m.omega[0] + m.omega[1] * m.omega[1] + m.omega[2] * m.omega[2]);
+    if (wn > 0.0) {
+        const double k[3] = {m.omega[0] / wn, m.omega[1] / wn, m.omega[2] / wn};
+        const double th = wn * tau;
+        const double sn = sin(th), hs = sin(0.5 * th), vc = 2.0 * hs * hs;
+        const double kr[3] = {k[1] * r[2] - k[2] * r[1], k[2] * r[0] - k[0] * r[2], k[0] * r[1] - k[1] * r[0]};
+        const double kkr[3] = {k[1] * kr[2] - k[2] * kr[1], k[2] * kr[0] - k[0] * kr[2], k[0] * kr[1] - k[1] * kr[0]};
+#pragma unroll
+        for (int x = 0; x < 3; ++x) d[x] = sn * kr[x] + vc * kkr[x];
+    }
+    double X[3], rr[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        X[x] = m.xyz0[3 * p + x] + m.vel[x] * tau + d[x];
+        rr[x] = r[x] + d[x];
+    }
+    const double v[3] = {m.vel[0] + m.omega[1] * rr[2] - m.omega[2] * rr[1],
+                         m.vel[1] + m.omega[2] * rr[0] - m.omega[0] * rr[2],
+                         m.vel[2] + m.omega[0] * rr[1] - m.omega[1] * rr[0]};
+    int b[3];
+    bool out = false;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        const double f = (X[x] - a.g.x0[x]) / a.g.h[x] - 0.5;
+        if (f >= 1.0 && f < (double)(a.g.n[x] - 2)) {
+            b[x] = (int)floor(f);
+        } else {  // also NaN
+            out = true;
+            b[x] = f >= 1.0 ? a.g.n[x] - 3 : 1;
+        }
+        m.xyz[3 * p + x] = X[x];
+        m.pvel[3 * p + x] = v[x];
+        m.base[3 * p + x] = b[x];
+    }
+    if (out) atomicOr(&a.st->ibm_outside, 1);
+    for (int dk = -1; dk <= 2; ++dk)
+        for (int dj = -1; dj <= 2; ++dj)
+            for (int di = -1; di <= 2; ++di) atomicAdd(&m.dcnt[flat_cell(a.g, b[0] + di, b[1] + dj, b[2] + dk)], 1);
+}
+
+// block sums of (cells with a count, entries) over BIN_CELLS consecutive cells, 16 per thread
+__global__ void __launch_bounds__(256) ibm_bincount_kernel(IbmMoveArgs m, long long ncells) {
+    __shared__ int sc[256], se[256];
+    const long long x0 = (long long)blockIdx.x * BIN_CELLS + 16 * threadIdx.x;
+    int c = 0, e = 0;
+    for (int q = 0; q < 16; ++q) {
+        if (x0 + q < ncells) {
+            const int v = m.dcnt[x0 + q];
+            c += v > 0;
+            e += v;
+        }
+    }
+    sc[threadIdx.x] = c;
+    se[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sc[threadIdx.x] += sc[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        m.blk[2 * blockIdx.x] = sc[0];
+        m.blk[2 * blockIdx.x + 1] = se[0];
+    }
+}
+
+// exclusive scan of the block sums in place (one workgroup, a contiguous run of blocks per thread);
+// totals to counts[0..1] and csr[cells] = entries
+__global__ void __launch_bounds__(1024) ibm_binscan_kernel(IbmMoveArgs m) {
+    __shared__ int sc[1024], se[1024];
+    const int per = (m.nblk + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(m.nblk, lo + per);
+    int c = 0, e = 0;
+    for (int b = lo; b < hi; ++b) {
+        c += m.blk[2 * b];
+        e += m.blk[2 * b + 1];
+    }
+    sc[threadIdx.x] = c;
+    se[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 1; w < 1024; w <<= 1) {  // inclusive Hillis-Steele scan
+        const int tc = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
+        const int te = threadIdx.x >= w ? se[threadIdx.x - w] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += tc;
+        se[threadIdx.x] += te;
+        __syncthreads();
+    }
+    c = sc[threadIdx.x] - c;
+    e = se[threadIdx.x] - e;
+    for (int b = lo; b < hi; ++b) {
+        const int bc = m.blk[2 * b], be = m.blk[2 * b + 1];
+        m.blk[2 * b] = c;
+        m.blk[2 * b + 1] = e;
+        c += bc;
+        e += be;
+    }
+    if (threadIdx.x == 1023) {
+        m.counts[0] = sc[1023];
+        m.counts[1] = se[1023];
+        m.csr[sc[1023]] = se[1023];
+    }
+}
+
+// cells with a count, in ascending order: (i, j, k), csr start, and the start as the fill cursor
+__global__ void __launch_bounds__(256) ibm_bincompact_kernel(IbmMoveArgs m, GridDesc g, long long ncells) {
+    __shared__ int sc[256], se[256];
+    const long long x0 = (long long)blockIdx.x * BIN_CELLS + 16 * threadIdx.x;
+    int v[16];
+    int c = 0, e = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        v[q] = x0 + q < ncells ? m.dcnt[x0 + q] : 0;
+        c += v[q] > 0;
+        e += v[q];
+    }
+    sc[threadIdx.x] = c;
+    se[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {
+        const int tc = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
+        const int te = threadIdx.x >= w ? se[threadIdx.x - w] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += tc;
+        se[threadIdx.x] += te;
+        __syncthreads();
+    }
+    int ci = m.blk[2 * blockIdx.x] + sc[threadIdx.x] - c;
+    int ei = m.blk[2 * blockIdx.x + 1] + se[threadIdx.x] - e;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        if (v[q] > 0) {
+            const long long x = x0 + q;
+            m.cell[3 * ci] = (int)(x % g.n[0]);
+            m.cell[3 * ci + 1] = (int)((x / g.n[0]) % g.n[1]);
+            m.cell[3 * ci + 2] = (int)(x / ((long long)g.n[0] * g.n[1]));
+            m.csr[ci] = ei;
+            m.dcnt[x] = ei;
+            ++ci;
+            ei += v[q];
+        }
+    }
+}
+
+// every (point, support cell) pair takes a slot of its cell
+__global__ void __launch_bounds__(256) ibm_binfill_kernel(IbmArgs a, IbmMoveArgs m) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 64LL * a.npts) return;
+    const int p = (int)(e >> 6), q = (int)(e & 63);
+    const int i = m.base[3 * p] + (q & 3) - 1, j = m.base[3 * p + 1] + ((q >> 2) & 3) - 1,
+              k = m.base[3 * p + 2] + (q >> 4) - 1;
+    const int slot = atomicAdd(&m.dcnt[flat_cell(a.g, i, j, k)], 1);
+    m.ent[slot] = p;
+}
+
+// points of a cell in ascending order (insertion sort); the cell's counter back to zero
+__global__ void __launch_bounds__(256) ibm_binsort_kernel(IbmArgs a, IbmMoveArgs m) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.counts[0]) return;
+    const int lo = m.csr[c], hi = m.csr[c + 1];
+    for (int x = lo + 1; x < hi; ++x) {
+        const int key = m.ent[x];
+        int y = x - 1;
+        while (y >= lo && m.ent[y] > key) {
+            m.ent[y + 1] = m.ent[y];
+            --y;
+        }
+        m.ent[y + 1] = key;
+    }
+    m.dcnt[flat_cell(a.g, m.cell[3 * c], m.cell[3 * c + 1], m.cell[3 * c + 2])] = 0;
+}
+
+hipError_t launch_ibm_move(const IbmArgs& a, const IbmMoveArgs& m, hipStream_t s) {
+    if (a.npts <= 0) return hipSuccess;
+    const long long ncells = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
+    const unsigned pblocks = (unsigned)((a.npts + 255) / 256);
+    const unsigned eblocks = (unsigned)((64LL * a.npts + 255) / 256);
+    hipLaunchKernelGGL(ibm_move_kernel, dim3(pblocks), dim3(256), 0, s, a, m);
+    hipLaunchKernelGGL(ibm_bincount_kernel, dim3(m.nblk), dim3(256), 0, s, m, ncells);
+    hipLaunchKernelGGL(ibm_binscan_kernel, dim3(1), dim3(1024), 0, s, m);
+    hipLaunchKernelGGL(ibm_bincompact_kernel, dim3(m.nblk), dim3(256), 0, s, m, a.g, ncells);
+    hipLaunchKernelGGL(ibm_binfill_kernel, dim3(eblocks), dim3(256), 0, s, a, m);
+    hipLaunchKernelGGL(ibm_binsort_kernel, dim3(eblocks), dim3(256), 0, s, a, m);
+    hipLaunchKernelGGL(ibm_vbar_kernel, dim3(eblocks), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_ibm_vbar(const IbmArgs& a, hipStream_t s) {

@@ -69,6 +69,7 @@ struct DevState {
     unsigned long long umax_diag_bits;
     int nonfinite;
     int ibm_iters_used;
+    int ibm_outside;  // a moving body's point support left the interior (sticky until new points)
 };
 
 struct GridDesc {

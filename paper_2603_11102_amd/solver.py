@@ -140,6 +140,19 @@ class GksSolver:
         L.check(self.lib, self.ctx, self.lib.gks_set_ibm_points(self.ctx, xyz.shape[0], xyz.ctypes.data_as(dp),
                                                                 ds.ctypes.data_as(dp),
                                                                 None if vel is None else vel.ctypes.data_as(dp)))
+        motion = getattr(ibm, "motion", None)
+        if motion is not None:
+            self.set_ibm_motion(motion)
+
+    def set_ibm_motion(self, motion):
+        """Rigid motion (centre, translation velocity, angular velocity, t0) of the body set last."""
+        m = L.gks_motion()
+        for d in range(3):
+            m.center[d] = float(motion.center[d])
+            m.velocity[d] = float(motion.velocity[d])
+            m.omega[d] = float(motion.omega[d])
+        m.t0 = float(motion.t0)
+        L.check(self.lib, self.ctx, self.lib.gks_set_ibm_motion(self.ctx, C.byref(m)))
 
     # ------------------------------------------------------------------ stepping
     def step(self, n: int = 1):

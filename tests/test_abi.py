@@ -119,3 +119,17 @@ def test_fp32_workspace_holds_the_low_order_state():
     lib = L.load()
     a = lib.gks_workspace_bytes(C.byref(_cfg()))
     assert a >= (2 + 3) * 4 * 16 ** 3 * 4
+
+
+def test_ibm_motion_null_rejected():
+    lib = L.load()
+    m = L.gks_motion()
+    assert lib.gks_set_ibm_motion(None, C.byref(m)) == L.GKS_E_INVALID_ARG
+
+
+def test_ibm_workspace_holds_the_rebinning_counters():
+    # a context that may hold immersed points reserves one counter per cell for moving bodies
+    lib = L.load()
+    a = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=10)))
+    b = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=0)))
+    assert a - b >= 4 * 16 ** 3
