@@ -142,10 +142,10 @@ size_t alm_block_bytes(int n) {
     return cv.off;
 }
 
-int bin_blocks(long long ncells) { return (int)((ncells + BIN_CELLS - 1) / BIN_CELLS); }
+int radix_tiles(long long npairs) { return (int)((npairs + RADIX_TILE - 1) / RADIX_TILE); }
 
 // Lagrangian-point block of the workspace; the carving order here and in gks_set_ibm_points agree
-size_t ibm_block_bytes(long long n, long long ncells) {
+size_t ibm_block_bytes(long long n) {
     if (n <= 0) return 0;
     const long long nc = 64 * n;
     Carver cv{nullptr, 0};
@@ -161,8 +161,10 @@ size_t ibm_block_bytes(long long n, long long ncells) {
     // rebinning of a moving body
     cv.take(sizeof(double) * 3 * n);   // positions at t0
     cv.take(sizeof(int) * 3 * n);      // lowest support cell
-    cv.take(sizeof(int) * ncells);     // per-cell counters
-    cv.take(sizeof(int) * 2 * bin_blocks(ncells));
+    for (int b = 0; b < 4; ++b) cv.take(sizeof(int) * nc);  // pair keys and values, ping-pong
+    cv.take(sizeof(int) * 256 * radix_tiles(nc));
+    cv.take(sizeof(int) * 256);
+    cv.take(sizeof(int) * radix_tiles(nc));
     cv.take(sizeof(int) * 2);
     return cv.off;
 }
@@ -184,7 +186,7 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     L->umax_part = cv.ptr<double>(sizeof(double) * UMAX_BLOCKS);
     size_t ab = alm_block_bytes(c->max_act);
     L->alm = ab ? cv.ptr<char>(ab) : nullptr;
-    size_t ib = ibm_block_bytes(c->max_ibm, (long long)N);
+    size_t ib = ibm_block_bytes(c->max_ibm);
     L->ibm = ib ? cv.ptr<char>(ib) : nullptr;
     L->total = cv.off;
     return true;
@@ -740,13 +742,16 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     a.xyz = dx;
     IbmMoveArgs& m = c->ibm_mv;
     std::memset(&m, 0, sizeof(m));
-    const long long ncells = (long long)c->g.n[0] * c->g.n[1] * c->g.n[2];
     double* dx0 = cv.ptr<double>(sizeof(double) * 3 * cap);
     m.base = cv.ptr<int>(sizeof(int) * 3 * cap);
-    m.dcnt = cv.ptr<int>(sizeof(int) * ncells);
-    m.blk = cv.ptr<int>(sizeof(int) * 2 * bin_blocks(ncells));
+    for (int b = 0; b < 2; ++b) {
+        m.key[b] = cv.ptr<unsigned>(sizeof(int) * nc);
+        m.val[b] = cv.ptr<int>(sizeof(int) * nc);
+    }
+    m.hist = cv.ptr<int>(sizeof(int) * 256 * radix_tiles(nc));
+    m.dtot = cv.ptr<int>(sizeof(int) * 256);
+    m.tcnt = cv.ptr<int>(sizeof(int) * radix_tiles(nc));
     m.counts = cv.ptr<int>(sizeof(int) * 2);
-    m.nblk = bin_blocks(ncells);
     m.xyz0 = dx0;
     m.xyz = dx;
     m.pvel = dvel;
@@ -793,8 +798,6 @@ int gks_set_ibm_motion(gks_ctx* c, const gks_motion* mo) {
         m.omega[d] = mo->omega[d];
     }
     m.t0 = mo->t0;
-    const long long ncells = (long long)c->g.n[0] * c->g.n[1] * c->g.n[2];
-    HIPCHK(c, launch_zero_words(m.dcnt, sizeof(int) * (size_t)ncells, c->stream));
     HIPCHK(c, launch_zero_words(&c->st->ibm_outside, sizeof(int), c->stream));
     IbmArgs& a = c->ibm;
     a.vel = m.pvel;

@@ -55,15 +55,17 @@ struct IbmMoveArgs {
     double* xyz;         // device, 3 npts: positions of the step (IbmArgs::xyz)
     double* pvel;        // device, 3 npts: velocities of the step (IbmArgs::vel)
     int* base;           // device, 3 npts: lowest support cell per axis (clamped into the interior)
-    int* dcnt;           // device, one counter per interior cell; all zero between steps
-    int* blk;            // device, 2 per block of BIN_CELLS cells: cells and entries, then their offsets
-    int* counts;         // device, [0] cells, [1] entries
+    unsigned* key[2];    // device, 64 npts each: cell index of the (cell, point) pairs, ping-pong
+    int* val[2];         // device, 64 npts each: point index of the pairs
+    int* hist;           // device, 256 * tiles: digit counts per tile, digit-major
+    int* dtot;           // device, 256: pairs per digit
+    int* tcnt;           // device, tiles: cells starting in each tile, then their offsets
+    int* counts;         // device, [0] cells, [1] pairs
     int* cell;           // device, 3 * 64 npts (IbmArgs::cell)
-    int* csr;            // device, 64 npts + 1
-    int* ent;            // device, 64 npts
-    int nblk;            // ceil(cells / BIN_CELLS)
+    int* csr;            // device, 64 npts + 1 (IbmArgs::csr)
+    int* ent;            // device, 64 npts: points per cell, the output of the pair sort (IbmArgs::ent)
 };
-constexpr int BIN_CELLS = 4096;  // dense cells per workgroup of the compaction (256 threads x 16)
+constexpr int RADIX_TILE = 2048;  // pairs per workgroup of the sort and compaction passes (8 rounds of 256)
 
 // Tip-correction factor f = (2/pi) acos(min(1, exp(-g1 N (R - r) / (2 r sin phi)))) and df/dphi.
 __device__ __forceinline__ double tip_factor(double g1, int N, double R, double r, double phi, double* dfdphi) {

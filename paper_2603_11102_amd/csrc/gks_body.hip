@@ -201,22 +201,34 @@ __device__ __forceinline__ double ibm_weight(const GridDesc& g, const double* X,
     return phi4d(rx) * phi4d(ry) * phi4d(rz);
 }
 
-// static V-bar_c = sum over the points whose support holds c of W V_p, and the cell velocity
-// v-bar_c = sum W V_p v_p / V-bar_c (fixed point order)
-__global__ void __launch_bounds__(256) ibm_vbar_kernel(IbmArgs a) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (a.ncell_dev ? *a.ncell_dev : a.ncell)) return;
+// V-bar_c = sum over the points whose support holds c of W V_p and the cell velocity
+// v-bar_c = sum W V_p v_p / V-bar_c; one wavefront per cell: the lanes take the cell's points in
+// strides of 64, then a butterfly sum (a fixed order, the same for every call)
+__device__ __forceinline__ void vbar_cell(const IbmArgs& a, int c, int lane) {
     const int i = a.cell[3 * c], j = a.cell[3 * c + 1], k = a.cell[3 * c + 2];
     double v = 0.0, mv[3] = {0.0, 0.0, 0.0};
-    for (int e = a.csr[c]; e < a.csr[c + 1]; ++e) {
+    for (int e = a.csr[c] + lane; e < a.csr[c + 1]; e += 64) {
         const int p = a.ent[e];
         const double wv = ibm_weight(a.g, a.xyz + 3 * p, i, j, k) * (a.g.h[0] * a.dS[p]);
         v += wv;
         if (a.vel)
             for (int d = 0; d < 3; ++d) mv[d] += wv * a.vel[3 * p + d];
     }
-    a.vbar[c] = v;
-    for (int d = 0; d < 3; ++d) a.vbar_vel[3 * c + d] = (a.vel && v > 0.0) ? mv[d] / v : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+        v += __shfl_xor(v, o, 64);
+        for (int d = 0; d < 3; ++d) mv[d] += __shfl_xor(mv[d], o, 64);
+    }
+    if (lane == 0) {
+        a.vbar[c] = v;
+        for (int d = 0; d < 3; ++d) a.vbar_vel[3 * c + d] = (a.vel && v > 0.0) ? mv[d] / v : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) ibm_vbar_kernel(IbmArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int nc = a.ncell_dev ? *a.ncell_dev : a.ncell;
+    for (int c = blockIdx.x * 4 + (threadIdx.x >> 6); c < nc; c += gridDim.x * 4)  // uniform over the wavefront
+        vbar_cell(a, c, lane);
 }
 
 // per cell: S direct-forcing iterations towards v-bar; FP64 block partials of sum F
@@ -304,7 +316,8 @@ __global__ void __launch_bounds__(256) ibm_resid_kernel(Field4<real> f, IbmArgs 
 
 // ------------------------------------------------------------------------------------------------
 // moving body: the positions of the step and its supports rebuilt on the device, in the order of
-// the host binning (cells ascending, x fastest; points ascending within a cell)
+// the host binning (cells ascending, x fastest; points ascending within a cell): the (cell, point)
+// pairs are sorted by cell with a stable radix sort, then the first pair of every cell is compacted
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ long long flat_cell(const GridDesc& g, int i, int j, int k) {
     return ((long long)k * g.n[1] + j) * g.n[0] + i;
@@ -313,7 +326,8 @@ __device__ __forceinline__ long long flat_cell(const GridDesc& g, int i, int j, 
 // Rigid motion to t^{n+1}: X_p = X_p(t0) + V tau + (R - I) r with r = X_p(t0) - c0 and
 // (R - I) r = sin(theta) k x r + (1 - cos theta) k x (k x r) (Rodrigues), v_p = V + omega x R r.
 // Lowest support cell per axis, clamped into the interior when the support leaves it (then the
-// flag stops the forcing); one count per support cell.
+// flag stops the forcing; the clamp keeps every later index valid: points were accepted by
+// gks_set_ibm_points, so every axis has at least 4 cells).
 __global__ void __launch_bounds__(256) ibm_move_kernel(IbmArgs a, IbmMoveArgs m) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.npts) return;
@@ -340,179 +354,223 @@ __global__ void __launch_bounds__(256) ibm_move_kernel(IbmArgs a, IbmMoveArgs m)
     const double v[3] = {m.vel[0] + m.omega[1] * rr[2] - m.omega[2] * rr[1],
                          m.vel[1] + m.omega[2] * rr[0] - m.omega[0] * rr[2],
                          m.vel[2] + m.omega[0] * rr[1] - m.omega[1] * rr[0]};
-    int b[3];
     bool out = false;
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
         const double f = (X[x] - a.g.x0[x]) / a.g.h[x] - 0.5;
+        int b;
         if (f >= 1.0 && f < (double)(a.g.n[x] - 2)) {
-            b[x] = (int)floor(f);
+            b = (int)floor(f);
         } else {  // also NaN
             out = true;
-            b[x] = f >= 1.0 ? a.g.n[x] - 3 : 1;
+            b = f >= 1.0 ? a.g.n[x] - 3 : 1;
         }
         m.xyz[3 * p + x] = X[x];
         m.pvel[3 * p + x] = v[x];
-        m.base[3 * p + x] = b[x];
+        m.base[3 * p + x] = b;
     }
     if (out) atomicOr(&a.st->ibm_outside, 1);
-    for (int dk = -1; dk <= 2; ++dk)
-        for (int dj = -1; dj <= 2; ++dj)
-            for (int di = -1; di <= 2; ++di) atomicAdd(&m.dcnt[flat_cell(a.g, b[0] + di, b[1] + dj, b[2] + dk)], 1);
 }
 
-// block sums of (cells with a count, entries) over BIN_CELLS consecutive cells, 16 per thread
-__global__ void __launch_bounds__(256) ibm_bincount_kernel(IbmMoveArgs m, long long ncells) {
-    __shared__ int sc[256], se[256];
-    const long long x0 = (long long)blockIdx.x * BIN_CELLS + 16 * threadIdx.x;
-    int c = 0, e = 0;
-    for (int q = 0; q < 16; ++q) {
-        if (x0 + q < ncells) {
-            const int v = m.dcnt[x0 + q];
-            c += v > 0;
-            e += v;
-        }
-    }
-    sc[threadIdx.x] = c;
-    se[threadIdx.x] = e;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            sc[threadIdx.x] += sc[threadIdx.x + w];
-            se[threadIdx.x] += se[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        m.blk[2 * blockIdx.x] = sc[0];
-        m.blk[2 * blockIdx.x + 1] = se[0];
-    }
-}
+unsigned vbar_blocks(int ncell) { return (unsigned)std::min(4096, (ncell + 3) / 4); }
 
-// exclusive scan of the block sums in place (one workgroup, a contiguous run of blocks per thread);
-// totals to counts[0..1] and csr[cells] = entries
-__global__ void __launch_bounds__(1024) ibm_binscan_kernel(IbmMoveArgs m) {
-    __shared__ int sc[1024], se[1024];
-    const int per = (m.nblk + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(m.nblk, lo + per);
-    int c = 0, e = 0;
-    for (int b = lo; b < hi; ++b) {
-        c += m.blk[2 * b];
-        e += m.blk[2 * b + 1];
-    }
-    sc[threadIdx.x] = c;
-    se[threadIdx.x] = e;
-    __syncthreads();
-    for (int w = 1; w < 1024; w <<= 1) {  // inclusive Hillis-Steele scan
-        const int tc = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
-        const int te = threadIdx.x >= w ? se[threadIdx.x - w] : 0;
-        __syncthreads();
-        sc[threadIdx.x] += tc;
-        se[threadIdx.x] += te;
-        __syncthreads();
-    }
-    c = sc[threadIdx.x] - c;
-    e = se[threadIdx.x] - e;
-    for (int b = lo; b < hi; ++b) {
-        const int bc = m.blk[2 * b], be = m.blk[2 * b + 1];
-        m.blk[2 * b] = c;
-        m.blk[2 * b + 1] = e;
-        c += bc;
-        e += be;
-    }
-    if (threadIdx.x == 1023) {
-        m.counts[0] = sc[1023];
-        m.counts[1] = se[1023];
-        m.csr[sc[1023]] = se[1023];
-    }
-}
-
-// cells with a count, in ascending order: (i, j, k), csr start, and the start as the fill cursor
-__global__ void __launch_bounds__(256) ibm_bincompact_kernel(IbmMoveArgs m, GridDesc g, long long ncells) {
-    __shared__ int sc[256], se[256];
-    const long long x0 = (long long)blockIdx.x * BIN_CELLS + 16 * threadIdx.x;
-    int v[16];
-    int c = 0, e = 0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        v[q] = x0 + q < ncells ? m.dcnt[x0 + q] : 0;
-        c += v[q] > 0;
-        e += v[q];
-    }
-    sc[threadIdx.x] = c;
-    se[threadIdx.x] = e;
-    __syncthreads();
-    for (int w = 1; w < 256; w <<= 1) {
-        const int tc = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
-        const int te = threadIdx.x >= w ? se[threadIdx.x - w] : 0;
-        __syncthreads();
-        sc[threadIdx.x] += tc;
-        se[threadIdx.x] += te;
-        __syncthreads();
-    }
-    int ci = m.blk[2 * blockIdx.x] + sc[threadIdx.x] - c;
-    int ei = m.blk[2 * blockIdx.x + 1] + se[threadIdx.x] - e;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        if (v[q] > 0) {
-            const long long x = x0 + q;
-            m.cell[3 * ci] = (int)(x % g.n[0]);
-            m.cell[3 * ci + 1] = (int)((x / g.n[0]) % g.n[1]);
-            m.cell[3 * ci + 2] = (int)(x / ((long long)g.n[0] * g.n[1]));
-            m.csr[ci] = ei;
-            m.dcnt[x] = ei;
-            ++ci;
-            ei += v[q];
-        }
-    }
-}
-
-// every (point, support cell) pair takes a slot of its cell
-__global__ void __launch_bounds__(256) ibm_binfill_kernel(IbmArgs a, IbmMoveArgs m) {
+// (cell, point) pairs in point-major order: item e = 64 p + q is the q-th support cell of point p
+__global__ void __launch_bounds__(256) ibm_pairs_kernel(IbmArgs a, IbmMoveArgs m) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 64LL * a.npts) return;
     const int p = (int)(e >> 6), q = (int)(e & 63);
     const int i = m.base[3 * p] + (q & 3) - 1, j = m.base[3 * p + 1] + ((q >> 2) & 3) - 1,
               k = m.base[3 * p + 2] + (q >> 4) - 1;
-    const int slot = atomicAdd(&m.dcnt[flat_cell(a.g, i, j, k)], 1);
-    m.ent[slot] = p;
+    m.key[0][e] = (unsigned)flat_cell(a.g, i, j, k);
+    m.val[0][e] = p;
 }
 
-// points of a cell in ascending order (insertion sort); the cell's counter back to zero
-__global__ void __launch_bounds__(256) ibm_binsort_kernel(IbmArgs a, IbmMoveArgs m) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m.counts[0]) return;
-    const int lo = m.csr[c], hi = m.csr[c + 1];
-    for (int x = lo + 1; x < hi; ++x) {
-        const int key = m.ent[x];
-        int y = x - 1;
-        while (y >= lo && m.ent[y] > key) {
-            m.ent[y + 1] = m.ent[y];
-            --y;
-        }
-        m.ent[y + 1] = key;
+// exclusive scan of 256 values held one per thread (Hillis-Steele in LDS); returns the total
+__device__ __forceinline__ int block_exclusive_scan_256(int v, int* sh, int* excl) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {
+        const int u = threadIdx.x >= w ? sh[threadIdx.x - w] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += u;
+        __syncthreads();
     }
-    m.dcnt[flat_cell(a.g, m.cell[3 * c], m.cell[3 * c + 1], m.cell[3 * c + 2])] = 0;
+    *excl = sh[threadIdx.x] - v;
+    const int total = sh[255];
+    __syncthreads();
+    return total;
+}
+
+// Stable least-significant-digit radix sort of the pairs by cell, 8 bits per pass; stability keeps
+// the points of a cell in ascending order. A tile is RADIX_TILE consecutive items, 256 per round.
+__global__ void __launch_bounds__(256) radix_hist_kernel(const unsigned* key, int n, int shift, int* hist, int ntiles) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const long long t0 = (long long)blockIdx.x * RADIX_TILE;
+    for (int r = 0; r < RADIX_TILE / 256; ++r) {
+        const long long e = t0 + r * 256 + threadIdx.x;
+        if (e < n) atomicAdd(&h[(key[e] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];  // digit-major
+}
+
+// one workgroup per digit: exclusive scan in place of the digit's tile counts, digit total to dtot
+__global__ void __launch_bounds__(256) radix_digit_scan_kernel(int* hist, int ntiles, int* dtot) {
+    __shared__ int sh[256];
+    int* h = hist + (long long)blockIdx.x * ntiles;
+    const int per = (ntiles + 255) / 256;
+    const int lo = threadIdx.x * per, hi = min(ntiles, lo + per);
+    int t = 0;
+    for (int x = lo; x < hi; ++x) t += h[x];
+    int run;
+    const int total = block_exclusive_scan_256(t, sh, &run);
+    for (int x = lo; x < hi; ++x) {
+        const int v = h[x];
+        h[x] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = total;
+}
+
+// scatter with stable ranks: within a round a lane's rank among the earlier lanes of its wavefront
+// with the same digit (ballot match), plus the counts of the earlier wavefronts, plus the running
+// count of the tile's earlier rounds, plus the tile's offset within its digit and the digit's base
+__global__ void __launch_bounds__(256) radix_scatter_kernel(const unsigned* key, const int* val, unsigned* key_out,
+                                                            int* val_out, int n, int shift, const int* hist,
+                                                            const int* dtot, int ntiles) {
+    __shared__ int sh[256];
+    __shared__ int run[256];
+    __shared__ int wc[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int base;
+    block_exclusive_scan_256(dtot[threadIdx.x], sh, &base);
+    run[threadIdx.x] = base + hist[threadIdx.x * ntiles + blockIdx.x];
+    const long long t0 = (long long)blockIdx.x * RADIX_TILE;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    for (int r = 0; r < RADIX_TILE / 256; ++r) {
+        for (int x = 0; x < 4; ++x) wc[x][threadIdx.x] = 0;
+        __syncthreads();
+        const long long e = t0 + r * 256 + threadIdx.x;
+        const bool ok = e < n;
+        const unsigned kk = ok ? key[e] : 0u;
+        const int d = (int)((kk >> shift) & 255);
+        unsigned long long mask = __ballot(ok);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const unsigned long long bb = __ballot(bit);
+            mask &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(mask & below);
+        if (ok && rank == 0) wc[w][d] = __popcll(mask);
+        __syncthreads();
+        if (ok) {
+            int off = run[d] + rank;
+            for (int x = 0; x < w; ++x) off += wc[x][d];
+            key_out[off] = kk;
+            val_out[off] = val[e];
+        }
+        __syncthreads();
+        run[threadIdx.x] += wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] + wc[3][threadIdx.x];
+    }
+}
+
+__device__ __forceinline__ bool run_head(const unsigned* key, long long e, int n) {
+    return e < n && (e == 0 || key[e] != key[e - 1]);
+}
+
+// first pairs of cells (run heads of the sorted keys) per tile
+__global__ void __launch_bounds__(256) ibm_head_count_kernel(const unsigned* key, int n, int* tcnt) {
+    __shared__ int sh[256];
+    const long long t0 = (long long)blockIdx.x * RADIX_TILE;
+    int c = 0;
+    for (int r = 0; r < RADIX_TILE / 256; ++r) c += run_head(key, t0 + r * 256 + threadIdx.x, n);
+    int excl;
+    const int total = block_exclusive_scan_256(c, sh, &excl);
+    if (threadIdx.x == 0) tcnt[blockIdx.x] = total;
+}
+
+// exclusive scan in place of the per-tile head counts (one workgroup, a contiguous run per thread);
+// the number of cells to counts[0] and csr[cells] = n
+__global__ void __launch_bounds__(256) ibm_head_scan_kernel(int* tcnt, int ntiles, int n, int* counts, int* csr) {
+    __shared__ int sh[256];
+    const int per = (ntiles + 255) / 256;
+    const int lo = threadIdx.x * per, hi = min(ntiles, lo + per);
+    int t = 0;
+    for (int x = lo; x < hi; ++x) t += tcnt[x];
+    int run;
+    const int total = block_exclusive_scan_256(t, sh, &run);
+    for (int x = lo; x < hi; ++x) {
+        const int v = tcnt[x];
+        tcnt[x] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        counts[0] = total;
+        counts[1] = n;
+        csr[total] = n;
+    }
+}
+
+// cells in ascending order: (i, j, k) and the index of their first pair (csr)
+__global__ void __launch_bounds__(256) ibm_head_compact_kernel(const unsigned* key, int n, const int* tcnt, GridDesc g,
+                                                               int* cell, int* csr) {
+    __shared__ int wc[4];
+    __shared__ int run;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) run = tcnt[blockIdx.x];
+    const long long t0 = (long long)blockIdx.x * RADIX_TILE;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    for (int r = 0; r < RADIX_TILE / 256; ++r) {
+        const long long e = t0 + r * 256 + threadIdx.x;
+        const bool hd = run_head(key, e, n);
+        const unsigned long long b = __ballot(hd);
+        if (lane == 0) wc[w] = __popcll(b);
+        __syncthreads();
+        if (hd) {
+            int c = run + __popcll(b & below);
+            for (int x = 0; x < w; ++x) c += wc[x];
+            const long long x = key[e];
+            cell[3 * c] = (int)(x % g.n[0]);
+            cell[3 * c + 1] = (int)((x / g.n[0]) % g.n[1]);
+            cell[3 * c + 2] = (int)(x / ((long long)g.n[0] * g.n[1]));
+            csr[c] = (int)e;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) run += wc[0] + wc[1] + wc[2] + wc[3];
+    }
 }
 
 hipError_t launch_ibm_move(const IbmArgs& a, const IbmMoveArgs& m, hipStream_t s) {
     if (a.npts <= 0) return hipSuccess;
     const long long ncells = (long long)a.g.n[0] * a.g.n[1] * a.g.n[2];
-    const unsigned pblocks = (unsigned)((a.npts + 255) / 256);
-    const unsigned eblocks = (unsigned)((64LL * a.npts + 255) / 256);
-    hipLaunchKernelGGL(ibm_move_kernel, dim3(pblocks), dim3(256), 0, s, a, m);
-    hipLaunchKernelGGL(ibm_bincount_kernel, dim3(m.nblk), dim3(256), 0, s, m, ncells);
-    hipLaunchKernelGGL(ibm_binscan_kernel, dim3(1), dim3(1024), 0, s, m);
-    hipLaunchKernelGGL(ibm_bincompact_kernel, dim3(m.nblk), dim3(256), 0, s, m, a.g, ncells);
-    hipLaunchKernelGGL(ibm_binfill_kernel, dim3(eblocks), dim3(256), 0, s, a, m);
-    hipLaunchKernelGGL(ibm_binsort_kernel, dim3(eblocks), dim3(256), 0, s, a, m);
-    hipLaunchKernelGGL(ibm_vbar_kernel, dim3(eblocks), dim3(256), 0, s, a);
+    const int n = 64 * a.npts;
+    const int ntiles = (n + RADIX_TILE - 1) / RADIX_TILE;
+    hipLaunchKernelGGL(ibm_move_kernel, dim3((a.npts + 255) / 256), dim3(256), 0, s, a, m);
+    hipLaunchKernelGGL(ibm_pairs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, m);
+    int bits = 1;
+    while (bits < 32 && (1LL << bits) < ncells) ++bits;
+    const int passes = (bits + 7) / 8;
+    int src = 0;
+    for (int ps = 0; ps < passes; ++ps, src ^= 1) {
+        const bool last = ps == passes - 1;
+        hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(256), 0, s, m.key[src], n, 8 * ps, m.hist, ntiles);
+        hipLaunchKernelGGL(radix_digit_scan_kernel, dim3(256), dim3(256), 0, s, m.hist, ntiles, m.dtot);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(256), 0, s, m.key[src], m.val[src], m.key[src ^ 1],
+                           last ? m.ent : m.val[src ^ 1], n, 8 * ps, m.hist, m.dtot, ntiles);
+    }
+    const unsigned* sorted = m.key[src];
+    hipLaunchKernelGGL(ibm_head_count_kernel, dim3(ntiles), dim3(256), 0, s, sorted, n, m.tcnt);
+    hipLaunchKernelGGL(ibm_head_scan_kernel, dim3(1), dim3(256), 0, s, m.tcnt, ntiles, n, m.counts, m.csr);
+    hipLaunchKernelGGL(ibm_head_compact_kernel, dim3(ntiles), dim3(256), 0, s, sorted, n, m.tcnt, a.g, m.cell, m.csr);
+    hipLaunchKernelGGL(ibm_vbar_kernel, dim3(vbar_blocks(n)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_ibm_vbar(const IbmArgs& a, hipStream_t s) {
     if (a.ncell <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ibm_vbar_kernel, dim3((a.ncell + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(ibm_vbar_kernel, dim3(vbar_blocks(a.ncell)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -127,9 +127,10 @@ def test_ibm_motion_null_rejected():
     assert lib.gks_set_ibm_motion(None, C.byref(m)) == L.GKS_E_INVALID_ARG
 
 
-def test_ibm_workspace_holds_the_rebinning_counters():
-    # a context that may hold immersed points reserves one counter per cell for moving bodies
+def test_ibm_workspace_holds_the_rebinning_pairs():
+    # a context that may hold immersed points reserves, per point, its 64 (cell, point) pairs twice
+    # over for the sort that rebuilds the supports of a moving body
     lib = L.load()
-    a = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=10)))
+    a = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=1000)))
     b = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=0)))
-    assert a - b >= 4 * 16 ** 3
+    assert a - b >= 1000 * 64 * 4 * 4
