@@ -62,6 +62,17 @@ R16 Moving immersed bodies (the introduction has the Lagrangian points follow th
     X_p(t) = c(t) + R(omega (t - t0)) (X_p(t0) - c0), v_p(t) = V + omega x (X_p(t) - c(t)). The
     forcing that closes the step from t^n to t^{n+1} uses X_p(t^{n+1}) and v_p(t^{n+1}); supports,
     weights, V-bar and v-bar are rebuilt from them every step.
+R17 Stretched meshes (the channel of Section 4.1 is computed on a tanh-clustered mesh given by a
+    coordinate transformation of a uniform computational mesh; the scheme section states the method
+    for uniform cells only): per axis, cell faces x_{i-1/2}; the reconstructions (WENO and the linear
+    stencils) act on the cell averages in index space exactly as on a uniform mesh; the chain rule
+    turns index derivatives into physical ones with the local spacing: the normal derivative at face
+    i-1/2 divides by the distance of the two adjacent cell centres (w_{i-1} + w_i)/2 (the adjacent
+    width at the two boundary faces), a tangential derivative along a cell line by that line's width
+    w_j; the face flux is the mean of its 2x2 Gauss-point fluxes times the face area, so the cell
+    update divides the flux difference by the normal width w_i; the CFL step takes the smallest
+    width. A uniform axis gives exactly the uniform scheme. Periodic axes and bodies need uniform
+    axes.
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
     momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
     U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).
@@ -83,7 +94,7 @@ __all__ = [
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
     "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics", "van_leer", "muscl_faces",
-    "rotation_matrix", "ibm_motion_state",
+    "rotation_matrix", "ibm_motion_state", "axis_metrics", "mesh_faces",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -245,14 +256,52 @@ def ghost_fill(Q, cfg):
     return A
 
 
+def mesh_faces(cfg, a):
+    """Cell faces along axis a (n + 1 coordinates): the stretched mesh's, else uniform."""
+    n = (cfg.nx, cfg.ny, cfg.nz)[a]
+    faces = getattr(cfg, "faces", None)
+    if faces is None or faces[a] is None:
+        x0, length = (cfg.x0, cfg.y0, cfg.z0)[a], (cfg.lx, cfg.ly, cfg.lz)[a]
+        return x0 + length * np.arange(n + 1) / n
+    f = np.asarray(faces[a], dtype=np.float64)
+    if f.shape != (n + 1,) or not np.all(np.diff(f) > 0):
+        raise ValueError("faces of axis %d must be %d increasing coordinates" % (a, n + 1))
+    return f
+
+
+def axis_metrics(cfg, a):
+    """Cell widths w_i [n] and face spacings [n + 1] along axis a (reading R17): the spacing at an
+    interior face is the distance of the adjacent cell centres, at a boundary face the adjacent width.
+    A uniform axis gives its cell size h everywhere."""
+    n = (cfg.nx, cfg.ny, cfg.nz)[a]
+    faces = getattr(cfg, "faces", None)
+    if faces is None or faces[a] is None:
+        h = (cfg.dx, cfg.dy, cfg.dz)[a]
+        return np.full(n, h), np.full(n + 1, h)
+    if cfg.bc[2 * a] == "periodic":
+        raise ValueError("a periodic axis must be uniform")
+    w = np.diff(mesh_faces(cfg, a))
+    hf = np.empty(n + 1)
+    hf[1:-1] = 0.5 * (w[:-1] + w[1:])
+    hf[0], hf[-1] = w[0], w[-1]
+    return w, hf
+
+
+def _uniform_mesh(cfg):
+    faces = getattr(cfg, "faces", None)
+    return faces is None or all(f is None for f in faces)
+
+
 def cfl_dt(Q, cfg):
-    """dt = CFL min(dx,dy,dz) / (|U|_max + C), |U|_max over the cells (Section 2); or the fixed dt."""
+    """dt = CFL h_min / (|U|_max + C), |U|_max over the cells, h_min the smallest cell width (Section 2;
+    reading R17 on stretched meshes); or the fixed dt."""
     if cfg.cfl <= 0:
         return float(cfg.dt_fixed)
     c = constants(cfg)["c"]
     u = Q[1:] / Q[0:1]
     umax = float(torch.sqrt((u * u).sum(0)).max())
-    return cfg.cfl * min(cfg.dx, cfg.dy, cfg.dz) / (umax + c)
+    hmin = min(float(axis_metrics(cfg, a)[0].min()) for a in range(3))
+    return cfg.cfl * hmin / (umax + c)
 
 
 # ================================================================================================
@@ -392,8 +441,14 @@ def _global(A, d):
 
 
 def _spacings(cfg, d):
-    dx, dy, dz = cfg.dx, cfg.dy, cfg.dz
-    return ((dx, dy, dz), (dy, dx, dz), (dz, dx, dy))[d]
+    """Metrics of direction d in the local layout [var, t2, t1, normal] (reading R17): face spacings
+    along the normal [N + 1], normal widths [N], t1 line widths [T1, 1], t2 line widths [T2, 1, 1]."""
+    axes = ((0, 1, 2), (1, 0, 2), (2, 0, 1))[d]
+    wn, hfn = axis_metrics(cfg, axes[0])
+    w1, _ = axis_metrics(cfg, axes[1])
+    w2, _ = axis_metrics(cfg, axes[2])
+    t = lambda x: torch.tensor(x, dtype=F64)
+    return t(hfn), t(wn), t(w1).view(-1, 1), t(w2).view(-1, 1, 1)
 
 
 def _grads_global(d, dn, dt1, dt2):
@@ -402,7 +457,7 @@ def _grads_global(d, dn, dt1, dt2):
 
 def _direction(P, d, cfg, lam, need_f0, ctl, chunk):
     """Face fluxes in direction d and their divergence contributions (per unit volume)."""
-    hn, h1, h2 = _spacings(cfg, d)
+    hf, wn, h1, h2 = _spacings(cfg, d)
     A = _local(P, d)
     T2, T1, N = A.shape[1] - 2 * NG, A.shape[2] - 2 * NG, A.shape[3] - 2 * NG
     eps = cfg.weno_eps
@@ -420,7 +475,7 @@ def _direction(P, d, cfg, lam, need_f0, ctl, chunk):
 
         qL = weno_point([cell(-3), cell(-2), cell(-1), cell(0), cell(1)], 0.5, eps, ctl)
         qR = weno_point([cell(-2), cell(-1), cell(0), cell(1), cell(2)], -0.5, eps, ctl)
-        D = sum(float(wd[r]) * cell(r - 2) for r in range(4)) / hn
+        D = sum(float(wd[r]) * cell(r - 2) for r in range(4)) / hf
         C = 0.5 * (qL + qR)
 
         def sl1(X, r):
@@ -445,15 +500,15 @@ def _direction(P, d, cfg, lam, need_f0, ctl, chunk):
                 gR = weno_point([sl2(t1[m]["R"], r) for r in range(5)], xn, eps, ctl)
                 dn = linear_point([sl2(t1[m]["D"], r) for r in range(5)], xn)
                 dt1 = linear_point([sl2(t1[m]["Ct1"], r) for r in range(5)], xn)
-                dt2 = linear_point([sl2(t1[m]["C"], r) for r in range(5)], xn, 1) / h2
+                dt2 = linear_point([sl2(t1[m]["C"], r) for r in range(5)], xn, 1) / h2[k0:k1]
                 Q0 = kinetic_average(gL, gR, d, lam)
                 F0, F1 = gks_point_flux(Q0, _grads_global(d, dn, dt1, dt2), d, lam, cfg.mu, need_f0)
                 F1s = F1s + 0.25 * F1
                 if need_f0:
                     F0s = F0s + 0.25 * F0
-        L1.append(-(F1s[..., 1:] - F1s[..., :-1]) / hn)
+        L1.append(-(F1s[..., 1:] - F1s[..., :-1]) / wn)
         if need_f0:
-            L0.append(-(F0s[..., 1:] - F0s[..., :-1]) / hn)
+            L0.append(-(F0s[..., 1:] - F0s[..., :-1]) / wn)
         k0 = k1
     L1 = _global(torch.cat(L1, 1), d)
     L0 = _global(torch.cat(L0, 1), d) if need_f0 else None
@@ -479,7 +534,7 @@ def muscl_faces(qm2, qm1, q0, qp1):
 def _direction_order2(P, d, cfg, lam, need_f0):
     """Second-order variant (reading R15): limited linear face states, central-difference gradients,
     one flux evaluation at the face centre."""
-    hn, h1, h2 = _spacings(cfg, d)
+    hf, wn, h1, h2 = _spacings(cfg, d)
     A = _local(P, d)
     T2, T1, N = A.shape[1] - 2 * NG, A.shape[2] - 2 * NG, A.shape[3] - 2 * NG
 
@@ -488,7 +543,7 @@ def _direction_order2(P, d, cfg, lam, need_f0):
         return A[:, NG + dk:NG + dk + T2, NG + dj:NG + dj + T1, NG + rel:NG + rel + N + 1]
 
     qL, qR = muscl_faces(cell(-2), cell(-1), cell(0), cell(1))
-    dn = (cell(0) - cell(-1)) / hn
+    dn = (cell(0) - cell(-1)) / hf
 
     def face_avg(dj, dk):
         return 0.5 * (cell(-1, dj, dk) + cell(0, dj, dk))
@@ -497,8 +552,8 @@ def _direction_order2(P, d, cfg, lam, need_f0):
     dt2 = (face_avg(0, 1) - face_avg(0, -1)) / (2.0 * h2)
     Q0 = kinetic_average(qL, qR, d, lam)
     F0, F1 = gks_point_flux(Q0, _grads_global(d, dn, dt1, dt2), d, lam, cfg.mu, need_f0)
-    L1 = _global(-(F1[..., 1:] - F1[..., :-1]) / hn, d)
-    L0 = _global(-(F0[..., 1:] - F0[..., :-1]) / hn, d) if need_f0 else None
+    L1 = _global(-(F1[..., 1:] - F1[..., :-1]) / wn, d)
+    L0 = _global(-(F0[..., 1:] - F0[..., :-1]) / wn, d) if need_f0 else None
     return L0, L1
 
 
@@ -588,6 +643,8 @@ def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     """Sample, blade-element forces, Gaussian projection truncated at 3 eps, momentum update
     (Section 3.1, Eqs. (axial-tangential), (Gaussian); Section 3.3; reading R9).
     Returns (Q_new, outputs)."""
+    if not _uniform_mesh(cfg):
+        raise ValueError("the actuator line model needs a uniform mesh (reading R17)")
     X, et = rotor_points(rotor, t)
     n = X.shape[0]
     if scales is None:
@@ -696,6 +753,8 @@ class IbmCache:
 def ibm_setup(cfg, ibm):
     """W_{p->ijk} = phi4((x_i-X)/dx) phi4((y_j-Y)/dy) phi4((z_k-Z)/dz); V_p = dx dS_p;
     V-bar_ijk = sum_p W V_p (Section 3.2); v-bar_ijk = sum_p W V_p v_p / V-bar_ijk (reading R14)."""
+    if not _uniform_mesh(cfg):
+        raise ValueError("immersed bodies need a uniform mesh (reading R17)")
     X = np.asarray(ibm.xyz, dtype=np.float64)
     n = X.shape[0]
     org = np.array([cfg.x0, cfg.y0, cfg.z0])
@@ -795,9 +854,13 @@ def ibm_apply(Q, dt, cfg, cache, iters):
 # step driver
 # ================================================================================================
 
-def conservation_sums(Q):
-    """Mass and momentum totals over the interior cells (per unit cell volume), exactly summed."""
+def conservation_sums(Q, cfg=None):
+    """Mass and momentum totals over the interior cells (per unit cell volume), exactly summed; on a
+    stretched mesh (cfg given) each cell weighs its volume over the uniform cell volume."""
     a = Q.detach().numpy()
+    if cfg is not None and not _uniform_mesh(cfg):
+        w = [axis_metrics(cfg, x)[0] / (cfg.dx, cfg.dy, cfg.dz)[x] for x in range(3)]
+        a = a * (w[2][:, None, None] * w[1][None, :, None] * w[0][None, None, :])[None]
     return [math.fsum(a[v].reshape(-1).tolist()) for v in range(4)]
 
 

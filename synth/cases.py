@@ -26,7 +26,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-CASE_NAMES = ("tgv", "channel", "alm", "alm_ibm", "adjoint")
+CASE_NAMES = ("tgv", "channel", "alm", "alm_ibm", "adjoint", "channel_tanh")
 
 
 @dataclass
@@ -113,6 +113,9 @@ class CaseConfig:
     ibm: Optional[IbmSpec] = None
     q0: Optional[np.ndarray] = field(default=None, repr=False)  # [4, nz, ny, nx]: rho, rho U, rho V, rho W
     seed: int = 0
+    # cell faces per axis (n + 1 increasing coordinates from the origin to origin + length) of a
+    # stretched mesh, None for a uniform axis
+    faces: Optional[tuple] = field(default=None, repr=False)
 
     @property
     def dx(self) -> float:
@@ -276,7 +279,8 @@ def make_case(name: str, grid: Optional[Sequence[int]] = None, seed: Optional[in
     rotor keep their size in rotor diameters; the cell count per diameter follows the grid)."""
     if name not in CASE_NAMES:
         raise ValueError(f"unknown case {name!r}")
-    builder = {"tgv": _tgv, "channel": _channel, "alm": _alm, "alm_ibm": _alm_ibm, "adjoint": _adjoint}[name]
+    builder = {"tgv": _tgv, "channel": _channel, "alm": _alm, "alm_ibm": _alm_ibm, "adjoint": _adjoint,
+               "channel_tanh": _channel_tanh}[name]
     cfg = builder(grid, seed)
     if steps is not None:
         cfg = cfg.with_(steps=steps)
@@ -325,6 +329,38 @@ def _channel(grid, seed):
                       ma=0.1, u_ref=1.0, rho_ref=1.0, mu=nu, cfl=0.5, dt_fixed=0.0,
                       bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
                       body_force=(u_tau * u_tau, 0.0, 0.0), steps=100, q0=q, seed=seed)
+
+
+def tanh_faces(n: int, b: float = 2.0) -> np.ndarray:
+    """Wall-clustered faces on [-1, 1]: y = tanh(b (eta / (1.5 pi) - 1)) / tanh(b) at eta = 3 pi j / n,
+    j = 0..n (the channel mapping of Section 4.1)."""
+    eta = 3.0 * math.pi * np.arange(n + 1) / n
+    y = np.tanh(b * (eta / (1.5 * math.pi) - 1.0)) / math.tanh(b)
+    y[0], y[-1] = -1.0, 1.0
+    return y
+
+
+def _channel_tanh(grid, seed):
+    """The channel of Section 4.1 on its own mesh: [0, 2 pi] x [-1, 1] x [0, pi], 128^3 cells uniform in
+    (xi, eta, zeta), tanh clustering towards the walls with b = 2; Poiseuille start with 5 % noise."""
+    nx, ny, nz = grid or (128, 128, 128)
+    seed = 5 if seed is None else seed
+    rng = np.random.default_rng(seed)
+    lx, ly, lz = 2 * math.pi, 2.0, math.pi
+    yf = tanh_faces(ny)
+    u_tau = 1.0 / 15.6
+    nu = u_tau / 180.0
+    q = np.zeros((4, nz, ny, nx))
+    q[0] = 1.0
+    ya, yb = yf[:-1], yf[1:]
+    prof = 1.5 * (1.0 - (yb ** 3 - ya ** 3) / (3.0 * (yb - ya)))  # exact cell average of 1.5 (1 - y^2)
+    q[1] = prof[None, :, None]
+    q[1:] += 0.05 * rng.uniform(-1.0, 1.0, size=(3, nz, ny, nx))
+    return CaseConfig(name="channel_tanh", nx=nx, ny=ny, nz=nz, x0=0.0, y0=-1.0, z0=0.0, lx=lx, ly=ly, lz=lz,
+                      ma=0.1, u_ref=1.0, rho_ref=1.0, mu=nu, cfl=0.5, dt_fixed=0.0,
+                      bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
+                      body_force=(u_tau * u_tau, 0.0, 0.0), steps=100, q0=q, seed=seed,
+                      faces=(None, yf, None))
 
 
 def _uniform_stream(nx, ny, nz, u=1.0):
