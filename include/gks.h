@@ -66,7 +66,8 @@ typedef struct gks_config {
     double ma, u_ref;            /* lambda = ma^2 / (2 u_ref^2) (Section 2); sound speed sqrt(1/(2 lambda)) */
     double rho_ref;              /* reference density; fields store rho - rho_ref */
     double mu;                   /* dynamic viscosity; collision time tau = mu / p (Section 2) */
-    double cfl;                  /* > 0: dt = cfl min(dx,dy,dz) / (|U|_max + C) each step (Section 2) */
+    double cfl;                  /* > 0: dt = cfl h_min / (|U|_max + C) each step (Section 2), h_min the
+                                    smallest cell width */
     double dt_fixed;             /* used when cfl <= 0 (the constant dt of Section 4.3) */
     int32_t bc[6];               /* GKS_BC_* for x-, x+, y-, y+, z-, z+; periodic must be paired */
     double u_in[3];              /* inflow velocity for GKS_BC_INFLOW sides */
@@ -78,6 +79,16 @@ typedef struct gks_config {
     int32_t order;               /* 5 (or 0): the high-order GKS (fifth-order WENO-JS to 2x2 Gauss points,
                                     Section 2); 2: the second-order GKS of the comparison in Section 4.3.3
                                     (van Leer-limited linear face states, one flux point per face) */
+    const double* faces[3];      /* NULL: uniform axis. Else HOST array of the n+1 increasing cell-face
+                                    coordinates of a stretched axis (the channel of Section 4.1 is computed
+                                    on a tanh-clustered mesh given by a coordinate transformation), with
+                                    faces[0] = x0 and faces[n] = x0 + lx (relative 1e-12). Reconstruction
+                                    runs in index space; derivatives take the local spacings (normal: the
+                                    distance of the adjacent cell centres, the adjacent width at a boundary
+                                    face; tangential: the line's cell width); the face flux is the mean of
+                                    its Gauss-point fluxes times the face area; the CFL step takes the
+                                    smallest width. Read during gks_init only. A periodic axis must be
+                                    uniform; rotors, immersed bodies and the adjoint need a uniform mesh. */
 } gks_config;
 
 typedef struct gks_field {

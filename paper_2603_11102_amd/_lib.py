@@ -34,6 +34,7 @@ class gks_config(C.Structure):
         ("weno_eps", C.c_double),
         ("ibm_iters", C.c_int32), ("max_act", C.c_int32), ("max_ibm", C.c_int64),
         ("order", C.c_int32),
+        ("faces", C.POINTER(C.c_double) * 3),
     ]
 
 

@@ -60,6 +60,12 @@ struct gks_ctx {
     double* diag_partials;
     int diag_nblk;
     double* umax_part;  // per-workgroup maxima of |U|^2 for the CFL time step
+    // per-axis inverse spacings in the stage precision (face spacings [n + 1], widths [n]) and FP64
+    // relative widths; stretched: some axis has its own faces
+    void* ihf[3];
+    void* ihc[3];
+    double* wrel[3];
+    int stretched;
     double lam, c, hmin, eps;
     int chunk[3];
     int flags;
@@ -118,6 +124,9 @@ size_t elem_size(const gks_config* c) { return c->precision == GKS_FP32 ? 4 : 8;
 // workspace layout; base == nullptr only measures
 struct Layout {
     DevState* st;
+    void* ihf[3];
+    void* ihc[3];
+    double* wrel[3];
     void* r0;
     void* r1;
     void* rx0;
@@ -174,6 +183,12 @@ bool layout(const gks_config* c, char* base, Layout* L) {
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     Carver cv{base, 0};
     L->st = cv.ptr<DevState>(sizeof(DevState));
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+        L->ihf[a] = cv.ptr<void>((n[a] + 1) * es);
+        L->ihc[a] = cv.ptr<void>(n[a] * es);
+        L->wrel[a] = cv.ptr<double>(sizeof(double) * n[a]);
+    }
     L->r0 = cv.ptr<void>(4 * N * es);
     L->r1 = cv.ptr<void>(4 * N * es);
     const size_t NB = (size_t)c->nx * ((c->ny + 15) / 16) * 16 * c->nz;
@@ -211,7 +226,61 @@ std::string validate(const gks_config* c) {
     if (c->max_ibm < 0 || c->max_ibm > (1LL << 24)) return "max_ibm must be in [0, 2^24]";
     if (c->max_ibm > 0 && c->ibm_iters < 1) return "ibm_iters must be >= 1";
     if (c->order != 0 && c->order != 2 && c->order != 5) return "order must be 5 (or 0) or 2";
+    const int n[3] = {c->nx, c->ny, c->nz};
+    const double org[3] = {c->x0, c->y0, c->z0}, len[3] = {c->lx, c->ly, c->lz};
+    for (int a = 0; a < 3; ++a) {
+        const double* f = c->faces[a];
+        if (!f) continue;
+        if (c->bc[2 * a] == GKS_BC_PERIODIC) return "a periodic axis must be uniform (faces NULL)";
+        for (int i = 0; i < n[a]; ++i)
+            if (!(std::isfinite(f[i]) && std::isfinite(f[i + 1]) && f[i + 1] > f[i]))
+                return "faces must be finite and increasing";
+        if (!(std::fabs(f[0] - org[a]) <= 1e-12 * len[a] && std::fabs(f[n[a]] - org[a] - len[a]) <= 1e-12 * len[a]))
+            return "faces must run from the origin to origin + length of their axis";
+    }
     return "";
+}
+
+// Inverse spacings of axis a (face spacings [n + 1], widths [n]) and relative widths, from the faces
+// of a stretched axis or the uniform size h.
+void axis_metrics(const gks_config* c, int a, double h, std::vector<double>* ihf, std::vector<double>* ihc,
+                  std::vector<double>* wrel) {
+    const int n = a == 0 ? c->nx : (a == 1 ? c->ny : c->nz);
+    ihf->assign(n + 1, 1.0 / h);
+    ihc->assign(n, 1.0 / h);
+    wrel->assign(n, 1.0);
+    const double* f = c->faces[a];
+    if (!f) return;
+    for (int i = 0; i < n; ++i) {
+        const double w = f[i + 1] - f[i];
+        (*ihc)[i] = 1.0 / w;
+        (*wrel)[i] = w / h;
+    }
+    for (int i = 1; i < n; ++i) (*ihf)[i] = 1.0 / (0.5 * ((f[i] - f[i - 1]) + (f[i + 1] - f[i])));
+    (*ihf)[0] = (*ihc)[0];
+    (*ihf)[n] = (*ihc)[n - 1];
+}
+
+// Copy the per-axis metrics into the workspace; synchronises (the host copies live until then).
+template <typename real>
+hipError_t upload_metrics(gks_ctx* c, const gks_config* cfg) {
+    std::vector<real> hf[3], hw[3];
+    std::vector<double> hr[3];
+    for (int a = 0; a < 3; ++a) {
+        std::vector<double> f, w;
+        axis_metrics(cfg, a, c->g.h[a], &f, &w, &hr[a]);
+        hf[a].assign(f.begin(), f.end());
+        hw[a].assign(w.begin(), w.end());
+        hipError_t e = hipMemcpyAsync(c->ihf[a], hf[a].data(), hf[a].size() * sizeof(real), hipMemcpyHostToDevice,
+                                      c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ihc[a], hw[a].data(), hw[a].size() * sizeof(real), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->wrel[a], hr[a].data(), hr[a].size() * sizeof(double), hipMemcpyHostToDevice,
+                               c->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(c->stream);
 }
 
 template <typename real>
@@ -286,6 +355,10 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.inv_hn = real(1.0 / c->g.h[ax[0]]);
     a.inv_h1 = real(1.0 / c->g.h[ax[1]]);
     a.inv_h2 = real(1.0 / c->g.h[ax[2]]);
+    a.ihf = static_cast<const real*>(c->ihf[ax[0]]);
+    a.ihc = static_cast<const real*>(c->ihc[ax[0]]);
+    a.ih1 = static_cast<const real*>(c->ihc[ax[1]]);
+    a.ih2 = static_cast<const real*>(c->ihc[ax[2]]);
     a.eps = real(c->eps);
     a.fc.lam = real(c->lam);
     a.fc.sl = real(std::sqrt(c->lam));
@@ -558,6 +631,19 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     c->lam = cfg->ma * cfg->ma / (2.0 * cfg->u_ref * cfg->u_ref);
     c->c = std::sqrt(1.0 / (2.0 * c->lam));
     c->hmin = std::min(c->g.h[0], std::min(c->g.h[1], c->g.h[2]));
+    c->stretched = 0;
+    for (int a = 0; a < 3; ++a) {
+        c->ihf[a] = L.ihf[a];
+        c->ihc[a] = L.ihc[a];
+        c->wrel[a] = L.wrel[a];
+        c->g.wrel[a] = nullptr;
+        if (cfg->faces[a]) {
+            c->stretched = 1;
+            c->g.wrel[a] = L.wrel[a];
+            for (int i = 0; i < n[a]; ++i) c->hmin = std::min(c->hmin, cfg->faces[a][i + 1] - cfg->faces[a][i]);
+        }
+        c->cfg.faces[a] = nullptr;  // the caller's arrays are read here only
+    }
     c->eps = c->cfg.weno_eps;
     c->diag_nblk = diag_blocks(c->g);
     c->flags = cfg->ma > 0.3 ? GKS_WARN_MACH : 0;
@@ -569,7 +655,8 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles, slots)
                                                  : face_chunk<double>(n[ax[0]], tiles, slots);
     }
-    hipError_t e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
+    hipError_t e = cfg->precision == GKS_FP32 ? upload_metrics<float>(c, cfg) : upload_metrics<double>(c, cfg);
+    if (e == hipSuccess) e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
     if (e == hipSuccess) e = clear_low_parts(c);
     if (e != hipSuccess) {
         g_init_error = std::string("clearing the device state: ") + hipGetErrorString(e);
@@ -589,6 +676,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
 int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!r) return fail(c, GKS_E_INVALID_ARG, "rotor is null");
+    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "the actuator line model needs a uniform mesh");
     const int n = r->n_blades * r->n_per_blade;
     if (r->n_blades < 1 || r->n_per_blade < 1) return fail(c, GKS_E_INVALID_ARG, "n_blades and n_per_blade must be >= 1");
     if (n > c->cfg.max_act) return fail(c, GKS_E_INVALID_ARG, "more actuator points than config.max_act");
@@ -682,6 +770,7 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
 int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* dS, const double* vel) {
     if (!c) return GKS_E_INVALID_ARG;
     if (n <= 0 || !xyz || !dS) return fail(c, GKS_E_INVALID_ARG, "need n > 0 points with xyz and dS");
+    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "immersed bodies need a uniform mesh");
     if (n > c->cfg.max_ibm) return fail(c, GKS_E_INVALID_ARG, "more Lagrangian points than config.max_ibm");
     // host-side binning (index work only): every (cell, point) pair of the 4x4x4 supports, sorted by
     // cell and then point, gives the cell list and a CSR of contributing points per cell
@@ -893,6 +982,7 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
     if (!c) return GKS_E_INVALID_ARG;
     if (!w || !grad_s || !adj_ws) return fail(c, GKS_E_INVALID_ARG, "null argument");
     if (c->cfg.precision != GKS_FP64) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs an FP64 context");
+    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a uniform mesh");
     if (c->cfg.order == 2) return fail(c, GKS_E_UNSUPPORTED, "the adjoint covers the high-order scheme only");
     if (c->cfg.cfl > 0) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a fixed dt (cfl <= 0)");
     if (!c->has_rotor) return fail(c, GKS_E_STATE, "the adjoint needs a rotor (gks_set_actuators)");

@@ -358,10 +358,13 @@ __global__ void __launch_bounds__(256) diag_kernel(Field4<real> f, GridDesc g, d
         const int k = (int)(r / g.n[1]);
         const long long p = g.pad0 + i * g.st[0] + j * g.st[1] + (long long)k * g.st[2];
         double q[4];
+        // stretched axes: each cell weighs its volume over the mean cell volume (exactly 1 when uniform)
+        const double wgt = (g.wrel[0] ? g.wrel[0][i] : 1.0) * (g.wrel[1] ? g.wrel[1][j] : 1.0) *
+                           (g.wrel[2] ? g.wrel[2][k] : 1.0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             q[v] = (double)f.v[v][p];
-            s[v] += q[v];
+            s[v] += q[v] * wgt;
             if (!isfinite(q[v])) bad = 1;
         }
         const double rho = rho_ref + q[0];

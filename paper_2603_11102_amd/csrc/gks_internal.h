@@ -40,6 +40,12 @@ struct FaceArgs {
     long long ist_n, ist_t1, ist_t2;  // interior strides
     long long pad0;                   // padded offset of interior cell (0,0,0)
     real inv_hn, inv_h1, inv_h2;
+    // inverse spacings (device): normal face spacings [n_n + 1], normal widths [n_n], t1 widths [n_t1],
+    // t2 widths [n_t2]; on a uniform axis every entry is 1/h
+    const real* ihf;
+    const real* ihc;
+    const real* ih1;
+    const real* ih2;
     real eps;
     FluxConst<real> fc;
     real g_global[3];                 // constant body force (x, y, z) for the stage-2 epilogue
@@ -77,8 +83,9 @@ struct GridDesc {
     long long st[3];          // padded strides x, y, z
     long long pad0;           // padded offset of interior cell (0,0,0)
     long long n_padded;       // elements per padded field
-    double h[3];
+    double h[3];              // mean cell size lx/nx, ... (the cell size of a uniform axis)
     double x0[3];
+    const double* wrel[3];    // device, n[a]: cell width / h[a] of a stretched axis, null when uniform
 };
 
 template <typename real>

@@ -190,7 +190,14 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     }
 
     const bool hi = m != 0;
+    // tangential inverse widths, loaded once (a vector load inside the march would make the wait for
+    // it also wait for the column prefetch): t2 of this thread's face line; t1 of its t1-phase items,
+    // whose t1 position is tid % TILE1 for every item (NT1 and FACE_THREADS are multiples of TILE1)
+    static_assert(NT1 % TILE1 == 0 && FACE_THREADS % TILE1 == 0, "t1 position of the t1-phase items");
+    const real ih2 = a.ih2[min(k0 + fk, a.n_t2 - 1)];
+    const real ih1 = a.ih1[min(j0 + tid % TILE1, a.n_t1 - 1)];
     for (int f = f0; f <= f1; ++f) {
+        const real ihf_f = a.ihf[f];  // inverse spacing at face f (normal derivative)
         // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
         real2 e_r0 = {0, 0}, e_r1 = {0, 0}, e_x0 = {0, 0}, e_x1 = {0, 0}, e_lo = {0, 0};
         real e_q[2] = {0, 0};
@@ -235,7 +242,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
                 weno_faces<real>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left);
                 const real qL = carry[v];
                 const real D = (ring[v][0] - real(15) * ring[v][1] + real(15) * ring[v][2] - ring[v][3]) *
-                               (real(1.0 / 12.0) * a.inv_hn);
+                               (real(1.0 / 12.0) * ihf_f);
                 s_nrm[v][0][c2][c1] = qL;
                 s_nrm[v][1][c2][c1] = left;
                 s_nrm[v][2][c2][c1] = D;
@@ -264,8 +271,8 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             s_t1[v][2][tk][tj][0] = vm;
             s_t1[v][2][tk][tj][1] = vp;
             quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-            s_t1[v][3][tk][tj][0] = vm * a.inv_h1;
-            s_t1[v][3][tk][tj][1] = vp * a.inv_h1;
+            s_t1[v][3][tk][tj][0] = vm * ih1;
+            s_t1[v][3][tk][tj][1] = vp * ih1;
             quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
             s_t1[v][4][tk][tj][0] = vm;
             s_t1[v][4][tk][tj][1] = vp;
@@ -294,8 +301,8 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             gp[v][0][3] = vm;
             gp[v][1][3] = vp;
             quartic_gauss_deriv<real>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
-            gp[v][0][4] = vm * a.inv_h2;
-            gp[v][1][4] = vp * a.inv_h2;
+            gp[v][0][4] = vm * ih2;
+            gp[v][1][4] = vp * ih2;
         }
 
         // ---- flux at this thread's two Gauss points, quadrature weight 1/4 each
@@ -330,11 +337,12 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             // between compile-time indices: indexing the argument or register arrays with the
             // lane-dependent index would fetch pointers from memory and move the arrays to scratch.
             real2 d1, d0;
-            d1.x = -(pick(hi, fa1[LOC[2]], fa1[LOC[0]]) - pick(hi, fprev1[LOC[2]], fprev1[LOC[0]])) * a.inv_hn;
-            d1.y = -(pick(hi, fa1[LOC[3]], fa1[LOC[1]]) - pick(hi, fprev1[LOC[3]], fprev1[LOC[1]])) * a.inv_hn;
+            const real ihc = a.ihc[cell];
+            d1.x = -(pick(hi, fa1[LOC[2]], fa1[LOC[0]]) - pick(hi, fprev1[LOC[2]], fprev1[LOC[0]])) * ihc;
+            d1.y = -(pick(hi, fa1[LOC[3]], fa1[LOC[1]]) - pick(hi, fprev1[LOC[3]], fprev1[LOC[1]])) * ihc;
             if (NEED_F0) {
-                d0.x = -(pick(hi, fa0[LOC[2]], fa0[LOC[0]]) - pick(hi, fprev0[LOC[2]], fprev0[LOC[0]])) * a.inv_hn;
-                d0.y = -(pick(hi, fa0[LOC[3]], fa0[LOC[1]]) - pick(hi, fprev0[LOC[3]], fprev0[LOC[1]])) * a.inv_hn;
+                d0.x = -(pick(hi, fa0[LOC[2]], fa0[LOC[0]]) - pick(hi, fprev0[LOC[2]], fprev0[LOC[0]])) * ihc;
+                d0.y = -(pick(hi, fa0[LOC[3]], fa0[LOC[1]]) - pick(hi, fprev0[LOC[3]], fprev0[LOC[1]])) * ihc;
             } else {
                 d0.x = d0.y = real(0);
             }

@@ -167,8 +167,11 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     }
     const real dt = real(*a.dt_ptr);
     real fprev0[4] = {0, 0, 0, 0}, fprev1[4] = {0, 0, 0, 0};
+    // tangential inverse widths of this thread's face line
+    const real ih1 = a.ih1[min(j0 + fj, a.n_t1 - 1)], ih2 = a.ih2[min(k0 + fk, a.n_t2 - 1)];
 
     for (int f = f0; f <= f1; ++f) {
+        const real ihf_f = a.ihf[f];  // inverse spacing at face f (normal derivative)
         // ---- column phase: window cells f-2 .. f+1 (prefetch f+2)
         if (col) {
 #pragma unroll
@@ -188,7 +191,7 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
                 const real qm2 = ring[v][0], qm1 = ring[v][1], q0 = ring[v][2], qp1 = ring[v][3];
                 s_face[v][0][c2][c1] = qm1 + real(0.5) * van_leer(qm1 - qm2, q0 - qm1);
                 s_face[v][1][c2][c1] = q0 - real(0.5) * van_leer(q0 - qm1, qp1 - q0);
-                s_face[v][2][c2][c1] = (q0 - qm1) * a.inv_hn;
+                s_face[v][2][c2][c1] = (q0 - qm1) * ihf_f;
                 s_face[v][3][c2][c1] = real(0.5) * (qm1 + q0);
             }
         }
@@ -203,8 +206,8 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
                 qL[v] = s_face[v][0][ck][cj];
                 qR[v] = s_face[v][1][ck][cj];
                 g[0][v] = s_face[v][2][ck][cj];
-                g[1][v] = (s_face[v][3][ck][cj + 1] - s_face[v][3][ck][cj - 1]) * (real(0.5) * a.inv_h1);
-                g[2][v] = (s_face[v][3][ck + 1][cj] - s_face[v][3][ck - 1][cj]) * (real(0.5) * a.inv_h2);
+                g[1][v] = (s_face[v][3][ck][cj + 1] - s_face[v][3][ck][cj - 1]) * (real(0.5) * ih1);
+                g[2][v] = (s_face[v][3][ck + 1][cj] - s_face[v][3][ck - 1][cj]) * (real(0.5) * ih2);
             }
             gp_flux<real, NEED_F0, SHIFT>(qL, qR, g, a.fc, real(1), fa0, fa1, cm);
         }
@@ -218,8 +221,8 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             real d1[4], d0[4];  // global variable order
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                d1[g] = -(fa1[LOC[g]] - fprev1[LOC[g]]) * a.inv_hn;
-                d0[g] = NEED_F0 ? -(fa0[LOC[g]] - fprev0[LOC[g]]) * a.inv_hn : real(0);
+                d1[g] = -(fa1[LOC[g]] - fprev1[LOC[g]]) * a.ihc[cell];
+                d0[g] = NEED_F0 ? -(fa0[LOC[g]] - fprev0[LOC[g]]) * a.ihc[cell] : real(0);
             }
             if constexpr (MODE == 3) {
                 const long long xidx = rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb);

@@ -60,6 +60,11 @@ class GksSolver:
         c.order = int(getattr(cfg, "order", 5))
         c.max_act = max_act
         c.max_ibm = max_ibm
+        faces = getattr(cfg, "faces", None) or (None, None, None)
+        self._faces = [None if f is None else np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in faces]
+        for a in range(3):
+            if self._faces[a] is not None:
+                c.faces[a] = self._faces[a].ctypes.data_as(C.POINTER(C.c_double))
         self.c_cfg = c
         shape = (4, cfg.nz + 2 * NG, cfg.ny + 2 * NG, cfg.nx + 2 * NG)
         self.q = torch.zeros(shape, dtype=self.dtype, device=self.device)

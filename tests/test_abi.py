@@ -134,3 +134,23 @@ def test_ibm_workspace_holds_the_rebinning_pairs():
     a = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=1000)))
     b = lib.gks_workspace_bytes(C.byref(_cfg(max_ibm=0)))
     assert a - b >= 1000 * 64 * 4 * 4
+
+
+def test_stretched_faces_validated():
+    import numpy as np
+    lib = L.load()
+    ok = np.tanh(2.0 * (np.arange(17) / 8.0 - 1.0)) / np.tanh(2.0) * 0.5 + 0.5  # 17 faces on [0, 1]
+    ok[0], ok[-1] = 0.0, 1.0
+    P = C.POINTER(C.c_double)
+    c = _cfg(bc=(C.c_int32 * 6)(0, 0, 1, 1, 0, 0))
+    c.faces[1] = ok.ctypes.data_as(P)
+    assert lib.gks_workspace_bytes(C.byref(c)) > 0
+    bad = ok[::-1].copy()                                  # decreasing
+    c.faces[1] = bad.ctypes.data_as(P)
+    assert lib.gks_workspace_bytes(C.byref(c)) == 0
+    short = ok * 0.9                                       # does not reach origin + length
+    c.faces[1] = short.ctypes.data_as(P)
+    assert lib.gks_workspace_bytes(C.byref(c)) == 0
+    p = _cfg()                                             # periodic axis with its own faces
+    p.faces[0] = ok.ctypes.data_as(P)
+    assert lib.gks_workspace_bytes(C.byref(p)) == 0
