@@ -88,7 +88,10 @@ typedef struct gks_config {
                                     face; tangential: the line's cell width); the face flux is the mean of
                                     its Gauss-point fluxes times the face area; the CFL step takes the
                                     smallest width. Read during gks_init only. A periodic axis must be
-                                    uniform; rotors, immersed bodies and the adjoint need a uniform mesh. */
+                                    uniform. A rotor (its disc and 3 eps spheres) or an immersed body must
+                                    sit in cells of one width (a uniformly refined block, as around the
+                                    paper's turbines) and then works on the uniform grid of that block;
+                                    moving bodies and the adjoint need a uniform mesh. */
 } gks_config;
 
 typedef struct gks_field {
@@ -162,7 +165,8 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
 
 /* Set (or replace) the rotor of the actuator line model (Section 3.1). Host arrays are copied; the
  * device scale array is referenced and read at every step. Every actuator point, its sampling cells
- * and its 3 eps projection sphere must lie inside the interior cells. */
+ * and its 3 eps projection sphere must lie inside the interior cells. GKS_E_UNSUPPORTED on a stretched
+ * mesh when these cells do not share one width per axis. */
 int gks_set_actuators(gks_ctx* ctx, const gks_rotor* rotor);
 
 /* Set the Lagrangian points of the immersed bodies (Section 3.2): n points at fixed positions, host
@@ -170,7 +174,8 @@ int gks_set_actuators(gks_ctx* ctx, const gks_rotor* rotor);
  * nacelle and tower). Each point's 4x4x4 discrete-delta support must lie inside the interior cells.
  * Computes on the device the interpolated volumes V-bar = sum W V_p (V_p = dx dS_p) and cell
  * velocities v-bar = sum W V_p v_p / V-bar that the forcing drives the fluid towards. Host arrays
- * are copied; GKS_E_INVALID_ARG for bad sizes, points or values. */
+ * are copied; GKS_E_INVALID_ARG for bad sizes, points or values; GKS_E_UNSUPPORTED on a stretched mesh
+ * when the cells within two cells of the body do not share one width per axis. */
 int gks_set_ibm_points(gks_ctx* ctx, int64_t n, const double* xyz, const double* dS, const double* vel);
 
 /* Move the body of the last gks_set_ibm_points rigidly (the introduction and Section 3.2 have the
@@ -182,7 +187,7 @@ int gks_set_ibm_points(gks_ctx* ctx, int64_t n, const double* xyz, const double*
  * the forcing; nothing is synchronised and nothing allocated. The motion lasts until the next
  * gks_set_ibm_points. If a point's 4x4x4 support leaves the interior cells the forcing stops for that
  * and every later step and gks_forces returns GKS_E_BODY_LEFT. Returns GKS_E_STATE without points,
- * GKS_E_INVALID_ARG for a null or non-finite motion. */
+ * GKS_E_INVALID_ARG for a null or non-finite motion, GKS_E_UNSUPPORTED on a stretched mesh. */
 int gks_set_ibm_motion(gks_ctx* ctx, const gks_motion* motion);
 
 /* Enqueue nsteps S2O4 steps (Section 2) with the body-force update of Section 3.3 on the stream and

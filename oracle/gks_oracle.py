@@ -71,8 +71,9 @@ R17 Stretched meshes (the channel of Section 4.1 is computed on a tanh-clustered
     width at the two boundary faces), a tangential derivative along a cell line by that line's width
     w_j; the face flux is the mean of its 2x2 Gauss-point fluxes times the face area, so the cell
     update divides the flux difference by the normal width w_i; the CFL step takes the smallest
-    width. A uniform axis gives exactly the uniform scheme. Periodic axes and bodies need uniform
-    axes.
+    width. A uniform axis gives exactly the uniform scheme. Periodic axes must be uniform. A rotor or
+    an immersed body needs one cell width on the cells around it (the paper keeps its turbines in a
+    uniformly refined block) and works on the uniform grid of that block.
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
     momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
     U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).
@@ -94,7 +95,7 @@ __all__ = [
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
     "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics", "van_leer", "muscl_faces",
-    "rotation_matrix", "ibm_motion_state", "axis_metrics", "mesh_faces",
+    "rotation_matrix", "ibm_motion_state", "axis_metrics", "mesh_faces", "body_grid",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -290,6 +291,27 @@ def axis_metrics(cfg, a):
 def _uniform_mesh(cfg):
     faces = getattr(cfg, "faces", None)
     return faces is None or all(f is None for f in faces)
+
+
+def body_grid(cfg, lo, hi, pad):
+    """Grid that a body sees (reading R17): on a stretched axis the cells from the one holding lo[a] to
+    the one holding hi[a], widened by pad cells, must share one width w; the body then works on the
+    uniform grid of that block, origin x_{i-1/2} - i w at its first cell i, spacing w. A uniform axis
+    gives (x0, h). Returns (origins, spacings)."""
+    org, h = [cfg.x0, cfg.y0, cfg.z0], [cfg.dx, cfg.dy, cfg.dz]
+    faces = getattr(cfg, "faces", None)
+    for a in range(3):
+        if faces is None or faces[a] is None:
+            continue
+        f = mesh_faces(cfg, a)
+        n = f.size - 1
+        i0 = max(0, int(np.searchsorted(f, lo[a], side="right")) - 1 - pad)
+        i1 = min(n - 1, int(np.searchsorted(f, hi[a], side="right")) - 1 + pad)
+        w = np.diff(f)[i0:i1 + 1]
+        if np.abs(w - w[0]).max() > 1e-12 * w[0]:
+            raise ValueError("a body on a stretched mesh needs one cell width around it (reading R17)")
+        org[a], h[a] = float(f[i0] - i0 * w[0]), float(w[0])
+    return tuple(org), tuple(h)
 
 
 def cfl_dt(Q, cfg):
@@ -607,11 +629,10 @@ def rotor_points(rotor, t):
     return X.reshape(-1, 3), et.reshape(-1, 3)
 
 
-def _trilinear(Q, cfg, X):
+def _trilinear(Q, cfg, X, grid=None):
     """Velocity U = (rho U)/rho at points X by trilinear interpolation of cell-centre values."""
     out = []
-    org = (cfg.x0, cfg.y0, cfg.z0)
-    h = (cfg.dx, cfg.dy, cfg.dz)
+    org, h = grid if grid is not None else ((cfg.x0, cfg.y0, cfg.z0), (cfg.dx, cfg.dy, cfg.dz))
     for p in range(X.shape[0]):
         f = [(X[p, a] - org[a]) / h[a] - 0.5 for a in range(3)]
         i0 = [int(math.floor(v)) for v in f]
@@ -643,8 +664,10 @@ def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     """Sample, blade-element forces, Gaussian projection truncated at 3 eps, momentum update
     (Section 3.1, Eqs. (axial-tangential), (Gaussian); Section 3.3; reading R9).
     Returns (Q_new, outputs)."""
-    if not _uniform_mesh(cfg):
-        raise ValueError("the actuator line model needs a uniform mesh (reading R17)")
+    rmax = float(np.max(rotor.r))
+    ext = 3.0 * rotor.eps
+    grid = body_grid(cfg, (rotor.hub[0] - ext, rotor.hub[1] - rmax - ext, rotor.hub[2] - rmax - ext),
+                     (rotor.hub[0] + ext, rotor.hub[1] + rmax + ext, rotor.hub[2] + rmax + ext), 1)
     X, et = rotor_points(rotor, t)
     n = X.shape[0]
     if scales is None:
@@ -654,7 +677,7 @@ def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     chord = torch.tensor(np.tile(rotor.chord, rotor.n_blades), dtype=F64)
     twist = torch.tensor(np.tile(rotor.twist, rotor.n_blades), dtype=F64)
     width = torch.tensor(np.tile(rotor.width, rotor.n_blades), dtype=F64)
-    U = _trilinear(Q, cfg, X)
+    U = _trilinear(Q, cfg, X, grid)
     ett = torch.tensor(et, dtype=F64)
     ux = U[:, 0]
     ut = (U * ett).sum(1)
@@ -689,8 +712,7 @@ def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     # Gaussian projection of minus the blade force, truncated at r = 3 eps, point values at cell centres
     eps = rotor.eps
     norm = 1.0 / (eps ** 3 * math.pi ** 1.5)
-    org = (cfg.x0, cfg.y0, cfg.z0)
-    h = (cfg.dx, cfg.dy, cfg.dz)
+    org, h = grid
     nn = (cfg.nx, cfg.ny, cfg.nz)
     force = torch.zeros((3,) + tuple(Q.shape[1:]), dtype=F64)
     for p in range(n):
@@ -741,24 +763,23 @@ class IbmCache:
     """Static data of Lagrangian points at fixed positions: per point the 4x4x4 support cells and
     weights and its prescribed velocity, per cell the interpolated volume V-bar and velocity v-bar."""
 
-    def __init__(self, cells, weights, vbar_index, vbar, vel, vbar_vel):
+    def __init__(self, cells, weights, vbar_index, vbar, vel, vbar_vel, vol):
         self.cells = cells        # [n, 64, 3] integer (i, j, k)
         self.weights = weights    # [n, 64]
         self.vbar_index = vbar_index  # [m, 3] cells with V-bar > 0
         self.vbar = vbar          # [m]
         self.vel = vel            # [n, 3] point velocities v_p (zeros when stationary)
         self.vbar_vel = vbar_vel  # [m, 3] v-bar at those cells
+        self.vol = vol            # cell volume around the body
 
 
 def ibm_setup(cfg, ibm):
     """W_{p->ijk} = phi4((x_i-X)/dx) phi4((y_j-Y)/dy) phi4((z_k-Z)/dz); V_p = dx dS_p;
     V-bar_ijk = sum_p W V_p (Section 3.2); v-bar_ijk = sum_p W V_p v_p / V-bar_ijk (reading R14)."""
-    if not _uniform_mesh(cfg):
-        raise ValueError("immersed bodies need a uniform mesh (reading R17)")
     X = np.asarray(ibm.xyz, dtype=np.float64)
     n = X.shape[0]
-    org = np.array([cfg.x0, cfg.y0, cfg.z0])
-    h = np.array([cfg.dx, cfg.dy, cfg.dz])
+    org, h = body_grid(cfg, X.min(0), X.max(0), 2)
+    org, h = np.array(org), np.array(h)
     f = (X - org) / h - 0.5
     i0 = np.floor(f).astype(np.int64)
     offs = np.arange(-1, 3)
@@ -776,7 +797,7 @@ def ibm_setup(cfg, ibm):
     nn = np.array([cfg.nx, cfg.ny, cfg.nz])
     if (cells < 0).any() or (cells >= nn).any():
         raise ValueError("IBM support leaves the interior cells")
-    vp = cfg.dx * np.asarray(ibm.dS, dtype=np.float64)
+    vp = h[0] * np.asarray(ibm.dS, dtype=np.float64)
     flat = (cells[..., 2] * cfg.ny + cells[..., 1]) * cfg.nx + cells[..., 0]
     vb = np.zeros(cfg.nx * cfg.ny * cfg.nz)
     np.add.at(vb, flat.reshape(-1), (weights * vp[:, None]).reshape(-1))
@@ -788,7 +809,7 @@ def ibm_setup(cfg, ibm):
         mv = np.zeros(cfg.nx * cfg.ny * cfg.nz)
         np.add.at(mv, flat.reshape(-1), (weights * (vp * vel[:, d])[:, None]).reshape(-1))
         vbar_vel[:, d] = mv[nz_idx] / vb[nz_idx]
-    return IbmCache(cells, weights, vbar_index, vb[nz_idx], vel, vbar_vel)
+    return IbmCache(cells, weights, vbar_index, vb[nz_idx], vel, vbar_vel, float(h[0] * h[1] * h[2]))
 
 
 def rotation_matrix(rotvec):
@@ -823,7 +844,7 @@ def ibm_apply(Q, dt, cfg, cache, iters):
     """Direct-forcing iterations at the cells with V-bar > 0 (Eq. (ibm-1) and the velocity update of
     Section 3.2, reading R8 for the divisor): F^s = rho V-bar (v-bar - U^s)/dt, (rho U)^{s+1} =
     (rho U)^s + dt F^s / |Omega|; f_IBM = sum_s F^s (Eq. (force-ibm)). Returns (Q_new, outputs)."""
-    vol = cfg.dx * cfg.dy * cfg.dz
+    vol = cache.vol
     vi = cache.vbar_index
     i, j, k = vi[:, 0], vi[:, 1], vi[:, 2]
     rho = Q[0, k, j, i]

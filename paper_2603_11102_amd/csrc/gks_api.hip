@@ -66,6 +66,7 @@ struct gks_ctx {
     void* ihc[3];
     double* wrel[3];
     int stretched;
+    std::vector<double> faces[3];  // host copy of the faces of each stretched axis (empty when uniform)
     double lam, c, hmin, eps;
     int chunk[3];
     int flags;
@@ -259,6 +260,29 @@ void axis_metrics(const gks_config* c, int a, double h, std::vector<double>* ihf
     for (int i = 1; i < n; ++i) (*ihf)[i] = 1.0 / (0.5 * ((f[i] - f[i - 1]) + (f[i + 1] - f[i])));
     (*ihf)[0] = (*ihc)[0];
     (*ihf)[n] = (*ihc)[n - 1];
+}
+
+// Grid that a body sees: on a stretched axis the cells from the one holding lo[a] to the one holding
+// hi[a], widened by pad cells, must share one width w; the body then works on the uniform grid of that
+// block (origin x_{i-1/2} - i w at its first cell i, spacing w). Uniform axes keep the context grid.
+bool body_grid(const gks_ctx* c, const double lo[3], const double hi[3], int pad, GridDesc* out) {
+    *out = c->g;
+    for (int a = 0; a < 3; ++a) {
+        const std::vector<double>& f = c->faces[a];
+        if (f.empty()) continue;
+        const int n = (int)f.size() - 1;
+        int i0 = (int)(std::upper_bound(f.begin(), f.end(), lo[a]) - f.begin()) - 1 - pad;
+        int i1 = (int)(std::upper_bound(f.begin(), f.end(), hi[a]) - f.begin()) - 1 + pad;
+        i0 = std::max(0, i0);
+        i1 = std::min(n - 1, i1);
+        if (i1 < i0) return false;
+        const double w = f[i0 + 1] - f[i0];
+        for (int i = i0; i <= i1; ++i)
+            if (std::fabs((f[i + 1] - f[i]) - w) > 1e-12 * w) return false;
+        out->x0[a] = f[i0] - i0 * w;
+        out->h[a] = w;
+    }
+    return true;
 }
 
 // Copy the per-axis metrics into the workspace; synchronises (the host copies live until then).
@@ -640,6 +664,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         if (cfg->faces[a]) {
             c->stretched = 1;
             c->g.wrel[a] = L.wrel[a];
+            c->faces[a].assign(cfg->faces[a], cfg->faces[a] + n[a] + 1);
             for (int i = 0; i < n[a]; ++i) c->hmin = std::min(c->hmin, cfg->faces[a][i + 1] - cfg->faces[a][i]);
         }
         c->cfg.faces[a] = nullptr;  // the caller's arrays are read here only
@@ -676,7 +701,6 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
 int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!r) return fail(c, GKS_E_INVALID_ARG, "rotor is null");
-    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "the actuator line model needs a uniform mesh");
     const int n = r->n_blades * r->n_per_blade;
     if (r->n_blades < 1 || r->n_per_blade < 1) return fail(c, GKS_E_INVALID_ARG, "n_blades and n_per_blade must be >= 1");
     if (n > c->cfg.max_act) return fail(c, GKS_E_INVALID_ARG, "more actuator points than config.max_act");
@@ -698,15 +722,18 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
     const double ext = 3.0 * r->eps;
     const double lo[3] = {r->hub[0] - ext, r->hub[1] - rmax - ext, r->hub[2] - rmax - ext};
     const double hi[3] = {r->hub[0] + ext, r->hub[1] + rmax + ext, r->hub[2] + rmax + ext};
+    GridDesc gb;
+    if (!body_grid(c, lo, hi, 1, &gb))
+        return fail(c, GKS_E_UNSUPPORTED, "a rotor on a stretched mesh needs one cell width on the cells around it");
     AlmArgs& a = c->alm;
     std::memset(&a, 0, sizeof(a));
     for (int d = 0; d < 3; ++d) {
-        int i0 = (int)std::ceil((lo[d] - c->g.x0[d]) / c->g.h[d] - 0.5);
-        int i1 = (int)std::floor((hi[d] - c->g.x0[d]) / c->g.h[d] - 0.5);
+        int i0 = (int)std::ceil((lo[d] - gb.x0[d]) / gb.h[d] - 0.5);
+        int i1 = (int)std::floor((hi[d] - gb.x0[d]) / gb.h[d] - 0.5);
         // sampling cells of any point on the disc
         const double slo = (d == 0 ? r->hub[0] : r->hub[d] - rmax), shi = (d == 0 ? r->hub[0] : r->hub[d] + rmax);
-        const int s0 = (int)std::floor((slo - c->g.x0[d]) / c->g.h[d] - 0.5);
-        const int s1 = (int)std::floor((shi - c->g.x0[d]) / c->g.h[d] - 0.5) + 1;
+        const int s0 = (int)std::floor((slo - gb.x0[d]) / gb.h[d] - 0.5);
+        const int s1 = (int)std::floor((shi - gb.x0[d]) / gb.h[d] - 0.5) + 1;
         if (std::min(i0, s0) < 0 || std::max(i1, s1) >= c->g.n[d])
             return fail(c, GKS_E_INVALID_ARG, "rotor (points, sampling cells or 3 eps spheres) leaves the interior cells");
         a.box_lo[d] = i0;
@@ -755,13 +782,13 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
     a.out_phi = cv.ptr<double>(sizeof(double) * cap);
     a.out_u = cv.ptr<double>(sizeof(double) * 3 * cap);
     a.scale = r->scale;
-    a.g = c->g;
+    a.g = gb;
     a.st = c->st;
     const double* src[4] = {r->r, r->chord, r->twist, r->width};
     for (int i = 0; i < 4; ++i)
         HIPCHK(c, hipMemcpyAsync(tab[i], src[i], sizeof(double) * r->n_per_blade, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (r->eps < 2.0 * c->hmin) c->flags |= GKS_WARN_EPS_SMALL;
+    if (r->eps < 2.0 * std::min(gb.h[0], std::min(gb.h[1], gb.h[2]))) c->flags |= GKS_WARN_EPS_SMALL;
     else c->flags &= ~GKS_WARN_EPS_SMALL;
     c->has_rotor = 1;
     return GKS_OK;
@@ -770,8 +797,18 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
 int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* dS, const double* vel) {
     if (!c) return GKS_E_INVALID_ARG;
     if (n <= 0 || !xyz || !dS) return fail(c, GKS_E_INVALID_ARG, "need n > 0 points with xyz and dS");
-    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "immersed bodies need a uniform mesh");
     if (n > c->cfg.max_ibm) return fail(c, GKS_E_INVALID_ARG, "more Lagrangian points than config.max_ibm");
+    // grid around the body (stretched meshes: the uniform block that holds it)
+    double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (long long p = 0; p < n; ++p)
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(xyz[3 * p + d])) return fail(c, GKS_E_INVALID_ARG, "non-finite point coordinate");
+            blo[d] = std::min(blo[d], xyz[3 * p + d]);
+            bhi[d] = std::max(bhi[d], xyz[3 * p + d]);
+        }
+    GridDesc gb;
+    if (!body_grid(c, blo, bhi, 2, &gb))
+        return fail(c, GKS_E_UNSUPPORTED, "a body on a stretched mesh needs one cell width on the cells around it");
     // host-side binning (index work only): every (cell, point) pair of the 4x4x4 supports, sorted by
     // cell and then point, gives the cell list and a CSR of contributing points per cell
     std::vector<long long> keys;
@@ -783,7 +820,7 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
             return fail(c, GKS_E_INVALID_ARG, "non-finite point velocity");
         int i0[3];
         for (int d = 0; d < 3; ++d) {
-            const double f = (xyz[3 * p + d] - c->g.x0[d]) / c->g.h[d] - 0.5;
+            const double f = (xyz[3 * p + d] - gb.x0[d]) / gb.h[d] - 0.5;
             if (!std::isfinite(f)) return fail(c, GKS_E_INVALID_ARG, "non-finite point coordinate");
             i0[d] = (int)std::floor(f);
             if (i0[d] - 1 < 0 || i0[d] + 2 >= c->g.n[d])
@@ -856,7 +893,7 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     a.ncell = ncell;
     a.iters = c->cfg.ibm_iters;
     a.rho_ref = c->cfg.rho_ref;
-    a.g = c->g;
+    a.g = gb;
     a.st = c->st;
     HIPCHK(c, hipMemcpyAsync(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(dx0, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
@@ -876,6 +913,7 @@ int gks_set_ibm_motion(gks_ctx* c, const gks_motion* mo) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!mo) return fail(c, GKS_E_INVALID_ARG, "motion is null");
     if (!c->has_ibm) return fail(c, GKS_E_STATE, "no Lagrangian points: call gks_set_ibm_points first");
+    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "moving bodies need a uniform mesh");
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(mo->center[d]) || !std::isfinite(mo->velocity[d]) || !std::isfinite(mo->omega[d]))
             return fail(c, GKS_E_INVALID_ARG, "non-finite motion");

@@ -76,7 +76,29 @@ def test_uniform_faces_match_the_uniform_path():
     assert max(err) < 1e-13, err
 
 
-def test_bodies_and_adjoint_need_a_uniform_mesh():
+def _top_stretched_faces(n_uniform, h, n_grow, ratio):
+    w = np.concatenate([np.full(n_uniform, h), h * ratio ** np.arange(1, n_grow + 1)])
+    return np.concatenate([[0.0], np.cumsum(w)])
+
+
+def test_rotor_and_body_in_a_uniform_block_fp64_vs_oracle():
+    # the rotor box of Section 4.3 and the tower/nacelle in uniform cells, the cells above them growing
+    cfg = make_case("alm_ibm", grid=(64, 32, 32))
+    zf = _top_stretched_faces(24, cfg.dz, 8, 1.1)
+    cfg = cfg.with_(lz=float(zf[-1]), faces=(None, None, zf))
+    print_case("stretched-alm-ibm-fp64", grid=(64, 32, 32), n_ibm=cfg.ibm.n)
+    s, gouts = run_gpu(cfg, "fp64", 2)
+    o, oouts = run_oracle(cfg, 2)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    for g, b in zip(gouts, oouts):
+        for k in ("thrust", "power"):
+            assert abs(g[k] - float(b["alm"][k])) < 1e-11 * abs(float(b["alm"][k]))
+        ref_f = b["ibm"]["body_force"].numpy()
+        assert np.allclose(g["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())
+
+
+def test_bodies_need_one_width_around_them():
     from paper_2603_11102_amd import GksSolver
     from paper_2603_11102_amd._lib import GKS_E_UNSUPPORTED, GksError
     cfg = make_case("alm", grid=(32, 16, 16))

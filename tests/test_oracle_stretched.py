@@ -114,3 +114,49 @@ def test_metrics_of_a_stretched_axis():
     assert np.allclose(hf[1:-1], np.diff(c), rtol=1e-15, atol=0)
     with pytest.raises(ValueError):
         axis_metrics(cfg.with_(bc=("periodic",) * 6), 1)
+
+
+def _top_stretched_faces(n_uniform, h, n_grow, ratio):
+    """Uniform cells of size h, then n_grow cells growing by ratio (a mesh refined around the body)."""
+    w = np.concatenate([np.full(n_uniform, h), h * ratio ** np.arange(1, n_grow + 1)])
+    return np.concatenate([[0.0], np.cumsum(w)])
+
+
+def test_rotor_in_a_uniform_block_sees_the_uniform_grid():
+    from oracle import alm_apply
+    cfg = make_case("alm", grid=(48, 24, 24))
+    h = cfg.dz
+    zf = cfg.z0 + h * np.arange(25.0)
+    zf[0] = cfg.z0 - 0.3 * h  # the first cell is wider; every other cell is where it was
+    st = cfg.with_(z0=float(zf[0]), lz=float(zf[-1] - zf[0]), faces=(None, None, zf))
+    Q = torch.tensor(cfg.q0)
+    Q[1] += 0.1 * torch.rand(Q[1].shape, generator=torch.Generator().manual_seed(3), dtype=torch.float64)
+    qa, oa = alm_apply(Q, 0.05, 0.01, cfg, cfg.rotor)
+    qb, ob = alm_apply(Q, 0.05, 0.01, st, st.rotor)
+    for k in ("thrust", "power", "torque"):
+        assert abs(float(oa[k]) - float(ob[k])) < 1e-13 * abs(float(oa[k]))
+    assert float((qa - qb).abs().max()) < 1e-13 * float(qa.abs().max())
+
+
+def test_body_in_a_uniform_block_sees_the_uniform_grid():
+    from oracle import ibm_setup
+    cfg = make_case("alm_ibm", grid=(64, 32, 32))
+    zf = _top_stretched_faces(24, cfg.dz, 8, 1.1)
+    st = cfg.with_(lz=float(zf[-1]), faces=(None, None, zf))
+    a, b = ibm_setup(cfg, cfg.ibm), ibm_setup(st, st.ibm)
+    assert np.array_equal(a.vbar_index, b.vbar_index)
+    assert np.abs(a.weights - b.weights).max() < 1e-13
+    assert np.abs(a.vbar - b.vbar).max() < 1e-13 * a.vbar.max()
+    assert abs(a.vol - b.vol) < 1e-15 * a.vol
+
+
+def test_body_across_a_width_change_is_rejected():
+    from oracle import body_grid
+    cfg = make_case("alm_ibm", grid=(64, 32, 32))
+    zf = _top_stretched_faces(12, cfg.dz, 20, 1.05)  # widths change at z = 1.5, inside the rotor box
+    st = cfg.with_(lz=float(zf[-1]), faces=(None, None, zf))
+    with pytest.raises(ValueError):
+        body_grid(st, (1.0, 1.0, 0.7), (1.2, 3.0, 1.7), 1)
+    # and a box below the change is accepted with the block's grid
+    org, h = body_grid(st, (1.0, 1.0, 0.3), (1.2, 3.0, 1.0), 1)
+    assert h[2] == cfg.dz and abs(org[2]) < 1e-15
