@@ -379,6 +379,7 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.inv_hn = real(1.0 / c->g.h[ax[0]]);
     a.inv_h1 = real(1.0 / c->g.h[ax[1]]);
     a.inv_h2 = real(1.0 / c->g.h[ax[2]]);
+    a.stretched = c->stretched;
     a.ihf = static_cast<const real*>(c->ihf[ax[0]]);
     a.ihc = static_cast<const real*>(c->ihc[ax[0]]);
     a.ih1 = static_cast<const real*>(c->ihc[ax[1]]);

@@ -40,8 +40,9 @@ struct FaceArgs {
     long long ist_n, ist_t1, ist_t2;  // interior strides
     long long pad0;                   // padded offset of interior cell (0,0,0)
     real inv_hn, inv_h1, inv_h2;
-    // inverse spacings (device): normal face spacings [n_n + 1], normal widths [n_n], t1 widths [n_t1],
-    // t2 widths [n_t2]; on a uniform axis every entry is 1/h
+    // inverse spacings (device) of a stretched mesh (stretched != 0): normal face spacings [n_n + 1],
+    // normal widths [n_n], t1 widths [n_t1], t2 widths [n_t2]; on a uniform axis every entry is 1/h
+    int stretched;
     const real* ihf;
     const real* ihc;
     const real* ih1;

@@ -73,7 +73,9 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 
 // MODE (the direction's role): 3 = x pass, writes its residual to the blocked arrays; 0 = y pass,
 // writes the main residual arrays; 4 = z pass, adds both and applies the S2O4 stage update.
-template <typename real, int STAGE, int MODE>
+// STR: the mesh is stretched and the spacings come from the per-axis arrays; otherwise the uniform
+// inverse spacings are kernel arguments (no memory access for them inside the march).
+template <typename real, int STAGE, int MODE, bool STR>
 __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
     static_assert(MODE == 0 || MODE == 3 || MODE == 4, "face pass mode");
     constexpr bool NEED_F0 = (STAGE == 1);
@@ -194,10 +196,10 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     // it also wait for the column prefetch): t2 of this thread's face line; t1 of its t1-phase items,
     // whose t1 position is tid % TILE1 for every item (NT1 and FACE_THREADS are multiples of TILE1)
     static_assert(NT1 % TILE1 == 0 && FACE_THREADS % TILE1 == 0, "t1 position of the t1-phase items");
-    const real ih2 = a.ih2[min(k0 + fk, a.n_t2 - 1)];
-    const real ih1 = a.ih1[min(j0 + tid % TILE1, a.n_t1 - 1)];
+    const real ih2 = STR ? a.ih2[min(k0 + fk, a.n_t2 - 1)] : a.inv_h2;
+    const real ih1 = STR ? a.ih1[min(j0 + tid % TILE1, a.n_t1 - 1)] : a.inv_h1;
     for (int f = f0; f <= f1; ++f) {
-        const real ihf_f = a.ihf[f];  // inverse spacing at face f (normal derivative)
+        const real ihf_f = STR ? a.ihf[f] : a.inv_hn;  // inverse spacing at face f (normal derivative)
         // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
         real2 e_r0 = {0, 0}, e_r1 = {0, 0}, e_x0 = {0, 0}, e_x1 = {0, 0}, e_lo = {0, 0};
         real e_q[2] = {0, 0};
@@ -337,7 +339,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
             // between compile-time indices: indexing the argument or register arrays with the
             // lane-dependent index would fetch pointers from memory and move the arrays to scratch.
             real2 d1, d0;
-            const real ihc = a.ihc[cell];
+            const real ihc = STR ? a.ihc[cell] : a.inv_hn;
             d1.x = -(pick(hi, fa1[LOC[2]], fa1[LOC[0]]) - pick(hi, fprev1[LOC[2]], fprev1[LOC[0]])) * ihc;
             d1.y = -(pick(hi, fa1[LOC[3]], fa1[LOC[1]]) - pick(hi, fprev1[LOC[3]], fprev1[LOC[1]])) * ihc;
             if (NEED_F0) {
@@ -431,7 +433,7 @@ int face_slots() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1, 4>, FACE_THREADS, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1, 4, false>, FACE_THREADS, 0) != hipSuccess)
         return 0;
     return cus * per_cu;
 }
@@ -462,7 +464,11 @@ hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
     const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(FACE_THREADS);
-#define GKS_FACE_LAUNCH(ST, MD) hipLaunchKernelGGL((face_kernel<real, ST, MD>), grid, block, 0, s, a)
+#define GKS_FACE_LAUNCH(ST, MD)                                                                     \
+    do {                                                                                            \
+        if (a.stretched) hipLaunchKernelGGL((face_kernel<real, ST, MD, true>), grid, block, 0, s, a);  \
+        else hipLaunchKernelGGL((face_kernel<real, ST, MD, false>), grid, block, 0, s, a);             \
+    } while (0)
     if (stage == 1) {
         if (a.mode == 0) GKS_FACE_LAUNCH(1, 0);
         else if (a.mode == 3) GKS_FACE_LAUNCH(1, 3);

@@ -78,7 +78,7 @@ __device__ __forceinline__ void two_sum2(float a, float b, float& s, float& e) {
 
 }  // namespace
 
-template <typename real, int STAGE, int MODE>
+template <typename real, int STAGE, int MODE, bool STR>
 __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real> a) {
     static_assert(MODE == 0 || MODE == 3 || MODE == 4, "face pass mode");
     constexpr bool NEED_F0 = (STAGE == 1);
@@ -168,10 +168,11 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     const real dt = real(*a.dt_ptr);
     real fprev0[4] = {0, 0, 0, 0}, fprev1[4] = {0, 0, 0, 0};
     // tangential inverse widths of this thread's face line
-    const real ih1 = a.ih1[min(j0 + fj, a.n_t1 - 1)], ih2 = a.ih2[min(k0 + fk, a.n_t2 - 1)];
+    const real ih1 = STR ? a.ih1[min(j0 + fj, a.n_t1 - 1)] : a.inv_h1;
+    const real ih2 = STR ? a.ih2[min(k0 + fk, a.n_t2 - 1)] : a.inv_h2;
 
     for (int f = f0; f <= f1; ++f) {
-        const real ihf_f = a.ihf[f];  // inverse spacing at face f (normal derivative)
+        const real ihf_f = STR ? a.ihf[f] : a.inv_hn;  // inverse spacing at face f (normal derivative)
         // ---- column phase: window cells f-2 .. f+1 (prefetch f+2)
         if (col) {
 #pragma unroll
@@ -221,8 +222,9 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             real d1[4], d0[4];  // global variable order
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                d1[g] = -(fa1[LOC[g]] - fprev1[LOC[g]]) * a.ihc[cell];
-                d0[g] = NEED_F0 ? -(fa0[LOC[g]] - fprev0[LOC[g]]) * a.ihc[cell] : real(0);
+                const real ihc = STR ? a.ihc[cell] : a.inv_hn;
+                d1[g] = -(fa1[LOC[g]] - fprev1[LOC[g]]) * ihc;
+                d0[g] = NEED_F0 ? -(fa0[LOC[g]] - fprev0[LOC[g]]) * ihc : real(0);
             }
             if constexpr (MODE == 3) {
                 const long long xidx = rx_block_index(cell, j0 + fj, k0 + fk, a.rx_nx, a.rx_nyb);
@@ -294,7 +296,7 @@ int face2_slots() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face2_kernel<real, 1, 4>, T2O_THREADS, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face2_kernel<real, 1, 4, false>, T2O_THREADS, 0) !=
         hipSuccess)
         return 0;
     return cus * per_cu;
@@ -306,7 +308,11 @@ hipError_t launch_face2(const FaceArgs<real>& a, int stage, hipStream_t s) {
     const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(T2O_THREADS);
-#define GKS_FACE2_LAUNCH(ST, MD) hipLaunchKernelGGL((face2_kernel<real, ST, MD>), grid, block, 0, s, a)
+#define GKS_FACE2_LAUNCH(ST, MD)                                                                     \
+    do {                                                                                             \
+        if (a.stretched) hipLaunchKernelGGL((face2_kernel<real, ST, MD, true>), grid, block, 0, s, a);  \
+        else hipLaunchKernelGGL((face2_kernel<real, ST, MD, false>), grid, block, 0, s, a);             \
+    } while (0)
     if (stage == 1) {
         if (a.mode == 0) GKS_FACE2_LAUNCH(1, 0);
         else if (a.mode == 3) GKS_FACE2_LAUNCH(1, 3);
