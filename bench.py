@@ -211,7 +211,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the x-slab multi-GPU "
-              "decomposition is a design note, not part of this build)", file=sys.stderr)
+              "decomposition is a design note only, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     from synth import make_case

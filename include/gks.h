@@ -41,7 +41,7 @@ extern "C" {
 #define GKS_E_HIP 3           /* a HIP runtime call failed */
 #define GKS_E_NONFINITE 4     /* a non-finite value was found in the field (reported by gks_forces) */
 #define GKS_E_UNSTABLE 5      /* |U|_max reached the sound speed (reported by gks_forces) */
-#define GKS_E_UNSUPPORTED 6   /* valid request this build does not implement */
+#define GKS_E_UNSUPPORTED 6   /* valid request the library does not implement */
 #define GKS_E_BODY_LEFT 7     /* a moving body's point support left the interior (reported by gks_forces) */
 
 /* boundary kinds, per side, order x-, x+, y-, y+, z-, z+ */
