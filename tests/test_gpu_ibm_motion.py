@@ -121,3 +121,29 @@ def test_body_leaving_the_interior_is_reported_and_stops_the_forcing():
     s.set_ibm(IbmSpec(xyz=xyz, dS=dS))
     s.step(1)
     assert s.forces()["status"] == 0
+
+
+def test_moving_body_step_in_a_hip_graph_replays_like_eager_steps():
+    # the per-step placement and rebinning are kernels only (no memset, no host work), so a captured
+    # step replays exactly like eager steps; each replay is checked, with eager work in between
+    from paper_2603_11102_amd import GksSolver
+    cfg = _yawing_body()
+    print_case("ibm-motion-graph", grid=GRID, n_ibm=cfg.ibm.n)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = GksSolver(cfg, precision="fp32")
+        b = GksSolver(cfg, precision="fp32")
+    a.step(1)
+    b.step(1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        a.step(1)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        b.step(1)
+        torch.cuda.synchronize()
+        assert torch.equal(a.interior(), b.interior())
+        fa, fb = a.forces(), b.forces()
+        assert fa["t"] == fb["t"] and fa["ibm_force"] == fb["ibm_force"]
