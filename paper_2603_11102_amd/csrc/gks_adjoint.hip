@@ -240,41 +240,67 @@ __global__ void __launch_bounds__(256) adj_gp_kernel(const AdjFaceArgs a) {
 // ------------------------------------------------------------------------------------------------
 // pass B: transpose of the t2 sweep -> adjoints of the t1 line values (q^L_m, q^R_m, D_m, Ct1_m, C_m)
 // ------------------------------------------------------------------------------------------------
+constexpr int T2_STRIP = 4;  // consecutive t2 outputs per thread in pass B
+
 __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
-    // one thread per (t1 line position, variable, Gauss line m, t2 position incl. halo, face);
-    // the t1 position is the fastest index so that a wave reads contiguous runs of every plane
-    const long long total = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 8 * a.n_t1;
+    // one thread per (t1 line position, variable, Gauss line m, strip of T2_STRIP consecutive t2
+    // positions incl. halo, face); the t1 position is the fastest index so that a wave reads
+    // contiguous runs of every plane. Each face value loaded serves every output of the strip whose
+    // 5-point stencil holds it; every output sums its faces in ascending t2 order, Gauss point n inner.
+    const int nstrip = (a.n_t2 + 4 + T2_STRIP - 1) / T2_STRIP;
+    const long long total = (long long)(a.n_n + 1) * nstrip * 8 * a.n_t1;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int j = (int)(t % a.n_t1);
     long long r_ = t / a.n_t1;
     const int vm = (int)(r_ % 8);  // v * 2 + m
     r_ /= 8;
-    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
-    const int f = (int)(r_ / (a.n_t2 + 4));
-    double bar[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = max(0, kx - 2); k <= min(a.n_t2 - 1, kx + 2); ++k) {
-        const int r = kx - k + 2;
+    const int kx0 = (int)(r_ % nstrip) * T2_STRIP - 2;
+    const int f = (int)(r_ / nstrip);
+    double bar[T2_STRIP][5];
+#pragma unroll
+    for (int o = 0; o < T2_STRIP; ++o)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bar[o][q] = 0.0;
+#pragma unroll
+    for (int dk = 0; dk < T2_STRIP + 4; ++dk) {  // faces k = kx0 - 2 .. kx0 + T2_STRIP + 1
+        const int k = kx0 - 2 + dk;
+        if (k < 0 || k >= a.n_t2) continue;
         const long long fi = face_ix(a, f, j, k);
+#pragma unroll
         for (int n = 0; n < 2; ++n) {
             const int side = n == 0 ? 2 : 3;
             const int s = n == 0 ? -1 : 1;
-            const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h2;
             const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
-            double wL[3], wR[3];
+            double wL[3], wR[3], gv[5];
+#pragma unroll
             for (int kk = 0; kk < 3; ++kk) {
                 wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * 3 + kk) * a.nface + fi];
                 wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * 3 + kk) * a.nface + fi];
             }
-            bar[0] += weno_eff(side, wL, r) * a.gpbar[gbase];
-            bar[1] += weno_eff(side, wR, r) * a.gpbar[gbase + a.nface];
-            bar[2] += cv * a.gpbar[gbase + 2 * a.nface];
-            bar[3] += cv * a.gpbar[gbase + 3 * a.nface];
-            bar[4] += cd * a.gpbar[gbase + 4 * a.nface];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) gv[q] = a.gpbar[gbase + q * a.nface];
+#pragma unroll
+            for (int o = 0; o < T2_STRIP; ++o) {
+                const int r = o - dk + 4;  // stencil slot of face k for output kx0 + o (compile time)
+                if (r < 0 || r > 4) continue;
+                const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h2;
+                bar[o][0] += weno_eff(side, wL, r) * gv[0];
+                bar[o][1] += weno_eff(side, wR, r) * gv[1];
+                bar[o][2] += cv * gv[2];
+                bar[o][3] += cv * gv[3];
+                bar[o][4] += cd * gv[4];
+            }
         }
     }
-    const long long p = t1_ix(a, f, j, kx);
-    for (int q = 0; q < 5; ++q) a.t1bar[(long long)(vm * 5 + q) * a.nt1pos + p] = bar[q];
+#pragma unroll
+    for (int o = 0; o < T2_STRIP; ++o) {
+        const int kx = kx0 + o;
+        if (kx > a.n_t2 + 1) break;
+        const long long p = t1_ix(a, f, j, kx);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a.t1bar[(long long)(vm * 5 + q) * a.nt1pos + p] = bar[o][q];
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -373,7 +399,7 @@ hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) 
         hipLaunchKernelGGL((adj_face_kernel<2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
         hipLaunchKernelGGL((adj_gp_kernel<2>), dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, s, a);
     }
-    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4) * 8;
+    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * ((a.n_t2 + 4 + T2_STRIP - 1) / T2_STRIP) * 8;
     hipLaunchKernelGGL(adj_t2_kernel, dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
     const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4) * 4;
     hipLaunchKernelGGL(adj_t1_kernel, dim3((unsigned)((nC + 255) / 256)), dim3(256), 0, s, a);
