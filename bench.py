@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--ibm-yaw", type=float, default=0.0, metavar="OMEGA",
                     help="turn the immersed tower and nacelle about the tower axis at OMEGA rad per unit time "
                          "(their supports are then rebuilt on the device every step)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio of the rotor-gradient window in the default line")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the adjoint against its checkpointed forward window and print that line")
     args = ap.parse_args()
@@ -296,6 +298,12 @@ def main():
         result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
         result["fp32_vs_fp64_rel_l2"] = {"after_steps": done, "per_variable": rl2}
         print(f"[bench] fp64: {ms64 / args.steps:.3f} ms/step; fp32 vs fp64 rel L2 {rl2}", flush=True)
+    if not args.no_adjoint and args.case == "channel" and args.order == 5 and args.precision == "fp32":
+        # the third part of the metric: adjoint/forward time of the 128^3 rotor-gradient window (FP64)
+        r = adjoint_ratio()
+        result["adjoint_forward_ratio"] = {"value": r["value"], "forward_s": r["forward_s"],
+                                           "adjoint_s": r["adjoint_s"], "workload": r["config"]["workload"]}
+        print(f"[bench] adjoint/forward: {r['value']:.3f}", flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample ...", flush=True)
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_planes)
