@@ -147,3 +147,19 @@ def test_moving_body_step_in_a_hip_graph_replays_like_eager_steps():
         assert torch.equal(a.interior(), b.interior())
         fa, fb = a.forces(), b.forces()
         assert fa["t"] == fb["t"] and fa["ibm_force"] == fb["ibm_force"]
+
+
+@pytest.mark.parametrize("order,rotor", [(2, False), (5, True)])
+def test_moving_body_with_the_second_order_scheme_or_a_rotor_fp64_vs_oracle(order, rotor):
+    base = make_case("alm_ibm", grid=GRID)
+    cfg = _yawing_body().with_(order=order, rotor=base.rotor if rotor else None)
+    print_case(f"ibm-motion-order{order}-rotor{int(rotor)}", grid=GRID, n_ibm=cfg.ibm.n)
+    s, gouts = run_gpu(cfg, "fp64", 3)
+    o, oouts = run_oracle(cfg, 3)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    for g, b in zip(gouts, oouts):
+        ref_f = b["ibm"]["body_force"].numpy()
+        assert np.allclose(g["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())
+        if rotor:
+            assert abs(g["power"] - float(b["alm"]["power"])) < 1e-11 * abs(float(b["alm"]["power"]))
