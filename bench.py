@@ -298,6 +298,10 @@ def main():
         result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
         result["fp32_vs_fp64_rel_l2"] = {"after_steps": done, "per_variable": rl2}
         print(f"[bench] fp64: {ms64 / args.steps:.3f} ms/step; fp32 vs fp64 rel L2 {rl2}", flush=True)
+    if not args.graph:
+        # run-to-run spread: the same K steps timed four more times (informational; `value` is the first
+        # timing; these run after the FP32-vs-FP64 comparison, which they do not touch)
+        result["repeat_ms_per_step"] = [_time_steps(s, args.steps) / args.steps for _ in range(4)]
     if not args.no_adjoint and args.case == "channel" and args.order == 5 and args.precision == "fp32":
         # the third part of the metric: adjoint/forward time of the 128^3 rotor-gradient window (FP64)
         r = adjoint_ratio()
