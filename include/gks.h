@@ -90,8 +90,9 @@ typedef struct gks_config {
                                     smallest width. Read during gks_init only. A periodic axis must be
                                     uniform. A rotor (its disc and 3 eps spheres) or an immersed body must
                                     sit in cells of one width (a uniformly refined block, as around the
-                                    paper's turbines) and then works on the uniform grid of that block;
-                                    moving bodies and the adjoint need a uniform mesh. */
+                                    paper's turbines) and then works on the uniform grid of that block
+                                    (a moving body on the widest run of cells of that width); the
+                                    adjoint needs a uniform mesh. */
 } gks_config;
 
 typedef struct gks_field {
@@ -185,9 +186,10 @@ int gks_set_ibm_points(gks_ctx* ctx, int64_t n, const double* xyz, const double*
  * velocity (t^{n+1} - t0), gives it the velocity v_p = velocity + omega x (X_p - c) (replacing the
  * velocities of gks_set_ibm_points) and rebuilds the supports, V-bar and v-bar on the device before
  * the forcing; nothing is synchronised and nothing allocated. The motion lasts until the next
- * gks_set_ibm_points. If a point's 4x4x4 support leaves the interior cells the forcing stops for that
- * and every later step and gks_forces returns GKS_E_BODY_LEFT. Returns GKS_E_STATE without points,
- * GKS_E_INVALID_ARG for a null or non-finite motion, GKS_E_UNSUPPORTED on a stretched mesh. */
+ * gks_set_ibm_points. If a point's 4x4x4 support leaves the interior cells (on a stretched mesh: the
+ * run of cells of the body's width around its initial position) the forcing stops for that and every
+ * later step and gks_forces returns GKS_E_BODY_LEFT. Returns GKS_E_STATE without points,
+ * GKS_E_INVALID_ARG for a null or non-finite motion. */
 int gks_set_ibm_motion(gks_ctx* ctx, const gks_motion* motion);
 
 /* Enqueue nsteps S2O4 steps (Section 2) with the body-force update of Section 3.3 on the stream and

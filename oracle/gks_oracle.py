@@ -73,7 +73,8 @@ R17 Stretched meshes (the channel of Section 4.1 is computed on a tanh-clustered
     update divides the flux difference by the normal width w_i; the CFL step takes the smallest
     width. A uniform axis gives exactly the uniform scheme. Periodic axes must be uniform. A rotor or
     an immersed body needs one cell width on the cells around it (the paper keeps its turbines in a
-    uniformly refined block) and works on the uniform grid of that block.
+    uniformly refined block) and works on the uniform grid of that block; a moving body is checked
+    again at every step.
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
     momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
     U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).

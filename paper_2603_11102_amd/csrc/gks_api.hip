@@ -265,10 +265,17 @@ void axis_metrics(const gks_config* c, int a, double h, std::vector<double>* ihf
 // Grid that a body sees: on a stretched axis the cells from the one holding lo[a] to the one holding
 // hi[a], widened by pad cells, must share one width w; the body then works on the uniform grid of that
 // block (origin x_{i-1/2} - i w at its first cell i, spacing w). Uniform axes keep the context grid.
-bool body_grid(const gks_ctx* c, const double lo[3], const double hi[3], int pad, GridDesc* out) {
+// run[a] (optional) receives the widest run of cells of that width around the block, [first, last]
+// (all cells of a uniform axis): the cells a moving body may reach without leaving that grid.
+bool body_grid(const gks_ctx* c, const double lo[3], const double hi[3], int pad, GridDesc* out,
+               int run_lo[3] = nullptr, int run_hi[3] = nullptr) {
     *out = c->g;
     for (int a = 0; a < 3; ++a) {
         const std::vector<double>& f = c->faces[a];
+        if (run_lo) {
+            run_lo[a] = 0;
+            run_hi[a] = c->g.n[a] - 1;
+        }
         if (f.empty()) continue;
         const int n = (int)f.size() - 1;
         int i0 = (int)(std::upper_bound(f.begin(), f.end(), lo[a]) - f.begin()) - 1 - pad;
@@ -277,10 +284,18 @@ bool body_grid(const gks_ctx* c, const double lo[3], const double hi[3], int pad
         i1 = std::min(n - 1, i1);
         if (i1 < i0) return false;
         const double w = f[i0 + 1] - f[i0];
+        auto same = [&](int i) { return std::fabs((f[i + 1] - f[i]) - w) <= 1e-12 * w; };
         for (int i = i0; i <= i1; ++i)
-            if (std::fabs((f[i + 1] - f[i]) - w) > 1e-12 * w) return false;
+            if (!same(i)) return false;
         out->x0[a] = f[i0] - i0 * w;
         out->h[a] = w;
+        if (run_lo) {
+            int r0 = i0, r1 = i1;
+            while (r0 > 0 && same(r0 - 1)) --r0;
+            while (r1 < n - 1 && same(r1 + 1)) ++r1;
+            run_lo[a] = r0;
+            run_hi[a] = r1;
+        }
     }
     return true;
 }
@@ -808,7 +823,8 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
             bhi[d] = std::max(bhi[d], xyz[3 * p + d]);
         }
     GridDesc gb;
-    if (!body_grid(c, blo, bhi, 2, &gb))
+    int run_lo[3], run_hi[3];
+    if (!body_grid(c, blo, bhi, 2, &gb, run_lo, run_hi))
         return fail(c, GKS_E_UNSUPPORTED, "a body on a stretched mesh needs one cell width on the cells around it");
     // host-side binning (index work only): every (cell, point) pair of the 4x4x4 supports, sorted by
     // cell and then point, gives the cell list and a CSR of contributing points per cell
@@ -881,6 +897,10 @@ int gks_set_ibm_points(gks_ctx* c, int64_t n, const double* xyz, const double* d
     m.counts = cv.ptr<int>(sizeof(int) * 2);
     m.xyz0 = dx0;
     m.xyz = dx;
+    for (int d = 0; d < 3; ++d) {
+        m.run_lo[d] = run_lo[d];
+        m.run_hi[d] = run_hi[d];
+    }
     m.pvel = dvel;
     m.cell = dcell;
     m.csr = dcsr;
@@ -914,7 +934,6 @@ int gks_set_ibm_motion(gks_ctx* c, const gks_motion* mo) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!mo) return fail(c, GKS_E_INVALID_ARG, "motion is null");
     if (!c->has_ibm) return fail(c, GKS_E_STATE, "no Lagrangian points: call gks_set_ibm_points first");
-    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "moving bodies need a uniform mesh");
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(mo->center[d]) || !std::isfinite(mo->velocity[d]) || !std::isfinite(mo->omega[d]))
             return fail(c, GKS_E_INVALID_ARG, "non-finite motion");

@@ -54,7 +54,9 @@ struct IbmMoveArgs {
     const double* xyz0;  // device, 3 npts: positions at t0
     double* xyz;         // device, 3 npts: positions of the step (IbmArgs::xyz)
     double* pvel;        // device, 3 npts: velocities of the step (IbmArgs::vel)
-    int* base;           // device, 3 npts: lowest support cell per axis (clamped into the interior)
+    int* base;           // device, 3 npts: lowest support cell per axis (clamped into the run)
+    int run_lo[3], run_hi[3];  // cells of the body's grid per axis (a stretched mesh: the run of cells
+                               // of the body's width; otherwise all cells); supports must stay inside
     unsigned* key[2];    // device, 64 npts each: cell index of the (cell, point) pairs, ping-pong
     int* val[2];         // device, 64 npts each: point index of the pairs
     int* hist;           // device, 256 * tiles: digit counts per tile, digit-major

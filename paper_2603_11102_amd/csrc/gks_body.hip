@@ -325,9 +325,9 @@ __device__ __forceinline__ long long flat_cell(const GridDesc& g, int i, int j, 
 
 // Rigid motion to t^{n+1}: X_p = X_p(t0) + V tau + (R - I) r with r = X_p(t0) - c0 and
 // (R - I) r = sin(theta) k x r + (1 - cos theta) k x (k x r) (Rodrigues), v_p = V + omega x R r.
-// Lowest support cell per axis, clamped into the interior when the support leaves it (then the
-// flag stops the forcing; the clamp keeps every later index valid: points were accepted by
-// gks_set_ibm_points, so every axis has at least 4 cells).
+// Lowest support cell per axis, clamped into the body's run of cells when the support leaves it
+// (then the flag stops the forcing; the clamp keeps every later index valid: the points were accepted
+// by gks_set_ibm_points, so every run holds at least 4 cells).
 __global__ void __launch_bounds__(256) ibm_move_kernel(IbmArgs a, IbmMoveArgs m) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.npts) return;
@@ -357,13 +357,15 @@ __global__ void __launch_bounds__(256) ibm_move_kernel(IbmArgs a, IbmMoveArgs m)
     bool out = false;
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
+        // support cells b - 1 .. b + 2 inside the run [run_lo, run_hi] (within the interior)
         const double f = (X[x] - a.g.x0[x]) / a.g.h[x] - 0.5;
+        const int lo = m.run_lo[x] + 1, hi = m.run_hi[x] - 2;
         int b;
-        if (f >= 1.0 && f < (double)(a.g.n[x] - 2)) {
+        if (f >= (double)lo && f < (double)(hi + 1)) {
             b = (int)floor(f);
         } else {  // also NaN
             out = true;
-            b = f >= 1.0 ? a.g.n[x] - 3 : 1;
+            b = f >= (double)lo ? hi : lo;
         }
         m.xyz[3 * p + x] = X[x];
         m.pvel[3 * p + x] = v[x];

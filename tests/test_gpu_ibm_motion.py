@@ -163,3 +163,48 @@ def test_moving_body_with_the_second_order_scheme_or_a_rotor_fp64_vs_oracle(orde
         assert np.allclose(g["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())
         if rotor:
             assert abs(g["power"] - float(b["alm"]["power"])) < 1e-11 * abs(float(b["alm"]["power"]))
+
+
+def _top_stretched(cfg, n_uniform, n_grow, ratio):
+    """The same box with the cells above the first n_uniform growing by ratio (z axis)."""
+    w = np.concatenate([np.full(n_uniform, cfg.dz), cfg.dz * ratio ** np.arange(1, n_grow + 1)])
+    zf = np.concatenate([[0.0], np.cumsum(w)])
+    return cfg.with_(lz=float(zf[-1]), faces=(None, None, zf))
+
+
+def test_moving_body_on_a_stretched_mesh_fp64_vs_oracle():
+    # the yawing tower and nacelle stay in the uniform cells under the growing ones
+    cfg = _top_stretched(_yawing_body(), 24, 8, 1.1)
+    print_case("ibm-motion-stretched-fp64", grid=GRID, n_ibm=cfg.ibm.n)
+    s, gouts = run_gpu(cfg, "fp64", 4)
+    o, oouts = run_oracle(cfg, 4)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    for g, b in zip(gouts, oouts):
+        assert g["status"] == 0
+        ref_f = b["ibm"]["body_force"].numpy()
+        assert np.allclose(g["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())
+
+
+def test_moving_body_leaving_its_uniform_cells_is_reported():
+    from paper_2603_11102_amd import GksSolver
+    from paper_2603_11102_amd._lib import GKS_E_BODY_LEFT
+    base = make_case("alm_ibm", grid=GRID).with_(rotor=None)
+    # a small sphere below the growing cells, driven upwards into them
+    h = base.dz
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=(40, 3))
+    d *= 1.5 * h / np.linalg.norm(d, axis=1, keepdims=True)
+    c0 = np.array([3.0, 2.0, 24 * h - 6.0 * h])
+    ib = IbmSpec(xyz=c0 + d, dS=np.full(40, 0.005 * h * h), motion=IbmMotion(center=c0, velocity=(0.0, 0.0, 60.0)))
+    cfg = _top_stretched(base.with_(ibm=ib), 24, 8, 1.1)
+    print_case("ibm-motion-stretched-leaves", grid=GRID)
+    s = GksSolver(cfg, precision="fp64")
+    outs = []
+    for _ in range(4):
+        s.step(1)
+        outs.append(s.forces(check=False))
+    assert outs[0]["status"] == 0
+    assert outs[-1]["status"] == GKS_E_BODY_LEFT
+    assert outs[-1]["ibm_force"] == [0.0, 0.0, 0.0]
+    assert bool(torch.isfinite(s.interior()).all())
