@@ -171,7 +171,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--case", default="channel")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
@@ -288,12 +288,15 @@ def main():
                               "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_launch}
     if args.precision == "fp32" and not args.no_fp64:
         s64, ms64, _, _, _ = run_gpu(cfg, "fp64", args.steps, args.warmup)
-        done = args.warmup + 2 * args.steps
-        if done < args.accuracy_steps:  # compare FP32 with FP64 after the same number of steps
-            s.step(args.accuracy_steps - done)
-            s64.step(args.accuracy_steps - done)
-            done = args.accuracy_steps
-        q32, q64 = s.interior(), s64.interior()
+        # accuracy: fresh FP32 and FP64 runs of exactly accuracy_steps steps from the same start
+        from paper_2603_11102_amd import GksSolver
+        a32, a64 = GksSolver(cfg, precision="fp32"), GksSolver(cfg, precision="fp64")
+        a32.step(args.accuracy_steps)
+        a64.step(args.accuracy_steps)
+        done = args.accuracy_steps
+        q32, q64 = a32.interior(), a64.interior()
+        a32.close()
+        a64.close()
         rl2 = [float(torch.linalg.vector_norm(q32[v] - q64[v]) / torch.linalg.vector_norm(q64[v])) for v in range(4)]
         result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
         result["fp32_vs_fp64_rel_l2"] = {"after_steps": done, "per_variable": rl2}
