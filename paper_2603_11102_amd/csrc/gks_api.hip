@@ -68,7 +68,8 @@ struct gks_ctx {
     int stretched;
     std::vector<double> faces[3];  // host copy of the faces of each stretched axis (empty when uniform)
     double lam, c, hmin, eps;
-    int chunk[3];
+    int chunk[3];      // faces per workgroup of the face kernels, per direction
+    int chunk_adj[3];  // the same for the adjoint's 16 x 16 tiles
     int flags;
     // actuator line model
     int has_rotor;
@@ -121,6 +122,12 @@ int fail(gks_ctx* c, int code, const std::string& msg) {
     } while (0)
 
 size_t elem_size(const gks_config* c) { return c->precision == GKS_FP32 ? 4 : 8; }
+
+// t2 extent of the face tile: the high-order kernel's per-precision tile, 16 for the second-order one
+template <typename real>
+int face_tile_t2(int order) {
+    return order == 2 ? TILE2 : FaceTile<real>::T2;
+}
 
 // workspace layout; base == nullptr only measures
 struct Layout {
@@ -372,8 +379,9 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.n_n = c->g.n[ax[0]];
     a.n_t1 = c->g.n[ax[1]];
     a.n_t2 = c->g.n[ax[2]];
+    const int t2 = face_tile_t2<real>(c->cfg.order);
     a.tiles_t1 = (a.n_t1 + TILE1 - 1) / TILE1;
-    a.tiles_t2 = (a.n_t2 + TILE2 - 1) / TILE2;
+    a.tiles_t2 = (a.n_t2 + t2 - 1) / t2;
     a.chunk = c->chunk[d];
     a.st_n = c->g.st[ax[0]];
     a.st_t1 = c->g.st[ax[1]];
@@ -447,7 +455,7 @@ AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4])
     a.n_t2 = c->g.n[ax[2]];
     a.tiles_t1 = (a.n_t1 + TILE1 - 1) / TILE1;
     a.tiles_t2 = (a.n_t2 + TILE2 - 1) / TILE2;
-    a.chunk = c->chunk[d];
+    a.chunk = c->chunk_adj[d];
     a.st_n = c->g.st[ax[0]];
     a.st_t1 = c->g.st[ax[1]];
     a.st_t2 = c->g.st[ax[2]];
@@ -690,11 +698,18 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
     c->flags = cfg->ma > 0.3 ? GKS_WARN_MACH : 0;
     const int slots = cfg->order == 2 ? (cfg->precision == GKS_FP32 ? face2_slots<float>() : face2_slots<double>())
                                       : (cfg->precision == GKS_FP32 ? face_slots<float>() : face_slots<double>());
+    const int t2 = cfg->precision == GKS_FP32 ? face_tile_t2<float>(cfg->order) : face_tile_t2<double>(cfg->order);
     for (int d = 0; d < 3; ++d) {
         const int* ax = kAxes[d];
-        const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + TILE2 - 1) / TILE2);
+        const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + t2 - 1) / t2);
         c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles, slots)
                                                  : face_chunk<double>(n[ax[0]], tiles, slots);
+        // the adjoint's kernels (16 x 16 tiles, one 512-thread workgroup per CU)
+        const int tiles16 = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + TILE2 - 1) / TILE2);
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        c->chunk_adj[d] = face_chunk<double>(n[ax[0]], tiles16, cus);
     }
     hipError_t e = cfg->precision == GKS_FP32 ? upload_metrics<float>(c, cfg) : upload_metrics<double>(c, cfg);
     if (e == hipSuccess) e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);

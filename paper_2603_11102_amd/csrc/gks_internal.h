@@ -13,6 +13,20 @@ constexpr int TILE1 = 16, TILE2 = 16;    // tangential faces per workgroup (t1 x
 constexpr int EXT1 = TILE1 + 4, EXT2 = TILE2 + 4;
 constexpr int FACE_THREADS = 512;        // 8 wave64 per workgroup
 
+// Tile of the high-order face kernel per precision. FP32: 16 x 16 faces, 512 threads (two waves per
+// SIMD, up to 256 registers each). FP64: 16 x 8 faces, 256 threads: one workgroup per CU (its LDS), one
+// wave per SIMD, so that a wave can use the 512 registers of the unified VGPR/AGPR file its doubled live
+// state needs instead of spilling to scratch. Both map one thread per tile column (20 x 20 and 20 x 12)
+// and one thread per face and Gauss line.
+template <typename real>
+struct FaceTile {
+    static constexpr int T2 = 16, THREADS = 512;
+};
+template <>
+struct FaceTile<double> {
+    static constexpr int T2 = 8, THREADS = 256;
+};
+
 // Arguments of the per-direction face kernel. Arrays are in the face's LOCAL variable order
 // (rho', m_normal, m_t1, m_t2); the caller permutes the global pointers.
 template <typename real>

@@ -2,21 +2,21 @@
 // stage combination, one launch per face direction (Section 2, Eqs. (semi), (finite), (x_example),
 // (flux); the two-stage fourth-order combinations).
 //
-// One workgroup (512 threads = 8 wave64) owns a 16 x 16 tile of faces in the tangential plane and
-// marches along the face normal through a chunk of faces:
-//   * column phase: each of the 20 x 20 tangential columns (tile + 2-cell halo per side) keeps a
+// One workgroup owns a tile of faces in the tangential plane (FP32: 16 x 16 faces, 512 threads = 8 wave64;
+// FP64: 16 x 8 faces, 256 threads) and marches along the face normal through a chunk of faces:
+//   * column phase: each of the 20 x 20 (FP64 20 x 12) tangential columns (tile + 2-cell halo per side) keeps a
 //     5-cell window of the field in registers; per cell it evaluates the WENO-JS values at both of its
 //     faces with one set of smoothness indicators, the normal derivative D (cubic through four cells)
 //     and C = (q^L + q^R)/2 for all four variables -> LDS;
 //   * t1 phase: WENO-JS at the two Gauss points of q^L, q^R, quartic Gauss values of D and C and the
-//     quartic Gauss derivative of C along t1, the 4 x 320 (variable, position) items spread over all
-//     512 threads -> LDS;
+//     quartic Gauss derivative of C along t1, the 4 x 320 (FP64 4 x 192) (variable, position) items spread
+//     over all threads -> LDS;
 //   * t2 phase: the same along t2 for each Gauss line, giving per Gauss point q^L, q^R, dQ/dn, dQ/dt1,
 //     dQ/dt2 in registers (one thread per face and Gauss line);
 //   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
 // No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
-// variables (77 KB in FP32, 154 KB in FP64 of the 160 KB per CU).
+// variables (77 KB in FP32, 92 KB in FP64 of the 160 KB per CU).
 #include "gks_internal.h"
 
 namespace gks {
@@ -76,8 +76,11 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 // STR: the mesh is stretched and the spacings come from the per-axis arrays; otherwise the uniform
 // inverse spacings are kernel arguments (no memory access for them inside the march).
 template <typename real, int STAGE, int MODE, bool STR>
-__global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real> a) {
+__global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const FaceArgs<real> a) {
     static_assert(MODE == 0 || MODE == 3 || MODE == 4, "face pass mode");
+    // tile of this precision: TILE1 x T2 faces, EXT1 x X2 columns, NTH threads
+    constexpr int T2 = FaceTile<real>::T2, X2 = T2 + 4, NTH = FaceTile<real>::THREADS;
+    static_assert(EXT1 * X2 <= NTH && 2 * TILE1 * T2 == NTH, "one thread per column and per face line");
     constexpr bool NEED_F0 = (STAGE == 1);
     // FP32: the z pass loads its epilogue operands at the top of the step (FP64 has no registers to
     // spare) and updates the compensated state (high part in the field, low part in lo_in / lo_a / lo_b)
@@ -85,9 +88,9 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     using real2 = typename Vec2<real>::type;
     constexpr int LOC[4] = {LocalOrder<MODE>::v[0], LocalOrder<MODE>::v[1], LocalOrder<MODE>::v[2],
                             LocalOrder<MODE>::v[3]};
-    constexpr int NT1 = TILE1 * EXT2;             // t1 items per variable (320)
-    __shared__ real s_nrm[4][4][EXT2][EXT1];      // [variable][q^L, q^R, D, C]
-    __shared__ real s_t1[4][5][EXT2][TILE1][2];   // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
+    constexpr int NT1 = TILE1 * X2;               // t1 items per variable (320 FP32, 192 FP64)
+    __shared__ real s_nrm[4][4][X2][EXT1];        // [variable][q^L, q^R, D, C]
+    __shared__ real s_t1[4][5][X2][TILE1][2];     // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
 
     const int tid = threadIdx.x;
     // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
@@ -101,11 +104,11 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     b /= a.tiles_t2;
     const int f0 = b * a.chunk;
     const int f1 = min(f0 + a.chunk, a.n_n);  // residuals of cells [f0, f1); faces f0..f1
-    const int j0 = tile1 * TILE1, k0 = tile2 * TILE2;
+    const int j0 = tile1 * TILE1, k0 = tile2 * T2;
     const real eps = a.eps;
 
     // column role
-    const bool col = tid < EXT1 * EXT2;
+    const bool col = tid < EXT1 * X2;
     const int c1 = tid % EXT1, c2 = tid / EXT1;
     const int jc = j0 - 2 + c1, kc = k0 - 2 + c2;
     const bool col_ld = col && (jc < a.n_t1 + NG) && (kc < a.n_t2 + NG);
@@ -140,7 +143,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
         }
     }
     if constexpr (SHIFT) {
-        __shared__ float s_range[2][FACE_THREADS / 64];
+        __shared__ float s_range[2][NTH / 64];
         float lo = col_ld ? float(ring[1][0]) : 3.0e38f, up = col_ld ? float(ring[1][0]) : -3.0e38f;
 #pragma unroll
         for (int r = 1; r < 5; ++r) {
@@ -160,7 +163,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
         lo = s_range[0][0];
         up = s_range[1][0];
 #pragma unroll
-        for (int w = 1; w < FACE_THREADS / 64; ++w) {
+        for (int w = 1; w < NTH / 64; ++w) {
             lo = fminf(lo, s_range[0][w]);
             up = fmaxf(up, s_range[1][w]);
         }
@@ -194,8 +197,8 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
     const bool hi = m != 0;
     // tangential inverse widths, loaded once (a vector load inside the march would make the wait for
     // it also wait for the column prefetch): t2 of this thread's face line; t1 of its t1-phase items,
-    // whose t1 position is tid % TILE1 for every item (NT1 and FACE_THREADS are multiples of TILE1)
-    static_assert(NT1 % TILE1 == 0 && FACE_THREADS % TILE1 == 0, "t1 position of the t1-phase items");
+    // whose t1 position is tid % TILE1 for every item (NT1 and NTH are multiples of TILE1)
+    static_assert(NT1 % TILE1 == 0 && NTH % TILE1 == 0, "t1 position of the t1-phase items");
     const real ih2 = STR ? a.ih2[min(k0 + fk, a.n_t2 - 1)] : a.inv_h2;
     const real ih1 = STR ? a.ih1[min(j0 + tid % TILE1, a.n_t1 - 1)] : a.inv_h1;
     for (int f = f0; f <= f1; ++f) {
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(FACE_THREADS) face_kernel(const FaceArgs<real>
         }
         __syncthreads();
         // ---- t1 phase: 4 x 320 (variable, item) pairs spread over all threads
-        for (int it = tid; it < 4 * NT1; it += FACE_THREADS) {
+        for (int it = tid; it < 4 * NT1; it += NTH) {
             const int v = it / NT1, item = it - v * NT1;
             const int tj = item % TILE1, tk = item / TILE1;
             real x[4][5];
@@ -433,7 +436,8 @@ int face_slots() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1, 4, false>, FACE_THREADS, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, face_kernel<real, 1, 4, false>, FaceTile<real>::THREADS,
+                                                     0) != hipSuccess)
         return 0;
     return cus * per_cu;
 }
@@ -463,7 +467,7 @@ hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
     const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)blocks), block(FACE_THREADS);
+    const dim3 grid((unsigned)blocks), block(FaceTile<real>::THREADS);
 #define GKS_FACE_LAUNCH(ST, MD)                                                                     \
     do {                                                                                            \
         if (a.stretched) hipLaunchKernelGGL((face_kernel<real, ST, MD, true>), grid, block, 0, s, a);  \
