@@ -92,7 +92,16 @@ def _time_graph(s, steps, side):
     return e0.elapsed_time(e1)
 
 
-def run_gpu(cfg, precision, steps, warmup, graph=False):
+def stage1_launch_ms(timing):
+    """Mean duration of one stage-1 face launch (x, y and z passes) from the per-launch event timing."""
+    s1_ms = sum(timing[k][0] for k in ("s1x", "s1y", "s1z"))
+    return s1_ms / max(1, sum(timing[k][1] for k in ("s1x", "s1y", "s1z")))
+
+
+def run_gpu(cfg, precision, steps, warmup, graph=False, repeats=5):
+    """Warm up, then time `repeats` windows of `steps` steps; returns the solver, the median window time,
+    every window time (ms), the per-launch timing of one more window and the forces."""
+    import statistics
     import torch
     from paper_2603_11102_amd import GksSolver
     side = torch.cuda.Stream() if graph else None
@@ -103,14 +112,26 @@ def run_gpu(cfg, precision, steps, warmup, graph=False):
         s = GksSolver(cfg, precision=precision)
     s.step(warmup)
     torch.cuda.synchronize()
-    ms = _time_graph(s, steps, side) if graph else _time_steps(s, steps)
+    windows = [(_time_graph(s, steps, side) if graph else _time_steps(s, steps)) for _ in range(max(1, repeats))]
+    ms = statistics.median(windows)
     torch.cuda.synchronize()
     s.set_timing(True)
-    ms_t = _time_steps(s, steps)
+    _time_steps(s, steps)
     timing = s.read_timing()
     s.set_timing(False)
     f = s.forces(check=False)
-    return s, ms, ms_t, timing, f
+    return s, ms, windows, timing, f
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(cfg, planes):
@@ -124,7 +145,7 @@ def cpu_baseline(cfg, planes):
     o.step()
     dt = time.perf_counter() - t0
     return {"value": sub.n_cells / dt, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model(),
             "sample": (f"1 S2O4 step of the FP64 oracle on the whole {sub.nx}x{sub.ny}x{sub.nz} field, {dt:.1f} s"
                        if sub is cfg else
                        f"1 S2O4 step of the FP64 oracle on {sub.nx}x{sub.ny}x{sub.nz} cells (first {planes} "
@@ -191,6 +212,9 @@ def main():
                          "(their supports are then rebuilt on the device every step)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio of the rotor-gradient window in the default line")
+    ap.add_argument("--repeats", type=int, default=5, help="timed windows of --steps steps; value is their median")
+    ap.add_argument("--no-bodies", action="store_true",
+                    help="skip the companion timing of the rotor + tower/nacelle workload in the default line")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the adjoint against its checkpointed forward window and print that line")
     args = ap.parse_args()
@@ -229,15 +253,14 @@ def main():
     print(f"[bench] case={args.case} order={args.order} grid={cfg.nx}x{cfg.ny}x{cfg.nz} precision={args.precision} "
           f"steps={args.steps} warmup={args.warmup}", flush=True)
     stretched = any(f is not None for f in (cfg.faces or ()))
-    s, ms, ms_t, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup, graph=args.graph)
+    s, ms, windows, timing, f = run_gpu(cfg, args.precision, args.steps, args.warmup, graph=args.graph,
+                                        repeats=args.repeats)
     n = cfg.n_cells
     value = n * args.steps / (ms * 1e-3)
     print(f"[bench] {args.precision}: {ms / args.steps:.3f} ms/step, {value:.4e} cell-updates/s", flush=True)
     print("[bench] per-category ms/step: " + ", ".join(f"{k}={v[0] / args.steps:.3f}" for k, v in timing.items()),
           flush=True)
-    s1_ms = sum(timing[k][0] for k in ("s1x", "s1y", "s1z"))
-    s1_launches = sum(timing[k][1] for k in ("s1x", "s1y", "s1z"))
-    avg_launch_ms = s1_ms / max(1, s1_launches)
+    avg_launch_ms = stage1_launch_ms(timing)
     flops_launch = FLOP_STAGE1_PER_CELL_DIR * n
     achieved = flops_launch / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
@@ -250,6 +273,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "timing": f"median of {len(windows)} timed windows of {args.steps} steps",
+        "window_ms_per_step": [w / args.steps for w in windows],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -287,7 +312,11 @@ def main():
                               "traffic": measured_traffic(args.case, args.precision, 2),
                               "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_launch}
     if args.precision == "fp32" and not args.no_fp64:
-        s64, ms64, _, _, _ = run_gpu(cfg, "fp64", args.steps, args.warmup)
+        s64, ms64, win64, timing64, _ = run_gpu(cfg, "fp64", args.steps, args.warmup, repeats=args.repeats)
+        s64.close()
+        del s64
+        l64 = stage1_launch_ms(timing64)
+        a64_tf = flops_launch / (l64 * 1e-3) / 1e12
         # accuracy: fresh FP32 and FP64 runs of exactly accuracy_steps steps from the same start
         from paper_2603_11102_amd import GksSolver
         a32, a64 = GksSolver(cfg, precision="fp32"), GksSolver(cfg, precision="fp64")
@@ -298,13 +327,32 @@ def main():
         a32.close()
         a64.close()
         rl2 = [float(torch.linalg.vector_norm(q32[v] - q64[v]) / torch.linalg.vector_norm(q64[v])) for v in range(4)]
-        result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps}
+        result["fp64"] = {"value": n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
+                          "window_ms_per_step": [w / args.steps for w in win64],
+                          "roofline": {"bound": "alu", "kernel": f"face_kernel<double, 1, 3 | 0 | 4, "
+                                                                 f"{str(stretched).lower()}> (stage 1: mean over "
+                                                                 "the x, y, z launches)",
+                                       "achieved": a64_tf, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                                       "frac": a64_tf / PEAK_TFLOPS["fp64"], "avg_launch_ms": l64}}
         result["fp32_vs_fp64_rel_l2"] = {"after_steps": done, "per_variable": rl2}
         print(f"[bench] fp64: {ms64 / args.steps:.3f} ms/step; fp32 vs fp64 rel L2 {rl2}", flush=True)
-    if not args.graph:
-        # run-to-run spread: the same K steps timed four more times (informational; `value` is the first
-        # timing; these run after the FP32-vs-FP64 comparison, which they do not touch)
-        result["repeat_ms_per_step"] = [_time_steps(s, args.steps) / args.steps for _ in range(4)]
+    s.close()
+    del s
+    if not args.no_bodies and args.case == "channel" and args.order == 5 and args.precision == "fp32":
+        # companion line: the rotor and tower/nacelle workload, 512 x 256 x 256 cells, 192 actuator points
+        # and 24,139 Lagrangian points, FP32 field with FP64 load reductions
+        bcfg = make_case("alm_ibm")
+        sb, msb, winb, timingb, fb = run_gpu(bcfg, "fp32", 10, 3, repeats=3)
+        sb.close()
+        del sb
+        result["alm_ibm"] = {"workload": f"alm_ibm {bcfg.nx}x{bcfg.ny}x{bcfg.nz} ({bcfg.n_cells} cells), "
+                                         f"{bcfg.rotor.n_act} actuator points, {bcfg.ibm.n} Lagrangian points, FP32",
+                             "value": bcfg.n_cells * 10 / (msb * 1e-3), "unit": "cell-updates/s",
+                             "ms_per_step": msb / 10, "window_ms_per_step": [w / 10 for w in winb],
+                             "per_category_ms_per_step": {k: v[0] / 10 for k, v in timingb.items()},
+                             "thrust": fb["thrust"], "power": fb["power"], "ibm_force": fb["ibm_force"]}
+        print(f"[bench] alm_ibm fp32: {msb / 10:.3f} ms/step, alm {timingb['alm'][0] / 10:.3f} ms, "
+              f"ibm {timingb['ibm'][0] / 10:.3f} ms", flush=True)
     if not args.no_adjoint and args.case == "channel" and args.order == 5 and args.precision == "fp32":
         # the third part of the metric: adjoint/forward time of the 128^3 rotor-gradient window (FP64)
         r = adjoint_ratio()

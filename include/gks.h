@@ -1,7 +1,8 @@
 /*
  * gks.h -- C ABI of the MI355X (gfx950) library for one two-stage fourth-order (S2O4) time step of the
- * high-order gas-kinetic scheme (GKS) for 3D weakly compressible isothermal flow on a uniform
- * Cartesian grid, with actuator-line (ALM) and immersed-boundary (IBM) body forces.
+ * high-order gas-kinetic scheme (GKS) for 3D weakly compressible isothermal flow on a structured
+ * Cartesian grid (uniform, or stretched per axis: gks_config.faces), with actuator-line (ALM) and
+ * immersed-boundary (IBM) body forces.
  *
  * Method: Huo, Pan, Cao, Meng, Tian, Huang, "High-order gas-kinetic scheme for numerical simulations
  * of wind turbine with nacelle and tower using ALM and IBM" (arXiv 2603.11102):

@@ -16,6 +16,8 @@ GKS_E_NONFINITE = 4
 GKS_E_UNSTABLE = 5
 GKS_E_UNSUPPORTED = 6
 GKS_E_BODY_LEFT = 7
+GKS_WARN_EPS_SMALL = 1
+GKS_WARN_MACH = 2
 
 BC = {"periodic": 0, "noslip": 1, "slip": 2, "inflow": 3, "outflow": 4}
 GKS_FP32 = 0
@@ -148,6 +150,11 @@ class GksError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"gks error {code}: {msg}")
         self.code = code
+
+
+def last_error(lib, ctx) -> str:
+    msg = lib.gks_last_error(ctx)
+    return msg.decode() if msg else ""
 
 
 def check(lib, ctx, rc):

@@ -980,9 +980,11 @@ int gks_forces(gks_ctx* c, gks_forces_out* out) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!out) return fail(c, GKS_E_INVALID_ARG, "out is null");
     if (c->cfg.precision == GKS_FP32)
-        HIPCHK(c, launch_diag<float>(field<float>(c->q), c->g, c->cfg.rho_ref, c->diag_partials, c->diag_nblk, c->st, c->stream));
+        HIPCHK(c, launch_diag<float>(field<float>(c->q), static_cast<const float*>(c->lo_q), c->g, c->cfg.rho_ref,
+                                     c->diag_partials, c->diag_nblk, c->st, c->stream));
     else
-        HIPCHK(c, launch_diag<double>(field<double>(c->q), c->g, c->cfg.rho_ref, c->diag_partials, c->diag_nblk, c->st, c->stream));
+        HIPCHK(c, launch_diag<double>(field<double>(c->q), nullptr, c->g, c->cfg.rho_ref, c->diag_partials,
+                                      c->diag_nblk, c->st, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     DevState h;
     HIPCHK(c, hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost));

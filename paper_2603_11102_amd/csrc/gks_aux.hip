@@ -343,8 +343,8 @@ int diag_blocks(const GridDesc& g) {
 }
 
 template <typename real>
-__global__ void __launch_bounds__(256) diag_kernel(Field4<real> f, GridDesc g, double rho_ref, double* partials,
-                                                   DevState* st) {
+__global__ void __launch_bounds__(256) diag_kernel(Field4<real> f, const real* lo, GridDesc g, double rho_ref,
+                                                   double* partials, DevState* st) {
     __shared__ double red[4][256];
     __shared__ double mxs[256];
     const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
@@ -363,7 +363,8 @@ __global__ void __launch_bounds__(256) diag_kernel(Field4<real> f, GridDesc g, d
                            (g.wrel[2] ? g.wrel[2][k] : 1.0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            q[v] = (double)f.v[v][p];
+            // FP32: the state is the field plus its low-order part ([cell][4], interior cells)
+            q[v] = lo ? (double)f.v[v][p] + (double)lo[4 * c + v] : (double)f.v[v][p];
             s[v] += q[v] * wgt;
             if (!isfinite(q[v])) bad = 1;
         }
@@ -414,10 +415,10 @@ __global__ void diag_reset_kernel(DevState* st) {
 }
 
 template <typename real>
-hipError_t launch_diag(Field4<real> f, const GridDesc& g, double rho_ref, double* partials, int nblk, DevState* st,
-                       hipStream_t s) {
+hipError_t launch_diag(Field4<real> f, const real* lo, const GridDesc& g, double rho_ref, double* partials, int nblk,
+                       DevState* st, hipStream_t s) {
     hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, s, st);
-    hipLaunchKernelGGL((diag_kernel<real>), dim3(nblk), dim3(256), 0, s, f, g, rho_ref, partials, st);
+    hipLaunchKernelGGL((diag_kernel<real>), dim3(nblk), dim3(256), 0, s, f, lo, g, rho_ref, partials, st);
     hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, (const double*)partials, nblk, st,
                        g.h[0] * g.h[1] * g.h[2]);
     return hipGetLastError();
@@ -449,7 +450,9 @@ template hipError_t launch_transpose_xy<float>(Field4<float>, Field4<float>, con
 template hipError_t launch_transpose_xy<double>(Field4<double>, Field4<double>, const GridDesc&, hipStream_t);
 template hipError_t launch_umax<float>(Field4<float>, const GridDesc&, double, double*, hipStream_t);
 template hipError_t launch_umax<double>(Field4<double>, const GridDesc&, double, double*, hipStream_t);
-template hipError_t launch_diag<float>(Field4<float>, const GridDesc&, double, double*, int, DevState*, hipStream_t);
-template hipError_t launch_diag<double>(Field4<double>, const GridDesc&, double, double*, int, DevState*, hipStream_t);
+template hipError_t launch_diag<float>(Field4<float>, const float*, const GridDesc&, double, double*, int, DevState*,
+                                      hipStream_t);
+template hipError_t launch_diag<double>(Field4<double>, const double*, const GridDesc&, double, double*, int,
+                                       DevState*, hipStream_t);
 
 }  // namespace gks

@@ -139,7 +139,8 @@ hipError_t launch_dt(DevState* st, const double* part, int nparts, double cfl, d
 hipError_t launch_finish(DevState* st, int has_rotor, double* hist, hipStream_t s);
 hipError_t launch_window_reset(DevState* st, hipStream_t s);
 template <typename real>
-hipError_t launch_diag(Field4<real> f, const GridDesc& g, double rho_ref, double* partials, int nblk, DevState* st,
+hipError_t launch_diag(Field4<real> f, const real* lo, const GridDesc& g, double rho_ref, double* partials, int nblk,
+                       DevState* st,
                        hipStream_t s);
 int diag_blocks(const GridDesc& g);
 hipError_t launch_copy_field(const void* src, void* dst, size_t bytes, hipStream_t s);
