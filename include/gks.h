@@ -16,7 +16,8 @@
  *
  * Memory ownership: the CALLER owns every device buffer (fields, workspace, checkpoints, scalings)
  * and keeps it alive until gks_destroy. The library never allocates device memory; it holds a small
- * host context. All device work is enqueued on the HIP stream given to gks_init, in order.
+ * host context and one static device array per GPU (the workspace of gks_init_static, for callers
+ * that cannot allocate). All device work is enqueued on the HIP stream given to gks_init, in order.
  *
  * Fields: a gks_field is four device pointers (rho - rho_ref, rho U, rho V, rho W). Each points to
  * (nx+6)(ny+6)(nz+6) elements of the configured precision (float or double), x fastest, then y, then
@@ -278,6 +279,21 @@ int gks_set_timing(gks_ctx* ctx, int32_t enable);
 /* Synchronise the stream and return the accumulated milliseconds and launch-group counts per
  * category (arrays of n <= GKS_TIMER_COUNT entries). */
 int gks_read_timing(gks_ctx* ctx, double* ms, int64_t* count, int32_t n);
+
+/* Bytes of the library's static device scratch (one array per GPU, held until the process ends). */
+#define GKS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): gks_init with the workspace taken from the library's static device
+ * array of GKS_STATIC_SCRATCH_BYTES on the current device (which must be the stream's). Allocates no
+ * device memory; the caller still provides q, q_stage and q_acc. Returns GKS_E_INVALID_ARG when
+ * gks_workspace_bytes(cfg) exceeds GKS_STATIC_SCRATCH_BYTES (e.g. FP32 grids above about 64^3, FP64
+ * above about 48^3, or room for many Lagrangian points), and GKS_E_STATE while another context made
+ * here on the same GPU is alive: one GPU holds one such workspace, and it keeps the last context's
+ * contents (gks_init_static clears what must start at zero). Contexts made by gks_init are not affected.
+ * The context is used and destroyed like any other; gks_destroy releases the scratch. */
+int gks_init_static(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_acc, void* hip_stream,
+                    gks_ctx** out);
 
 /* Release the host context (device buffers stay the caller's). */
 void gks_destroy(gks_ctx* ctx);

@@ -22,6 +22,7 @@ GKS_WARN_MACH = 2
 BC = {"periodic": 0, "noslip": 1, "slip": 2, "inflow": 3, "outflow": 4}
 GKS_FP32 = 0
 GKS_FP64 = 1
+GKS_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class gks_config(C.Structure):
@@ -82,7 +83,7 @@ EXPORTS = (
     "gks_forces", "gks_reset_window", "gks_field_changed", "gks_checkpoint_slot_bytes", "gks_set_checkpoints",
     "gks_adjoint_workspace_bytes", "gks_adjoint", "gks_set_timing", "gks_read_timing", "gks_destroy",
     "gks_last_error", "gks_statistics_bytes", "gks_set_statistics", "gks_read_statistics", "gks_set_history",
-    "gks_history_count",
+    "gks_history_count", "gks_init_static",
 )
 TIMERS = ("ghost", "dt", "s1x", "s1y", "s1z", "s2x", "s2y", "s2z", "alm", "ibm", "other")
 
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.gks_workspace_bytes.restype = C.c_size_t
     lib.gks_init.argtypes = [C.POINTER(gks_config), gks_field, gks_field, gks_field, P, C.c_size_t, P, C.POINTER(P)]
     lib.gks_init.restype = C.c_int
+    lib.gks_init_static.argtypes = [C.POINTER(gks_config), gks_field, gks_field, gks_field, P, C.POINTER(P)]
+    lib.gks_init_static.restype = C.c_int
     lib.gks_set_actuators.argtypes = [P, C.POINTER(gks_rotor)]
     lib.gks_set_actuators.restype = C.c_int
     lib.gks_set_ibm_points.argtypes = [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), P]

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -101,7 +102,25 @@ struct gks_ctx {
     double t_ms[GKS_TIMER_COUNT];
     long long t_cnt[GKS_TIMER_COUNT];
     std::string err;
+    int static_dev;  // device whose static scratch holds the workspace (gks_init_static), else -1
 };
+
+// Workspace for callers that cannot allocate device memory (gks_init_static): one array per GPU, held
+// until the process ends. Host code never names it in a kernel argument or a copy: it uses the device
+// address hipGetSymbolAddress returns, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[GKS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kStaticDevices = 64;
+struct StaticSlot {
+    void* ptr;             // device address of this GPU's scratch (null until first use)
+    const gks_ctx* owner;  // the context whose workspace it is, or null
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kStaticDevices];
+
+}  // namespace
 
 namespace {
 
@@ -638,6 +657,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
                     "workspace too small: need " + std::to_string(L.total) + " bytes (gks_workspace_bytes)");
     gks_ctx* c = new (std::nothrow) gks_ctx();
     if (!c) return fail(nullptr, GKS_E_INVALID_ARG, "out of host memory");
+    c->static_dev = -1;
     c->cfg = *cfg;
     if (!(c->cfg.weno_eps > 0)) c->cfg.weno_eps = 1e-6;
     c->es = elem_size(cfg);
@@ -1224,9 +1244,49 @@ int gks_read_timing(gks_ctx* c, double* ms, int64_t* count, int32_t n) {
     return GKS_OK;
 }
 
+int gks_init_static(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_acc, void* hip_stream,
+                    gks_ctx** out) {
+    if (!out) return fail(nullptr, GKS_E_INVALID_ARG, "out is null");
+    *out = nullptr;
+    std::string why = validate(cfg);
+    if (!why.empty()) return fail(nullptr, GKS_E_INVALID_ARG, why);
+    Layout L;
+    layout(cfg, nullptr, &L);
+    if (L.total > GKS_STATIC_SCRATCH_BYTES)
+        return fail(nullptr, GKS_E_INVALID_ARG,
+                    "the configuration needs " + std::to_string(L.total) + " bytes of workspace; the static scratch holds " +
+                        std::to_string((size_t)GKS_STATIC_SCRATCH_BYTES) + " (use gks_init with a caller workspace)");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, GKS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kStaticDevices) return fail(nullptr, GKS_E_UNSUPPORTED, "device index beyond the static slots");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot& slot = g_static[dev];
+    if (slot.owner)
+        return fail(nullptr, GKS_E_STATE, "another context holds this GPU's static scratch (gks_destroy it first)");
+    if (!slot.ptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, GKS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        slot.ptr = p;
+    }
+    gks_ctx* c = nullptr;
+    const int rc = gks_init(cfg, q, q_stage, q_acc, slot.ptr, GKS_STATIC_SCRATCH_BYTES, hip_stream, &c);
+    if (rc != GKS_OK) return rc;
+    c->static_dev = dev;
+    slot.owner = c;
+    *out = c;
+    return GKS_OK;
+}
+
 void gks_destroy(gks_ctx* c) {
     if (!c) return;
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static[c->static_dev].owner == c) g_static[c->static_dev].owner = nullptr;
+    }
     delete c;
 }
 

@@ -29,7 +29,8 @@ class GksSolver:
     """
 
     def __init__(self, cfg, precision: str = "fp32", device: str = "cuda:0", max_act: Optional[int] = None,
-                 max_ibm: Optional[int] = None, q0: Optional[np.ndarray] = None, stream=None):
+                 max_ibm: Optional[int] = None, q0: Optional[np.ndarray] = None, stream=None,
+                 static_scratch: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("GksSolver needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.lib = L.load()
@@ -72,18 +73,26 @@ class GksSolver:
         self.q_acc = torch.zeros_like(self.q)
         q0 = cfg.q0 if q0 is None else q0
         self.set_interior(q0)
-        nbytes = self.lib.gks_workspace_bytes(C.byref(c))
-        if nbytes == 0:
-            raise L.GksError(L.GKS_E_INVALID_ARG, "invalid configuration")
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = _ptr(self.workspace)
-        self._ws_ptr = (base + 255) // 256 * 256
-        self._ws_bytes = nbytes
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = C.c_void_p()
-        rc = self.lib.gks_init(C.byref(c), self._field(self.q), self._field(self.q_stage), self._field(self.q_acc),
-                               C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
-                               C.byref(ctx))
+        if static_scratch:
+            # the workspace is the library's static device array (gks_init_static allocates nothing)
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                rc = self.lib.gks_init_static(C.byref(c), self._field(self.q), self._field(self.q_stage),
+                                              self._field(self.q_acc), C.c_void_p(self.stream.cuda_stream),
+                                              C.byref(ctx))
+        else:
+            nbytes = self.lib.gks_workspace_bytes(C.byref(c))
+            if nbytes == 0:
+                raise L.GksError(L.GKS_E_INVALID_ARG, "invalid configuration")
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = _ptr(self.workspace)
+            self._ws_ptr = (base + 255) // 256 * 256
+            self._ws_bytes = nbytes
+            rc = self.lib.gks_init(C.byref(c), self._field(self.q), self._field(self.q_stage),
+                                   self._field(self.q_acc), C.c_void_p(self._ws_ptr), C.c_size_t(nbytes),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         L.check(self.lib, None, rc)
         self.ctx = ctx
         self.n_act = 0

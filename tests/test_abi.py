@@ -154,3 +154,17 @@ def test_stretched_faces_validated():
     p = _cfg()                                             # periodic axis with its own faces
     p.faces[0] = ok.ctypes.data_as(P)
     assert lib.gks_workspace_bytes(C.byref(p)) == 0
+
+
+def test_static_init_refuses_oversize_before_device_work():
+    # gks_init_static checks the configuration's workspace against its static scratch before any HIP call
+    lib = L.load()
+    f = L.gks_field()
+    ctx = C.c_void_p()
+    big = _cfg(nx=192, ny=96, nz=96)
+    assert lib.gks_workspace_bytes(C.byref(big)) > L.GKS_STATIC_SCRATCH_BYTES
+    rc = lib.gks_init_static(C.byref(big), f, f, f, None, C.byref(ctx))
+    assert rc == L.GKS_E_INVALID_ARG and ctx.value is None
+    assert b"static scratch" in lib.gks_last_error(None)
+    assert lib.gks_init_static(C.byref(_cfg(nx=2)), f, f, f, None, C.byref(ctx)) == L.GKS_E_INVALID_ARG
+    assert lib.gks_init_static(C.byref(_cfg()), f, f, f, None, None) == L.GKS_E_INVALID_ARG
