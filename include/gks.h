@@ -120,6 +120,13 @@ typedef struct gks_rotor {
     int32_t u_inf_correction;        /* 1: free-stream velocity correction of Section 3.1 */
     int32_t tip_correction;          /* 1: tip correction of Section 4.4, Eq. (tip-correction), on F_x and F_theta */
     const double* scale;             /* DEVICE, n_act doubles: per-point force scaling s_p; NULL = 1 */
+    int32_t line_points;             /* line sampling of the NTNU rotor (Sections 3.1, 4.4; the method is
+                                        defined in the work they cite, so this is a stated reading): the
+                                        velocity of a point is the mean of trilinear samples at line_points
+                                        points, the midpoints of equal parts of the segment of half-length
+                                        line_half_length through it along the blade's direction of motion.
+                                        <= 1 or a zero length: point sampling (Section 3.1, NREL rotor) */
+    double line_half_length;         /* >= 0; every sampling segment must stay inside the interior cells */
 } gks_rotor;
 
 typedef struct gks_forces_out {
@@ -225,17 +232,22 @@ int gks_set_checkpoints(gks_ctx* ctx, void* buffer, int32_t capacity);
 /* Bytes of device scratch gks_adjoint needs. */
 size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
 
+/* gks_adjoint flags */
+#define GKS_ADJ_EXACT_WENO 1  /* differentiate the WENO nonlinear weights too (default: frozen) */
+
 /* Reverse-mode gradient of J = w[0] * mean_n P^n + w[1] * mean_n T^n over the first nsteps
  * checkpointed steps of the window with respect to the per-point force scalings s_p, written to grad_s
  * (DEVICE, n_act doubles, overwritten). If grad_q0 is not NULL it receives dJ/dQ^0 (DEVICE, 4 arrays of
- * nx*ny*nz doubles back to back, interior cells, x fastest; variable 0 is the density). The WENO
- * nonlinear weights are frozen at their forward values (differentiated as constants); everything else
- * (flux, kinetic average, S2O4 combination, ghost cells, actuator-line sampling, forces and projection)
- * is linearised exactly. Requires an FP64 context of the high-order scheme (order 5) with a rotor, no
- * immersed bodies, a fixed dt and periodic, wall or outflow boundaries. The stage buffers q_stage and q_acc are overwritten; q is not.
- * adj_ws: device scratch of gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
+ * nx*ny*nz doubles back to back, interior cells, x fastest; variable 0 is the density). By default the
+ * WENO nonlinear weights are frozen at their forward values (differentiated as constants); with
+ * GKS_ADJ_EXACT_WENO in flags they are differentiated as well, so the gradient is the derivative of the
+ * discrete forward itself. Everything else (flux, kinetic average, S2O4 combination, ghost cells,
+ * actuator-line sampling, forces and projection) is linearised exactly. Requires an FP64 context of the
+ * high-order scheme (order 5) with a rotor, no immersed bodies, a fixed dt and periodic, wall or outflow
+ * boundaries. The stage buffers q_stage and q_acc are overwritten; q is not. adj_ws: device scratch of
+ * gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
 int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0,
-                void* adj_ws, size_t adj_ws_bytes);
+                void* adj_ws, size_t adj_ws_bytes, int32_t flags);
 
 /* Running flow statistics of the cell velocity U = (rho U)/rho (Sections 4.1, 4.2, 4.3.2). The caller
  * provides a DEVICE buffer of gks_statistics_bytes (8-byte aligned); gks_set_statistics clears it and

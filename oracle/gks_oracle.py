@@ -75,6 +75,13 @@ R17 Stretched meshes (the channel of Section 4.1 is computed on a tanh-clustered
     an immersed body needs one cell width on the cells around it (the paper keeps its turbines in a
     uniformly refined block) and works on the uniform grid of that block; a moving body is checked
     again at every step.
+R18 Line sampling of the NTNU rotor (Section 3.1 and Section 4.4 name a line sampling method and defer
+    its definition to the cited ALM work; PROPOSED, parity unpinned against the paper): the velocity
+    of actuator point p is the mean of trilinear samples at N points spaced evenly (midpoints of N
+    equal parts) on the segment of half-length l through X_p along the blade's direction of motion
+    e_theta. The velocity that the element's own bound vortex induces is antisymmetric about X_p
+    along that direction and cancels in the mean. N = 1 or l = 0 is the point sampling of the NREL
+    case (Section 3.1).
 R11 Ghost cells: periodic copy; no-slip = mirror with rho even and all momenta odd; slip = normal
     momentum odd; inflow = prescribed velocity with rho from the outgoing isothermal Riemann invariant
     U -+ C ln rho; outflow = zero gradient. Axes are filled x, then y, then z (corners included).
@@ -96,7 +103,7 @@ __all__ = [
     "micro_coefficients", "gks_point_flux", "operator", "s2o4_stage1", "s2o4_final", "cfl_dt", "alm_apply", "rotor_points",
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
     "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics", "van_leer", "muscl_faces",
-    "rotation_matrix", "ibm_motion_state", "axis_metrics", "mesh_faces", "body_grid",
+    "rotation_matrix", "ibm_motion_state", "axis_metrics", "mesh_faces", "body_grid", "line_sample",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -650,6 +657,19 @@ def _trilinear(Q, cfg, X, grid=None):
     return torch.stack(out, 0)  # [n, 3]
 
 
+def line_sample(Q, cfg, X, et, half, npts, grid=None):
+    """Velocity at actuator points X by line sampling (reading R18): the mean of trilinear samples at
+    X + s_k e_theta, s_k = half ((2k + 1) / npts - 1), k = 0 .. npts - 1."""
+    if npts <= 1 or half == 0.0:
+        return _trilinear(Q, cfg, X, grid)
+    acc = None
+    for k in range(npts):
+        s_k = half * ((2 * k + 1) / npts - 1.0)
+        u = _trilinear(Q, cfg, X + s_k * np.asarray(et), grid)
+        acc = u if acc is None else acc + u
+    return acc / npts
+
+
 def tip_factor(rotor, r, phi, c1, c2):
     """f = (2/pi) acos(exp(-g1 N (R - r) / (2 r sin phi))), g1 = exp(-c1 (N lambda - c2)) + 0.1
     (Section 4.4, Eq. (tip-correction)); lambda = omega R / U_inf."""
@@ -662,13 +682,17 @@ def tip_factor(rotor, r, phi, c1, c2):
 
 
 def alm_apply(Q, t, dt, cfg, rotor, scales=None):
-    """Sample, blade-element forces, Gaussian projection truncated at 3 eps, momentum update
+    """Sample (point or line sampling, reading R18), blade-element forces, Gaussian projection truncated at 3 eps, momentum update
     (Section 3.1, Eqs. (axial-tangential), (Gaussian); Section 3.3; reading R9).
     Returns (Q_new, outputs)."""
     rmax = float(np.max(rotor.r))
     ext = 3.0 * rotor.eps
-    grid = body_grid(cfg, (rotor.hub[0] - ext, rotor.hub[1] - rmax - ext, rotor.hub[2] - rmax - ext),
-                     (rotor.hub[0] + ext, rotor.hub[1] + rmax + ext, rotor.hub[2] + rmax + ext), 1)
+    npts = int(getattr(rotor, "line_points", 1) or 1)
+    half = float(getattr(rotor, "line_half_length", 0.0) or 0.0)
+    # the sampling segments of line sampling reach sqrt(r^2 + l^2) from the rotor axis
+    reach = max(rmax + ext, math.sqrt(rmax * rmax + half * half)) if npts > 1 and half > 0.0 else rmax + ext
+    grid = body_grid(cfg, (rotor.hub[0] - ext, rotor.hub[1] - reach, rotor.hub[2] - reach),
+                     (rotor.hub[0] + ext, rotor.hub[1] + reach, rotor.hub[2] + reach), 1)
     X, et = rotor_points(rotor, t)
     n = X.shape[0]
     if scales is None:
@@ -678,7 +702,7 @@ def alm_apply(Q, t, dt, cfg, rotor, scales=None):
     chord = torch.tensor(np.tile(rotor.chord, rotor.n_blades), dtype=F64)
     twist = torch.tensor(np.tile(rotor.twist, rotor.n_blades), dtype=F64)
     width = torch.tensor(np.tile(rotor.width, rotor.n_blades), dtype=F64)
-    U = _trilinear(Q, cfg, X, grid)
+    U = line_sample(Q, cfg, X, et, half, npts, grid) if npts > 1 and half > 0.0 else _trilinear(Q, cfg, X, grid)
     ett = torch.tensor(et, dtype=F64)
     ux = U[:, 0]
     ut = (U * ett).sum(1)

@@ -18,6 +18,7 @@ GKS_E_UNSUPPORTED = 6
 GKS_E_BODY_LEFT = 7
 GKS_WARN_EPS_SMALL = 1
 GKS_WARN_MACH = 2
+GKS_ADJ_EXACT_WENO = 1
 
 BC = {"periodic": 0, "noslip": 1, "slip": 2, "inflow": 3, "outflow": 4}
 GKS_FP32 = 0
@@ -56,6 +57,7 @@ class gks_rotor(C.Structure):
         ("cd0", C.c_double), ("cd2", C.c_double),
         ("u_inf_correction", C.c_int32), ("tip_correction", C.c_int32),
         ("scale", C.c_void_p),
+        ("line_points", C.c_int32), ("line_half_length", C.c_double),
     ]
 
 
@@ -125,7 +127,7 @@ def load(path: str = LIB_PATH):
     lib.gks_set_checkpoints.restype = C.c_int
     lib.gks_adjoint_workspace_bytes.argtypes = [C.POINTER(gks_config), C.c_int32]
     lib.gks_adjoint_workspace_bytes.restype = C.c_size_t
-    lib.gks_adjoint.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P, P, P, C.c_size_t]
+    lib.gks_adjoint.argtypes = [P, C.c_int32, C.POINTER(C.c_double), P, P, P, C.c_size_t, C.c_int32]
     lib.gks_adjoint.restype = C.c_int
     lib.gks_set_timing.argtypes = [P, C.c_int32]
     lib.gks_set_timing.restype = C.c_int

@@ -1,10 +1,12 @@
 // gks_adjoint.h -- discrete adjoint of the S2O4 step with the actuator-line body force (internal).
 //
-// The reverse sweep linearises the step exactly except for the WENO nonlinear weights, which are
-// held at their forward values. Per face direction and stage operator the transpose is computed in
-// gather form, without atomics, in four passes over buffers in the adjoint workspace:
-//   A  recompute the forward face pipeline, store the frozen weights of every WENO evaluation and the
-//      adjoints of the Gauss-point inputs (q^L, q^R, dQ/dn, dQ/dt1, dQ/dt2) from the flux seeds;
+// The reverse sweep linearises the step exactly; the WENO nonlinear weights are either held at their
+// forward values (frozen, the default) or differentiated too (exact). Per face direction and stage
+// operator the transpose is computed in gather form, without atomics, in four passes over buffers in
+// the adjoint workspace:
+//   A  recompute the forward face pipeline, store the coefficients of every WENO evaluation (frozen:
+//      its weights; exact: its Jacobian row) and the adjoints of the Gauss-point inputs (q^L, q^R,
+//      dQ/dn, dQ/dt1, dQ/dt2) from the flux seeds;
 //   B  transpose of the t2 sweep (gather over the five faces whose stencils hold a t1 line value);
 //   C  transpose of the t1 sweep (gather over five positions) and of C = (q^L + q^R)/2;
 //   D  transpose of the normal reconstruction into the padded cell adjoint;
@@ -23,9 +25,9 @@ struct AdjFaceArgs {
     const double* mu0[4];   // seed of L (interior, local order), stage 1 only
     const double* mu1[4];   // seed of L_t
     double* gpbar;          // [80][nface]
-    double* w_t2;           // [96][nface]
-    double* w_t1;           // [48][nt1pos]
-    double* w_n;            // [24][nnpos]
+    double* w_t2;           // [32 NW][nface], NW = 3 frozen weights or 5 Jacobian entries per evaluation
+    double* w_t1;           // [16 NW][nt1pos]
+    double* w_n;            // [8 NW][nnpos]
     double* t1bar;          // [40][nt1pos]
     double* fabar;          // [12][nnpos]
     double* acc[4];         // padded cell adjoint accumulator (LOCAL order)
@@ -38,6 +40,7 @@ struct AdjFaceArgs {
     double inv_hn, inv_h1, inv_h2;
     double eps;
     FluxConst<double> fc;
+    int exact;              // 1: the WENO weights are differentiated (Jacobian rows), 0: frozen
 };
 
 size_t adjoint_workspace_bytes(int nx, int ny, int nz, int n_act);

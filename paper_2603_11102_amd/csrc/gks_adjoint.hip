@@ -8,6 +8,7 @@
 // forward values; every other operation is linearised exactly. No atomics are used, so gradients are
 // bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "gks_adjoint.h"
 
@@ -25,17 +26,36 @@ __device__ __forceinline__ long long n_ix(const AdjFaceArgs& a, int f, int jx, i
     return ((long long)f * (a.n_t2 + 4) + (kx + 2)) * (a.n_t1 + 4) + (jx + 2);
 }
 
+// Coefficient of stencil cell r in a WENO evaluation on `side` from its stored coefficients: the frozen
+// weights expanded over the sub-stencils, or (EXACT) the stored Jacobian entry.
+template <bool EXACT>
+__device__ __forceinline__ double wcoef(int side, const double* c, int r) {
+    if constexpr (EXACT) {
+        return c[r];
+    } else {
+        return weno_eff(side, c, r);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
-// pass A: recompute the face pipeline of one direction, store the frozen weights and the Gauss-point
-// states (in the gpbar slots)
+// pass A: recompute the face pipeline of one direction (the forward's 16 x 8 face tiles of 256 threads,
+// one wave per SIMD so that the FP64 state fits the unified register file), store the coefficients of
+// every WENO evaluation (frozen: its three nonlinear weights; EXACT: its Jacobian row over the five
+// stencil cells, the weights differentiated too) and, per face and Gauss point, the adjoints of the
+// Gauss-point inputs from the reverse of the flux (seeds Fbar(f) = (mu(f) - mu(f-1)) / h)
 // ------------------------------------------------------------------------------------------------
-template <int STAGE>
-__global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArgs a) {
+template <int STAGE, bool EXACT>
+__global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(const AdjFaceArgs a) {
     constexpr bool NEED_F0 = (STAGE == 1);
-    __shared__ double s_nrm[4][EXT2][EXT1];
-    __shared__ double s_t1[5][EXT2][TILE1][2];
+    constexpr int T2 = FaceTile<double>::T2, X2 = T2 + 4, NTH = FaceTile<double>::THREADS;
+    constexpr int NW = EXACT ? 5 : 3;
+    static_assert(EXT1 * X2 <= NTH && 2 * TILE1 * T2 == NTH && TILE1 * X2 <= NTH, "thread roles");
+    __shared__ double s_nrm[4][X2][EXT1];
+    __shared__ double s_t1[5][X2][TILE1][2];
+    // Gauss-point states of each thread's face line: [(variable * 2 + Gauss point) * 5 + quantity][thread]
+    __shared__ double s_gp[40][NTH];
 
     const int tid = threadIdx.x;
     // consecutive logical workgroups on the same XCD (grid padded to a multiple of 8), as in the forward
@@ -47,21 +67,30 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
     b /= a.tiles_t2;
     const int f0 = b * a.chunk;
     const int f1 = min(f0 + a.chunk, a.n_n);
-    const int j0 = tile1 * TILE1, k0 = tile2 * TILE2;
+    const int j0 = tile1 * TILE1, k0 = tile2 * T2;
     const double eps = a.eps;
 
-    const bool col = tid < EXT1 * EXT2;
+    const bool col = tid < EXT1 * X2;
     const int c1 = tid % EXT1, c2 = tid / EXT1;
     const int jc = j0 - 2 + c1, kc = k0 - 2 + c2;
     const bool col_ld = col && (jc < a.n_t1 + NG) && (kc < a.n_t2 + NG);
     const bool col_st = col && (jc < a.n_t1 + 2) && (kc < a.n_t2 + 2);
     const long long cbase = a.pad0 + (long long)jc * a.st_t1 + (long long)kc * a.st_t2;
-    const bool t1r = tid < TILE1 * EXT2;
+    const bool t1r = tid < TILE1 * X2;
     const int tj = tid % TILE1, tk = tid / TILE1;
     const bool t1_st = t1r && (j0 + tj < a.n_t1) && (k0 - 2 + tk < a.n_t2 + 2);
     const int m = tid & 1;
     const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
     const bool face_ok = (j0 + fj < a.n_t1) && (k0 + fk < a.n_t2);
+
+    // coefficients of one WENO evaluation: the weights, or the Jacobian row
+    auto coefs = [&](int side, const double q[5], const double w[3], double v, double out[NW]) {
+        if constexpr (EXACT) {
+            weno_jacobian(side, q, eps, w, v, out);
+        } else {
+            for (int kk = 0; kk < 3; ++kk) out[kk] = w[kk];
+        }
+    };
 
     double ring[4][5];
     double carry[4];
@@ -79,8 +108,10 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
             weno_faces_w<double>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left, wr, wl);
             carry[v] = right;
             if (col_st) {
+                double cf[NW];
+                coefs(0, ring[v], wr, right, cf);
                 const long long p = n_ix(a, f0, jc, kc);
-                for (int kk = 0; kk < 3; ++kk) a.w_n[((v * 2 + 0) * 3 + kk) * a.nnpos + p] = wr[kk];
+                for (int kk = 0; kk < NW; ++kk) a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p] = cf[kk];
             }
         }
     }
@@ -93,13 +124,9 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                 ring[v][4] = a.q[v][idx];
             }
         }
-        // Gauss-point states of this face go to the gpbar slots; adj_gp_kernel turns them into adjoints
-        const long long fi_own = face_ok ? face_ix(a, f, j0 + fj, k0 + fk) : 0;
-        auto put = [&](int v, int n, int q, double val) {
-            if (face_ok) a.gpbar[(long long)(((v * 2 + m) * 2 + n) * 5 + q) * a.nface + fi_own] = val;
-        };
-
-        auto column = [&](int v) {
+        // column phase of one variable; v is a compile-time constant so that ring stays in registers
+        auto column = [&](auto vc) {
+            constexpr int v = decltype(vc)::value;
             if (col) {
                 double right, left, wr[3], wl[3];
                 weno_faces_w<double>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left,
@@ -112,17 +139,21 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                 s_nrm[3][c2][c1] = 0.5 * (qL + left);
                 carry[v] = right;
                 if (col_st) {
+                    double cf[NW];
                     const long long p = n_ix(a, f, jc, kc);
-                    for (int kk = 0; kk < 3; ++kk) a.w_n[((v * 2 + 1) * 3 + kk) * a.nnpos + p] = wl[kk];
+                    coefs(1, ring[v], wl, left, cf);
+                    for (int kk = 0; kk < NW; ++kk) a.w_n[((v * 2 + 1) * NW + kk) * a.nnpos + p] = cf[kk];
                     if (f + 1 <= f1) {
                         const long long p1 = n_ix(a, f + 1, jc, kc);
-                        for (int kk = 0; kk < 3; ++kk) a.w_n[((v * 2 + 0) * 3 + kk) * a.nnpos + p1] = wr[kk];
+                        coefs(0, ring[v], wr, right, cf);
+                        for (int kk = 0; kk < NW; ++kk) a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p1] = cf[kk];
                     }
                 }
             }
         };
 
-        column(0);
+        auto put = [&](int v, int n, int q, double val) { s_gp[(v * 2 + n) * 5 + q][tid] = val; };
+        column(std::integral_constant<int, 0>{});
         __syncthreads();
         for (int v = 0; v < 4; ++v) {
             if (t1r) {
@@ -135,11 +166,15 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                     weno_gauss_w<double>(x[side][0], x[side][1], x[side][2], x[side][3], x[side][4], eps, vm, vp, wm, wp);
                     s_t1[side][tk][tj][0] = vm;
                     s_t1[side][tk][tj][1] = vp;
-                    if (t1_st)
-                        for (int kk = 0; kk < 3; ++kk) {
-                            a.w_t1[(((v * 2 + side) * 2 + 0) * 3 + kk) * a.nt1pos + p] = wm[kk];
-                            a.w_t1[(((v * 2 + side) * 2 + 1) * 3 + kk) * a.nt1pos + p] = wp[kk];
+                    if (t1_st) {
+                        double cm_[NW], cp_[NW];
+                        coefs(2, x[side], wm, vm, cm_);
+                        coefs(3, x[side], wp, vp, cp_);
+                        for (int kk = 0; kk < NW; ++kk) {
+                            a.w_t1[(((v * 2 + side) * 2 + 0) * NW + kk) * a.nt1pos + p] = cm_[kk];
+                            a.w_t1[(((v * 2 + side) * 2 + 1) * NW + kk) * a.nt1pos + p] = cp_[kk];
                         }
+                    }
                 }
                 quartic_gauss_value<double>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
                 s_t1[2][tk][tj][0] = vm;
@@ -162,11 +197,15 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                     weno_gauss_w<double>(y[side][0], y[side][1], y[side][2], y[side][3], y[side][4], eps, vm, vp, wm, wp);
                     put(v, 0, side, vm);
                     put(v, 1, side, vp);
-                    if (face_ok)
-                        for (int kk = 0; kk < 3; ++kk) {
-                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 0) * 3 + kk) * a.nface + fi] = wm[kk];
-                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 1) * 3 + kk) * a.nface + fi] = wp[kk];
+                    if (face_ok) {
+                        double cm_[NW], cp_[NW];
+                        coefs(2, y[side], wm, vm, cm_);
+                        coefs(3, y[side], wp, vp, cp_);
+                        for (int kk = 0; kk < NW; ++kk) {
+                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 0) * NW + kk) * a.nface + fi] = cm_[kk];
+                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 1) * NW + kk) * a.nface + fi] = cp_[kk];
                         }
+                    }
                 }
                 quartic_gauss_value<double>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
                 put(v, 0, 2, vm);
@@ -178,62 +217,55 @@ __global__ void __launch_bounds__(FACE_THREADS) adj_face_kernel(const AdjFaceArg
                 put(v, 0, 4, vm * a.inv_h2);
                 put(v, 1, 4, vp * a.inv_h2);
             }
-            if (v < 3) column(v + 1);
+            switch (v) {
+                case 0: column(std::integral_constant<int, 1>{}); break;
+                case 1: column(std::integral_constant<int, 2>{}); break;
+                case 2: column(std::integral_constant<int, 3>{}); break;
+                default: break;
+            }
             __syncthreads();
         }
 
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
-// pass A2: adjoint of the gas-kinetic flux at one Gauss point per thread. Reads the point's state from
-// its gpbar slots (written by pass A) and overwrites them with the adjoints of that state.
-// ------------------------------------------------------------------------------------------------
-template <int STAGE>
-__global__ void __launch_bounds__(256) adj_gp_kernel(const AdjFaceArgs a) {
-    constexpr bool NEED_F0 = (STAGE == 1);
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 4 * a.nface) return;
-    const long long fi = t % a.nface;
-    const int mn = (int)(t / a.nface);
-    const int m = mn & 1, n = mn >> 1;
-    const int j = (int)(fi % a.n_t1);
-    const long long r_ = fi / a.n_t1;
-    const int k = (int)(r_ % a.n_t2);
-    const int f = (int)(r_ / a.n_t2);
-    // seeds of the face flux: L(i) = -(F(i+1/2) - F(i-1/2))/h  =>  Fbar(f) = (mu(f) - mu(f-1))/h
-    const long long jk = (long long)j * a.ist_t1 + (long long)k * a.ist_t2;
-    double b0[4], b1[4];
-    for (int v = 0; v < 4; ++v) {
-        const double hi1 = f < a.n_n ? a.mu1[v][(long long)f * a.ist_n + jk] : 0.0;
-        const double lo1 = f >= 1 ? a.mu1[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
-        b1[v] = (hi1 - lo1) * a.inv_hn;
-        if (NEED_F0) {
-            const double hi0 = f < a.n_n ? a.mu0[v][(long long)f * a.ist_n + jk] : 0.0;
-            const double lo0 = f >= 1 ? a.mu0[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
-            b0[v] = (hi0 - lo0) * a.inv_hn;
-        } else {
-            b0[v] = 0.0;
+        // reverse of the flux at this thread's two Gauss points: the adjoints of their inputs go to the
+        // gpbar slots of this face
+        if (face_ok) {
+            const long long fi = face_ix(a, f, j0 + fj, k0 + fk);
+            const long long jk = (long long)(j0 + fj) * a.ist_t1 + (long long)(k0 + fk) * a.ist_t2;
+            double b0[4], b1[4];
+            for (int v = 0; v < 4; ++v) {
+                const double hi1 = f < a.n_n ? a.mu1[v][(long long)f * a.ist_n + jk] : 0.0;
+                const double lo1 = f >= 1 ? a.mu1[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
+                b1[v] = (hi1 - lo1) * a.inv_hn;
+                if (NEED_F0) {
+                    const double hi0 = f < a.n_n ? a.mu0[v][(long long)f * a.ist_n + jk] : 0.0;
+                    const double lo0 = f >= 1 ? a.mu0[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
+                    b0[v] = (hi0 - lo0) * a.inv_hn;
+                } else {
+                    b0[v] = 0.0;
+                }
+            }
+            for (int n = 0; n < 2; ++n) {
+                double qL[4], qR[4], g[3][4], qLb[4] = {0, 0, 0, 0}, qRb[4] = {0, 0, 0, 0};
+                double gb[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+                for (int v = 0; v < 4; ++v) {
+                    const int q0 = (v * 2 + n) * 5;
+                    qL[v] = s_gp[q0][tid];
+                    qR[v] = s_gp[q0 + 1][tid];
+                    g[0][v] = s_gp[q0 + 2][tid];
+                    g[1][v] = s_gp[q0 + 3][tid];
+                    g[2][v] = s_gp[q0 + 4][tid];
+                }
+                gp_flux_adj<NEED_F0>(qL, qR, g, a.fc, 0.25, b0, b1, qLb, qRb, gb);
+                for (int v = 0; v < 4; ++v) {
+                    const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
+                    a.gpbar[base] = qLb[v];
+                    a.gpbar[base + a.nface] = qRb[v];
+                    a.gpbar[base + 2 * a.nface] = gb[0][v];
+                    a.gpbar[base + 3 * a.nface] = gb[1][v];
+                    a.gpbar[base + 4 * a.nface] = gb[2][v];
+                }
+            }
         }
-    }
-    double qL[4], qR[4], g[3][4], qLb[4] = {0, 0, 0, 0}, qRb[4] = {0, 0, 0, 0};
-    double gb[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    for (int v = 0; v < 4; ++v) {
-        const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
-        qL[v] = a.gpbar[base];
-        qR[v] = a.gpbar[base + a.nface];
-        g[0][v] = a.gpbar[base + 2 * a.nface];
-        g[1][v] = a.gpbar[base + 3 * a.nface];
-        g[2][v] = a.gpbar[base + 4 * a.nface];
-    }
-    gp_flux_adj<NEED_F0>(qL, qR, g, a.fc, 0.25, b0, b1, qLb, qRb, gb);
-    for (int v = 0; v < 4; ++v) {
-        const long long base = (long long)(((v * 2 + m) * 2 + n) * 5) * a.nface + fi;
-        a.gpbar[base] = qLb[v];
-        a.gpbar[base + a.nface] = qRb[v];
-        a.gpbar[base + 2 * a.nface] = gb[0][v];
-        a.gpbar[base + 3 * a.nface] = gb[1][v];
-        a.gpbar[base + 4 * a.nface] = gb[2][v];
     }
 }
 
@@ -242,7 +274,9 @@ __global__ void __launch_bounds__(256) adj_gp_kernel(const AdjFaceArgs a) {
 // ------------------------------------------------------------------------------------------------
 constexpr int T2_STRIP = 4;  // consecutive t2 outputs per thread in pass B
 
+template <bool EXACT>
 __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
+    constexpr int NW = EXACT ? 5 : 3;
     // one thread per (t1 line position, variable, Gauss line m, strip of T2_STRIP consecutive t2
     // positions incl. halo, face); the t1 position is the fastest index so that a wave reads
     // contiguous runs of every plane. Each face value loaded serves every output of the strip whose
@@ -272,11 +306,11 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
             const int side = n == 0 ? 2 : 3;
             const int s = n == 0 ? -1 : 1;
             const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
-            double wL[3], wR[3], gv[5];
+            double wL[NW], wR[NW], gv[5];
 #pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-                wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * 3 + kk) * a.nface + fi];
-                wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * 3 + kk) * a.nface + fi];
+            for (int kk = 0; kk < NW; ++kk) {
+                wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * NW + kk) * a.nface + fi];
+                wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * NW + kk) * a.nface + fi];
             }
 #pragma unroll
             for (int q = 0; q < 5; ++q) gv[q] = a.gpbar[gbase + q * a.nface];
@@ -285,8 +319,8 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
                 const int r = o - dk + 4;  // stencil slot of face k for output kx0 + o (compile time)
                 if (r < 0 || r > 4) continue;
                 const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h2;
-                bar[o][0] += weno_eff(side, wL, r) * gv[0];
-                bar[o][1] += weno_eff(side, wR, r) * gv[1];
+                bar[o][0] += wcoef<EXACT>(side, wL, r) * gv[0];
+                bar[o][1] += wcoef<EXACT>(side, wR, r) * gv[1];
                 bar[o][2] += cv * gv[2];
                 bar[o][3] += cv * gv[3];
                 bar[o][4] += cd * gv[4];
@@ -307,7 +341,9 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
 // pass C: transpose of the t1 sweep and of C = (q^L + q^R)/2 -> adjoints of q^L, q^R, D per face
 // position (tangential halo included)
 // ------------------------------------------------------------------------------------------------
+template <bool EXACT>
 __global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
+    constexpr int NW = EXACT ? 5 : 3;
     // one thread per (t1 position incl. halo, variable, t2 position incl. halo, face)
     const long long total = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 4 * (a.n_t1 + 4);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,13 +363,13 @@ __global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
             const int s = m == 0 ? -1 : 1;
             const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h1;
             const long long tb = (long long)((v * 2 + m) * 5) * a.nt1pos + p;
-            double wL[3], wR[3];
-            for (int kk = 0; kk < 3; ++kk) {
-                wL[kk] = a.w_t1[(((v * 2 + 0) * 2 + m) * 3 + kk) * a.nt1pos + p];
-                wR[kk] = a.w_t1[(((v * 2 + 1) * 2 + m) * 3 + kk) * a.nt1pos + p];
+            double wL[NW], wR[NW];
+            for (int kk = 0; kk < NW; ++kk) {
+                wL[kk] = a.w_t1[(((v * 2 + 0) * 2 + m) * NW + kk) * a.nt1pos + p];
+                wR[kk] = a.w_t1[(((v * 2 + 1) * 2 + m) * NW + kk) * a.nt1pos + p];
             }
-            bar[0] += weno_eff(side, wL, r) * a.t1bar[tb];
-            bar[1] += weno_eff(side, wR, r) * a.t1bar[tb + a.nt1pos];
+            bar[0] += wcoef<EXACT>(side, wL, r) * a.t1bar[tb];
+            bar[1] += wcoef<EXACT>(side, wR, r) * a.t1bar[tb + a.nt1pos];
             bar[2] += cv * a.t1bar[tb + 2 * a.nt1pos];
             Cb += cd * a.t1bar[tb + 3 * a.nt1pos];
             Cb += cv * a.t1bar[tb + 4 * a.nt1pos];
@@ -348,7 +384,9 @@ __global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
 // ------------------------------------------------------------------------------------------------
 // pass D: transpose of the normal reconstruction -> padded cell adjoint (accumulated)
 // ------------------------------------------------------------------------------------------------
+template <bool EXACT>
 __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
+    constexpr int NW = EXACT ? 5 : 3;
     const long long total = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
@@ -362,9 +400,9 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
         const int r = i - f + 3;
         const long long p = n_ix(a, f, jx, kx);
         for (int v = 0; v < 4; ++v) {
-            double w[3];
-            for (int kk = 0; kk < 3; ++kk) w[kk] = a.w_n[((v * 2 + 0) * 3 + kk) * a.nnpos + p];
-            bar[v] += weno_eff(0, w, r) * a.fabar[(long long)(v * 3 + 0) * a.nnpos + p];
+            double w[NW];
+            for (int kk = 0; kk < NW; ++kk) w[kk] = a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p];
+            bar[v] += wcoef<EXACT>(0, w, r) * a.fabar[(long long)(v * 3 + 0) * a.nnpos + p];
         }
     }
     // q^R(f) = sum_r W^R_f[r] Q(f-2+r)
@@ -372,9 +410,9 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
         const int r = i - f + 2;
         const long long p = n_ix(a, f, jx, kx);
         for (int v = 0; v < 4; ++v) {
-            double w[3];
-            for (int kk = 0; kk < 3; ++kk) w[kk] = a.w_n[((v * 2 + 1) * 3 + kk) * a.nnpos + p];
-            bar[v] += weno_eff(1, w, r) * a.fabar[(long long)(v * 3 + 1) * a.nnpos + p];
+            double w[NW];
+            for (int kk = 0; kk < NW; ++kk) w[kk] = a.w_n[((v * 2 + 1) * NW + kk) * a.nnpos + p];
+            bar[v] += wcoef<EXACT>(1, w, r) * a.fabar[(long long)(v * 3 + 1) * a.nnpos + p];
         }
     }
     // D(f) = (Q(f-2) - 15 Q(f-1) + 15 Q(f) - Q(f+1)) / (12 h)
@@ -388,24 +426,25 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
     for (int v = 0; v < 4; ++v) a.acc[v][q] += bar[v];
 }
 
-hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) {
+template <bool EXACT>
+hipError_t launch_adj_passes(const AdjFaceArgs& a, int stage, hipStream_t s) {
     const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
     const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
-    const long long nA = 4 * a.nface;
-    if (stage == 1) {
-        hipLaunchKernelGGL((adj_face_kernel<1>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
-        hipLaunchKernelGGL((adj_gp_kernel<1>), dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((adj_face_kernel<2>), dim3((unsigned)blocks), dim3(FACE_THREADS), 0, s, a);
-        hipLaunchKernelGGL((adj_gp_kernel<2>), dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, s, a);
-    }
+    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 fgrid((unsigned)blocks), fblock(FaceTile<double>::THREADS);
+    if (stage == 1) hipLaunchKernelGGL((adj_face_kernel<1, EXACT>), fgrid, fblock, 0, s, a);
+    else hipLaunchKernelGGL((adj_face_kernel<2, EXACT>), fgrid, fblock, 0, s, a);
     const long long nB = (long long)(a.n_n + 1) * a.n_t1 * ((a.n_t2 + 4 + T2_STRIP - 1) / T2_STRIP) * 8;
-    hipLaunchKernelGGL(adj_t2_kernel, dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adj_t2_kernel<EXACT>), dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
     const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4) * 4;
-    hipLaunchKernelGGL(adj_t1_kernel, dim3((unsigned)((nC + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adj_t1_kernel<EXACT>), dim3((unsigned)((nC + 255) / 256)), dim3(256), 0, s, a);
     const long long nD = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
-    hipLaunchKernelGGL(adj_normal_kernel, dim3((unsigned)((nD + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((adj_normal_kernel<EXACT>), dim3((unsigned)((nD + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s) {
+    return a.exact ? launch_adj_passes<true>(a, stage, s) : launch_adj_passes<false>(a, stage, s);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -626,34 +665,46 @@ __global__ void alm_adj_points_kernel(AlmAdjArgs A) {
     A.pt[5 * a.n_act + p] = utb * et2;
 }
 
-// adjoint of the trilinear sampling, points in fixed order (one thread)
+// adjoint of the velocity sampling (trilinear, or the mean of trilinear samples along the direction of
+// motion), points and samples in fixed order (one thread)
 __global__ void alm_adj_scatter_kernel(AlmAdjArgs A) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const AlmArgs& a = A.fwd;
+    const int ns = a.line_n > 1 ? a.line_n : 1;
+    const double t = a.st->t_next;
     for (int p = 0; p < a.n_act; ++p) {
-        const double Ub[3] = {A.pt[3 * a.n_act + p], A.pt[4 * a.n_act + p], A.pt[5 * a.n_act + p]};
-        int i0[3];
-        double w1[3];
-        for (int d = 0; d < 3; ++d) {
-            const double fc = (a.X[3 * p + d] - a.g.x0[d]) / a.g.h[d] - 0.5;
-            const double fl = floor(fc);
-            i0[d] = (int)fl;
-            w1[d] = fc - fl;
-        }
-        for (int dz = 0; dz < 2; ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) * (dz ? w1[2] : 1.0 - w1[2]);
-                    const long long q = pidx_g(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
-                    const double rho = a.rho_ref + A.qpre[0][q];
-                    double dot = 0.0;
-                    for (int c = 0; c < 3; ++c) {
-                        const double Uc = A.qpre[1 + c][q] / rho;
-                        A.lam_pre[1 + c][q] += w * Ub[c] / rho;
-                        dot += Ub[c] * Uc;
+        double Ub[3] = {A.pt[3 * a.n_act + p], A.pt[4 * a.n_act + p], A.pt[5 * a.n_act + p]};
+        if (ns > 1)
+            for (int c = 0; c < 3; ++c) Ub[c] /= (double)ns;
+        const int bl = p / a.npb;
+        const double th = a.theta0 + a.omega * t + 2.0 * M_PI * (double)bl / (double)a.nb;
+        const double et1 = -sin(th), et2 = cos(th);
+        for (int k = 0; k < ns; ++k) {
+            const double sk = ns > 1 ? line_offset(a, k) : 0.0;
+            const double Xs[3] = {a.X[3 * p], a.X[3 * p + 1] + sk * et1, a.X[3 * p + 2] + sk * et2};
+            int i0[3];
+            double w1[3];
+            for (int d = 0; d < 3; ++d) {
+                const double fc = (Xs[d] - a.g.x0[d]) / a.g.h[d] - 0.5;
+                const double fl = floor(fc);
+                i0[d] = (int)fl;
+                w1[d] = fc - fl;
+            }
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) * (dz ? w1[2] : 1.0 - w1[2]);
+                        const long long q = pidx_g(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+                        const double rho = a.rho_ref + A.qpre[0][q];
+                        double dot = 0.0;
+                        for (int c = 0; c < 3; ++c) {
+                            const double Uc = A.qpre[1 + c][q] / rho;
+                            A.lam_pre[1 + c][q] += w * Ub[c] / rho;
+                            dot += Ub[c] * Uc;
+                        }
+                        A.lam_pre[0][q] += -w * dot / rho;
                     }
-                    A.lam_pre[0][q] += -w * dot / rho;
-                }
+        }
     }
 }
 
@@ -692,10 +743,11 @@ void adjoint_carve(char* base, int nx, int ny, int nz, int n_act, AdjBuffers* b,
         nn = std::max(nn, a0 * (a1 + 4) * (a2 + 4));
     }
     b->gpbar = reinterpret_cast<double*>(take(80 * nface * 8));
-    b->w_t2 = reinterpret_cast<double*>(take(96 * nface * 8));
-    b->w_t1 = reinterpret_cast<double*>(take(48 * nt1 * 8));
+    // WENO coefficients: 5 per evaluation (the Jacobian rows of the exact mode; the frozen weights use 3)
+    b->w_t2 = reinterpret_cast<double*>(take(160 * nface * 8));
+    b->w_t1 = reinterpret_cast<double*>(take(80 * nt1 * 8));
     b->t1bar = reinterpret_cast<double*>(take(40 * nt1 * 8));
-    b->w_n = reinterpret_cast<double*>(take(24 * nn * 8));
+    b->w_n = reinterpret_cast<double*>(take(40 * nn * 8));
     b->fabar = reinterpret_cast<double*>(take(12 * nn * 8));
     b->pt = reinterpret_cast<double*>(take(16 * (size_t)std::max(n_act, 1) * 8));
     *total = off;

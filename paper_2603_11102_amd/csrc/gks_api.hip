@@ -70,7 +70,6 @@ struct gks_ctx {
     std::vector<double> faces[3];  // host copy of the faces of each stretched axis (empty when uniform)
     double lam, c, hmin, eps;
     int chunk[3];      // faces per workgroup of the face kernels, per direction
-    int chunk_adj[3];  // the same for the adjoint's 16 x 16 tiles
     int flags;
     // actuator line model
     int has_rotor;
@@ -450,7 +449,7 @@ FaceArgs<real> face_args(gks_ctx* c, int d, int stage, void* const src[4]) {
     return face_args_buf<real>(c, d, 2, src, c->q, c->qa, nullptr, c->qt, c->lo_qa, c->lo_q, nullptr);
 }
 
-AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4]) {
+AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4], int exact) {
     AdjFaceArgs a;
     std::memset(&a, 0, sizeof(a));
     const int* pm = kPerm[d];
@@ -472,9 +471,10 @@ AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4])
     a.n_n = c->g.n[ax[0]];
     a.n_t1 = c->g.n[ax[1]];
     a.n_t2 = c->g.n[ax[2]];
+    // the forward FP64 face tiles (16 x 8 faces, 256 threads) and march chunks
     a.tiles_t1 = (a.n_t1 + TILE1 - 1) / TILE1;
-    a.tiles_t2 = (a.n_t2 + TILE2 - 1) / TILE2;
-    a.chunk = c->chunk_adj[d];
+    a.tiles_t2 = (a.n_t2 + FaceTile<double>::T2 - 1) / FaceTile<double>::T2;
+    a.chunk = c->chunk[d];
     a.st_n = c->g.st[ax[0]];
     a.st_t1 = c->g.st[ax[1]];
     a.st_t2 = c->g.st[ax[2]];
@@ -495,6 +495,7 @@ AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4])
     a.fc.c2 = 1.0 / (2.0 * c->lam);
     a.fc.mu = c->cfg.mu;
     a.fc.rho_ref = c->cfg.rho_ref;
+    a.exact = exact;
     return a;
 }
 
@@ -724,12 +725,6 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + t2 - 1) / t2);
         c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles, slots)
                                                  : face_chunk<double>(n[ax[0]], tiles, slots);
-        // the adjoint's kernels (16 x 16 tiles, one 512-thread workgroup per CU)
-        const int tiles16 = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + TILE2 - 1) / TILE2);
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 256;
-        c->chunk_adj[d] = face_chunk<double>(n[ax[0]], tiles16, cus);
     }
     hipError_t e = cfg->precision == GKS_FP32 ? upload_metrics<float>(c, cfg) : upload_metrics<double>(c, cfg);
     if (e == hipSuccess) e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
@@ -768,21 +763,30 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
             if (r->chord[i] * (r->cd0 + r->cd2 * (M_PI * M_PI)) >= 4.0 * std::sqrt(M_PI) * r->eps)
                 return fail(c, GKS_E_INVALID_ARG, "free-stream correction denominator can vanish (chord too large for eps)");
     }
+    if (!(r->line_half_length >= 0.0) || !std::isfinite(r->line_half_length))
+        return fail(c, GKS_E_INVALID_ARG, "line_half_length must be finite and >= 0");
+    const bool line = r->line_points > 1 && r->line_half_length > 0.0;
+    // distance from the rotor axis that a sampling position can reach over a revolution (a segment
+    // along the direction of motion at radius r reaches sqrt(r^2 + l^2))
+    const double reach = line ? std::sqrt(rmax * rmax + r->line_half_length * r->line_half_length) : rmax;
     // box of cells the rotor can touch: projection spheres (3 eps) around the swept disc, plus the
-    // trilinear sampling cells; it must lie inside the interior cells
+    // trilinear sampling cells; it must lie inside the interior cells (and on a stretched mesh within
+    // cells of one width)
     const double ext = 3.0 * r->eps;
     const double lo[3] = {r->hub[0] - ext, r->hub[1] - rmax - ext, r->hub[2] - rmax - ext};
     const double hi[3] = {r->hub[0] + ext, r->hub[1] + rmax + ext, r->hub[2] + rmax + ext};
+    const double glo[3] = {lo[0], std::min(lo[1], r->hub[1] - reach), std::min(lo[2], r->hub[2] - reach)};
+    const double ghi[3] = {hi[0], std::max(hi[1], r->hub[1] + reach), std::max(hi[2], r->hub[2] + reach)};
     GridDesc gb;
-    if (!body_grid(c, lo, hi, 1, &gb))
+    if (!body_grid(c, glo, ghi, 1, &gb))
         return fail(c, GKS_E_UNSUPPORTED, "a rotor on a stretched mesh needs one cell width on the cells around it");
     AlmArgs& a = c->alm;
     std::memset(&a, 0, sizeof(a));
     for (int d = 0; d < 3; ++d) {
         int i0 = (int)std::ceil((lo[d] - gb.x0[d]) / gb.h[d] - 0.5);
         int i1 = (int)std::floor((hi[d] - gb.x0[d]) / gb.h[d] - 0.5);
-        // sampling cells of any point on the disc
-        const double slo = (d == 0 ? r->hub[0] : r->hub[d] - rmax), shi = (d == 0 ? r->hub[0] : r->hub[d] + rmax);
+        // sampling cells of any sampling position of the swept disc
+        const double slo = (d == 0 ? r->hub[0] : r->hub[d] - reach), shi = (d == 0 ? r->hub[0] : r->hub[d] + reach);
         const int s0 = (int)std::floor((slo - gb.x0[d]) / gb.h[d] - 0.5);
         const int s1 = (int)std::floor((shi - gb.x0[d]) / gb.h[d] - 0.5) + 1;
         if (std::min(i0, s0) < 0 || std::max(i1, s1) >= c->g.n[d])
@@ -791,6 +795,8 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
         a.box_n[d] = i1 - i0 + 1;
     }
     a.n_act = n;
+    a.line_n = line ? r->line_points : 1;
+    a.line_half = line ? r->line_half_length : 0.0;
     a.nb = r->n_blades;
     a.npb = r->n_per_blade;
     a.corr = r->u_inf_correction ? 1 : 0;
@@ -1073,9 +1079,11 @@ size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act) {
 }
 
 int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0, void* adj_ws,
-                size_t adj_ws_bytes) {
+                size_t adj_ws_bytes, int32_t flags) {
     if (!c) return GKS_E_INVALID_ARG;
     if (!w || !grad_s || !adj_ws) return fail(c, GKS_E_INVALID_ARG, "null argument");
+    if (flags & ~GKS_ADJ_EXACT_WENO) return fail(c, GKS_E_INVALID_ARG, "unknown adjoint flags");
+    const int exact = (flags & GKS_ADJ_EXACT_WENO) ? 1 : 0;
     if (c->cfg.precision != GKS_FP64) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs an FP64 context");
     if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a uniform mesh");
     if (c->cfg.order == 2) return fail(c, GKS_E_UNSUPPORTED, "the adjoint covers the high-order scheme only");
@@ -1142,7 +1150,7 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
             HIPCHK(c, launch_pad_to_int(B.mu1[v], B.lam_pre[v], dt * dt / 3.0, nullptr, 0.0, c->g, S));
             HIPCHK(c, launch_zero(B.acc[v], np, S));
         }
-        for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, c->qs), 2, S));
+        for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, c->qs, exact), 2, S));
         HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, S));
         for (int v = 0; v < 4; ++v) HIPCHK(c, launch_axpby(B.lam_star[v], B.acc[v], 1.0, nullptr, 0.0, np, S));
         // stage 1: seeds dt lam_pre + dt/2 lam* (of L) and dt^2/6 lam_pre + dt^2/8 lam* (of L_t) at Q^n
@@ -1151,7 +1159,7 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
             HIPCHK(c, launch_pad_to_int(B.mu1[v], B.lam_pre[v], dt * dt / 6.0, B.lam_star[v], dt * dt / 8.0, c->g, S));
             HIPCHK(c, launch_zero(B.acc[v], np, S));
         }
-        for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, qwork), 1, S));
+        for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, qwork, exact), 1, S));
         HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, S));
         // lam^n = lam_pre + lam* + J^T(...)
         for (int v = 0; v < 4; ++v) {

@@ -25,9 +25,18 @@ struct AlmArgs {
     double* out_phi;
     double* out_u;        // device, 3 n_act: sampled velocity
     int box_lo[3], box_n[3];
+    int line_n;            // line sampling: samples along the direction of motion (<= 1: point sampling)
+    double line_half;      // half-length of the sampling segment
     GridDesc g;
     DevState* st;
 };
+
+// Sampling positions of the line sampling of an actuator point (the NTNU rotor of Section 4.4): the
+// midpoints s_k = l ((2k + 1) / N - 1), k = 0 .. N - 1, of N equal parts of the segment [-l, l] along
+// the blade's direction of motion.
+__host__ __device__ inline double line_offset(const AlmArgs& a, int k) {
+    return a.line_half * ((double)(2 * k + 1) / (double)a.line_n - 1.0);
+}
 
 struct IbmArgs {
     int npts, ncell, iters;

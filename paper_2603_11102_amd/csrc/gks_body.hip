@@ -40,30 +40,43 @@ __global__ void __launch_bounds__(1024) alm_points_kernel(Field4<real> f, AlmArg
         rr = a.r[ip];
         const double X[3] = {a.hub[0], a.hub[1] + rr * cth, a.hub[2] + rr * sth};
         const double et[3] = {0.0, -sth, cth};
-        // trilinear sampling of U = (rho U)/rho at cell centres
-        int i0[3];
-        double w1[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double fc = (X[d] - a.g.x0[d]) / a.g.h[d] - 0.5;
-            const double fl = floor(fc);
-            i0[d] = (int)fl;
-            w1[d] = fc - fl;
-        }
+        // velocity U = (rho U)/rho at the point: trilinear interpolation of the cell-centre values
+        // (point sampling, Section 3.1), or the mean of such samples along the direction of motion
+        // (line sampling of the NTNU rotor, Section 4.4)
         double U[3] = {0.0, 0.0, 0.0};
+        const int ns = a.line_n > 1 ? a.line_n : 1;
+        for (int k = 0; k < ns; ++k) {
+            const double sk = ns > 1 ? line_offset(a, k) : 0.0;
+            const double Xs[3] = {X[0], X[1] + sk * et[1], X[2] + sk * et[2]};
+            int i0[3];
+            double w1[3];
 #pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
+            for (int d = 0; d < 3; ++d) {
+                const double fc = (Xs[d] - a.g.x0[d]) / a.g.h[d] - 0.5;
+                const double fl = floor(fc);
+                i0[d] = (int)fl;
+                w1[d] = fc - fl;
+            }
+            double Us[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
+            for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) *
-                                     (dz ? w1[2] : 1.0 - w1[2]);
-                    const long long q = pidx(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
-                    const double rho = a.rho_ref + (double)f.v[0][q];
+                for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) U[c] += w * ((double)f.v[1 + c][q] / rho);
-                }
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) *
+                                         (dz ? w1[2] : 1.0 - w1[2]);
+                        const long long q = pidx(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+                        const double rho = a.rho_ref + (double)f.v[0][q];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) Us[c] += w * ((double)f.v[1 + c][q] / rho);
+                    }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) U[c] += Us[c];
+        }
+        if (ns > 1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) U[c] /= (double)ns;
         double ux = U[0];
         double ut = U[1] * et[1] + U[2] * et[2];
         const double om = a.omega;

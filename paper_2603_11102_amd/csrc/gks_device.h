@@ -441,6 +441,38 @@ __device__ __forceinline__ double weno_eff(int side, const double w[3], int r) {
     return w[0] * sub_coef(side, 0, r) + w[1] * sub_coef(side, 1, r) + w[2] * sub_coef(side, 2, r);
 }
 
+// Jacobian row dv/dq_r (r = 0..4 over the stencil -2..2) of a WENO-JS evaluation on `side` (as in
+// sub_coef) with the nonlinear weights differentiated too. With e_k = 4 (eps + beta_k) the normalised
+// weights are omega_k = (gamma_k / e_k^2) / sum_j (gamma_j / e_j^2), so
+//   dv/dq_r = sum_k omega_k c_k[r] - 2 sum_k omega_k (v_k - v) (de_k/dq_r) / e_k,
+// v_k the sub-stencil values and c_k[r] their coefficients. w: the weights, v: the value.
+__device__ __forceinline__ void weno_jacobian(int side, const double q[5], double eps, const double w[3], double v,
+                                              double J[5]) {
+    const double c133 = 13.0 / 3.0, e4 = 4.0 * eps;
+    // 4 beta_k = (13/3) a_k^2 + b_k^2 with a_k, b_k linear in the sub-stencil's cells
+    const double a0 = q[0] - 2.0 * q[1] + q[2], b0 = q[0] - 4.0 * q[1] + 3.0 * q[2];
+    const double a1 = q[1] - 2.0 * q[2] + q[3], b1 = q[1] - q[3];
+    const double a2 = q[2] - 2.0 * q[3] + q[4], b2 = 3.0 * q[2] - 4.0 * q[3] + q[4];
+    const double e[3] = {e4 + c133 * a0 * a0 + b0 * b0, e4 + c133 * a1 * a1 + b1 * b1, e4 + c133 * a2 * a2 + b2 * b2};
+    double g[3];
+    for (int k = 0; k < 3; ++k) {
+        double vk = 0.0;
+        for (int l = 0; l < 3; ++l) vk += sub_coef(side, k, k + l) * q[k + l];
+        g[k] = -2.0 * w[k] * (vk - v) / e[k];
+    }
+    // de_k/dq over the sub-stencil's three cells: (26/3) a (1, -2, 1) + 2 b (db/dq)
+    const double t0 = 26.0 / 3.0 * a0, t1 = 26.0 / 3.0 * a1, t2 = 26.0 / 3.0 * a2;
+    const double d0[3] = {t0 + 2.0 * b0, -2.0 * t0 - 8.0 * b0, t0 + 6.0 * b0};
+    const double d1[3] = {t1 + 2.0 * b1, -2.0 * t1, t1 - 2.0 * b1};
+    const double d2[3] = {t2 + 6.0 * b2, -2.0 * t2 - 8.0 * b2, t2 + 2.0 * b2};
+    for (int r = 0; r < 5; ++r) J[r] = weno_eff(side, w, r);
+    for (int l = 0; l < 3; ++l) {
+        J[l] += g[0] * d0[l];
+        J[1 + l] += g[1] * d1[l];
+        J[2 + l] += g[2] * d2[l];
+    }
+}
+
 // Quartic Gauss value (deriv = 0) or derivative (deriv = 1) coefficient of stencil cell r at s.
 __device__ __forceinline__ double quartic_coef(int deriv, int s, int r) {
     const double t = GKS_SQRT3;

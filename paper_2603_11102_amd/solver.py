@@ -142,6 +142,8 @@ class GksSolver:
         r.u_inf_correction = 1 if rotor.u_inf_correction else 0
         r.tip_correction = 1 if getattr(rotor, "tip_correction", False) else 0
         r.scale = C.c_void_p(_ptr(self.scale))
+        r.line_points = int(getattr(rotor, "line_points", 1) or 1)
+        r.line_half_length = float(getattr(rotor, "line_half_length", 0.0) or 0.0)
         L.check(self.lib, self.ctx, self.lib.gks_set_actuators(self.ctx, C.byref(r)))
         self.n_act = n_act
 
@@ -240,9 +242,10 @@ class GksSolver:
         ptr = (self._ckpt.data_ptr() + 255) // 256 * 256
         L.check(self.lib, self.ctx, self.lib.gks_set_checkpoints(self.ctx, C.c_void_p(ptr), int(capacity)))
 
-    def adjoint(self, nsteps: int, w, want_field: bool = False):
+    def adjoint(self, nsteps: int, w, want_field: bool = False, exact: bool = False):
         """Gradient of J = w0 mean P + w1 mean T over the checkpointed window with respect to the force
-        scalings (device float64 [n_act]); optionally dJ/dQ^0 as [4, nz, ny, nx]."""
+        scalings (device float64 [n_act]); optionally dJ/dQ^0 as [4, nz, ny, nx]. The WENO nonlinear
+        weights are frozen unless ``exact``."""
         nbytes = self.lib.gks_adjoint_workspace_bytes(C.byref(self.c_cfg), self.n_act)
         if getattr(self, "_adj_ws", None) is None or self._adj_ws.numel() < nbytes + 256:
             self._adj_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -254,7 +257,7 @@ class GksSolver:
         wv = (C.c_double * 2)(float(w[0]), float(w[1]))
         rc = self.lib.gks_adjoint(self.ctx, int(nsteps), wv, C.c_void_p(grad_s.data_ptr()),
                                   C.c_void_p(gq.data_ptr()) if gq is not None else None,
-                                  C.c_void_p(ptr), C.c_size_t(nbytes))
+                                  C.c_void_p(ptr), C.c_size_t(nbytes), L.GKS_ADJ_EXACT_WENO if exact else 0)
         L.check(self.lib, self.ctx, rc)
         return grad_s, gq
 

@@ -50,6 +50,8 @@ class RotorSpec:
     cd2: float = 0.02
     u_inf_correction: bool = True
     tip_correction: bool = False        # Shen tip correction of the NTNU case (Section 4.4)
+    line_points: int = 1                # line sampling of the NTNU case: samples along e_theta (1: point)
+    line_half_length: float = 0.0       # half-length of the sampling segment
     scale: Optional[np.ndarray] = None  # per actuator point, n_blades * n_per_blade
 
     @property
@@ -338,6 +340,16 @@ def tanh_faces(n: int, b: float = 2.0) -> np.ndarray:
     y = np.tanh(b * (eta / (1.5 * math.pi) - 1.0)) / math.tanh(b)
     y[0], y[-1] = -1.0, 1.0
     return y
+
+
+def block_faces(n_lo, n_block, n_hi, h, ratio, start):
+    """Faces of a locally refined axis (the refined block around the turbines of Section 4.3.3):
+    n_block cells of width h beginning at `start`, with n_lo cells below and n_hi above whose widths grow
+    by `ratio` per cell away from the block."""
+    lo = h * ratio ** np.arange(n_lo, 0, -1)
+    hi = h * ratio ** np.arange(1, n_hi + 1)
+    w = np.concatenate([lo, np.full(n_block, h), hi])
+    return (start - lo.sum()) + np.concatenate([[0.0], np.cumsum(w)])
 
 
 def _channel_tanh(grid, seed):

@@ -107,3 +107,68 @@ def test_bodies_need_one_width_around_them():
     with pytest.raises(GksError) as e:
         GksSolver(cfg.with_(faces=(None, None, zf)), precision="fp64")
     assert e.value.code == GKS_E_UNSUPPORTED
+
+
+def _perturbed(cfg, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    q = cfg.q0.copy()
+    q[1:] += amp * rng.uniform(-1, 1, size=q[1:].shape)
+    q[0] += 0.1 * amp * rng.uniform(-1, 1, size=q[0].shape)
+    return cfg.with_(q0=q)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_stretched_x_with_inflow_and_outflow_vs_oracle(precision):
+    # the stretched instance of the x pass (its normal spacings from the per-axis arrays) under the
+    # inflow and outflow boundaries of the rotor workloads
+    from synth.cases import block_faces
+    cfg = make_case("alm", grid=(48, 24, 24)).with_(rotor=None)
+    xf = block_faces(8, 12, 28, 0.125, 1.06, 1.0)
+    cfg = _perturbed(cfg.with_(x0=float(xf[0]), lx=float(xf[-1] - xf[0]), faces=(xf, None, None)), 21)
+    print_case("stretched-x-inflow", precision=precision, grid=(48, 24, 24))
+    s, _ = run_gpu(cfg, precision, 2)
+    o, _ = run_oracle(cfg, 2)
+    if precision == "fp64":
+        err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+        assert max(err) < 1e-12, err
+    else:
+        err = rel_l2(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+        assert max(err) < 1e-5, err
+
+
+def _refined_block_case():
+    """The locally refined grid of Section 4.3.3: the rotor in a uniform block of cells with dx = 0.125
+    along x and dy = dz = 0.1 across, the cells growing outside the block along all three axes; inflow
+    and outflow in x, slip walls in y and z."""
+    from synth.cases import block_faces
+    q = np.zeros((4, 32, 32, 48))
+    q[0], q[1] = 1.0, 1.0
+    cfg = make_case("alm", grid=(48, 24, 24)).with_(nx=48, ny=32, nz=32, q0=q)
+    xf = block_faces(8, 16, 24, 0.125, 1.08, 0.5)
+    yf = block_faces(2, 28, 2, 0.1, 1.2, 0.1)
+    zf = block_faces(2, 28, 2, 0.1, 1.2, 0.1)
+    cfg = cfg.with_(x0=float(xf[0]), lx=float(xf[-1] - xf[0]), y0=float(yf[0]), ly=float(yf[-1] - yf[0]),
+                    z0=float(zf[0]), lz=float(zf[-1] - zf[0]), faces=(xf, yf, zf),
+                    bc=("inflow", "outflow", "slip", "slip", "slip", "slip"))
+    from dataclasses import replace
+    cfg = cfg.with_(rotor=replace(cfg.rotor, eps=0.25, theta0=0.2))
+    return _perturbed(cfg, 23)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rotor_in_refined_block_three_stretched_axes_vs_oracle(precision):
+    cfg = _refined_block_case()
+    print_case("stretched-xyz-rotor", precision=precision, grid=(48, 32, 32))
+    s, gouts = run_gpu(cfg, precision, 2)
+    o, oouts = run_oracle(cfg, 2)
+    if precision == "fp64":
+        err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+        assert max(err) < 1e-12, err
+        tol = 1e-11
+    else:
+        err = rel_l2(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+        assert max(err) < 1e-5, err
+        tol = 1e-5
+    for g, b in zip(gouts, oouts):
+        for k in ("thrust", "power"):
+            assert abs(g[k] - float(b["alm"][k])) < tol * abs(float(b["alm"][k])), k
