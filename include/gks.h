@@ -221,12 +221,13 @@ int gks_reset_window(gks_ctx* ctx);
  * GKS_E_HIP if the clear cannot be enqueued. */
 int gks_field_changed(gks_ctx* ctx);
 
-/* Bytes of device memory one checkpoint slot needs (one field, the time and dt of a step). */
+/* Bytes of device memory one checkpoint slot needs: three fields of a step (Q^n, the S2O4 intermediate
+ * state Q* and the field before the body forces of Section 3.3) and its time. */
 size_t gks_checkpoint_slot_bytes(const gks_config* cfg);
 
-/* Register a DEVICE buffer of `capacity` checkpoint slots (or NULL to stop). While registered, every
- * gks_step stores Q^n (before the step) in slot (window step index) and the window sums are reset.
- * Used by gks_adjoint to recompute each step. */
+/* Register a DEVICE buffer of `capacity` checkpoint slots (or NULL to stop); the window sums are reset.
+ * While registered, every gks_step stores in slot (window step index) Q^n (before the step), Q* and the
+ * field before the body forces. Used by gks_adjoint to run each step backwards. */
 int gks_set_checkpoints(gks_ctx* ctx, void* buffer, int32_t capacity);
 
 /* Bytes of device scratch gks_adjoint needs. */

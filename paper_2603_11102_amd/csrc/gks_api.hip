@@ -550,16 +550,17 @@ int steps(gks_ctx* c, int nsteps) {
     const size_t field_bytes = (size_t)c->g.n_padded * sizeof(real);
     const int cat1[3] = {GKS_TIMER_S1X, GKS_TIMER_S1Y, GKS_TIMER_S1Z};
     const int cat2[3] = {GKS_TIMER_S2X, GKS_TIMER_S2Y, GKS_TIMER_S2Z};
+    const size_t fb = (field_bytes + 255) & ~size_t(255);
     for (int s = 0; s < nsteps; ++s) {
         int tp;
+        // checkpoint slot of this step: Q^n, Q* and the field before the body forces, then t
+        char* ck = nullptr;
         if (c->ckpt && c->ckpt_n < c->ckpt_cap) {
             tp = tbeg(c, GKS_TIMER_OTHER);
             const size_t slot = gks_checkpoint_slot_bytes(&c->cfg);
-            char* dst = c->ckpt + (size_t)c->ckpt_n * slot;
-            for (int v = 0; v < 4; ++v)
-                HIPCHK(c, launch_copy_field(c->q[v], dst + v * ((field_bytes + 255) & ~size_t(255)), field_bytes,
-                                            c->stream));
-            HIPCHK(c, launch_copy_field(&c->st->t, dst + slot - 256, sizeof(double), c->stream));
+            ck = c->ckpt + (size_t)c->ckpt_n * slot;
+            for (int v = 0; v < 4; ++v) HIPCHK(c, launch_copy_field(c->q[v], ck + v * fb, field_bytes, c->stream));
+            HIPCHK(c, launch_copy_field(&c->st->t, ck + slot - 256, sizeof(double), c->stream));
             tend(c, tp);
             c->ckpt_n++;
         }
@@ -578,6 +579,11 @@ int steps(gks_ctx* c, int nsteps) {
                                         : launch_face<real>(face_args<real>(c, d, 1, c->q), 1, c->stream));
             tend(c, tp);
         }
+        if (ck) {
+            tp = tbeg(c, GKS_TIMER_OTHER);
+            for (int v = 0; v < 4; ++v) HIPCHK(c, launch_copy_field(c->qs[v], ck + (4 + v) * fb, field_bytes, c->stream));
+            tend(c, tp);
+        }
         tp = tbeg(c, GKS_TIMER_GHOST);
         HIPCHK(c, launch_ghost_transpose<real>(field<real>(c->qs), field<real>(c->qt), c->g, c->cfg.bc, c->cfg.u_in,
                                                c->c, c->cfg.rho_ref, c->stream));
@@ -586,6 +592,11 @@ int steps(gks_ctx* c, int nsteps) {
             tp = tbeg(c, cat2[d]);
             HIPCHK(c, c->cfg.order == 2 ? launch_face2<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream)
                                         : launch_face<real>(face_args<real>(c, d, 2, c->qs), 2, c->stream));
+            tend(c, tp);
+        }
+        if (ck) {
+            tp = tbeg(c, GKS_TIMER_OTHER);
+            for (int v = 0; v < 4; ++v) HIPCHK(c, launch_copy_field(c->q[v], ck + (8 + v) * fb, field_bytes, c->stream));
             tend(c, tp);
         }
         if (c->has_rotor) {
@@ -635,7 +646,7 @@ size_t gks_checkpoint_slot_bytes(const gks_config* cfg) {
     if (!validate(cfg).empty()) return 0;
     const size_t np = (size_t)(cfg->nx + 6) * (cfg->ny + 6) * (cfg->nz + 6);
     const size_t fb = ((np * elem_size(cfg)) + 255) & ~size_t(255);
-    return 4 * fb + 256;
+    return 12 * fb + 256;  // Q^n, Q* and the field before the body forces; t
 }
 
 int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_acc, void* workspace,
@@ -1115,19 +1126,20 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
         qpre[v] = B.qpre[v];
     }
     for (int n = nsteps - 1; n >= 0; --n) {
-        // recompute step n from its checkpoint
+        // step n from its checkpoint: Q^n, Q* and the field before the body forces (stored by the
+        // forward, bitwise what a recompute gives), and t
         const char* src = c->ckpt + (size_t)n * slot;
-        for (int v = 0; v < 4; ++v) HIPCHK(c, launch_copy_field(src + v * fb, B.qwork[v], (size_t)np * 8, S));
+        for (int v = 0; v < 4; ++v) {
+            HIPCHK(c, launch_copy_field(src + v * fb, B.qwork[v], (size_t)np * 8, S));
+            HIPCHK(c, launch_copy_field(src + (4 + v) * fb, c->qs[v], (size_t)np * 8, S));
+            HIPCHK(c, launch_copy_field(src + (8 + v) * fb, B.qpre[v], (size_t)np * 8, S));
+        }
         HIPCHK(c, launch_copy_field(src + slot - 256, &c->st->t, sizeof(double), S));
         HIPCHK(c, launch_dt(c->st, nullptr, 0, 0.0, c->hmin, c->c, dt, S));
         int rc = ghost_all<double>(c, qwork);
         if (rc) return rc;
-        for (int d = 0; d < 3; ++d)
-            HIPCHK(c, launch_face<double>(face_args_buf<double>(c, d, 1, qwork, c->qs, c->qa, qwork), 1, S));
         rc = ghost_all<double>(c, c->qs);
         if (rc) return rc;
-        for (int d = 0; d < 3; ++d)
-            HIPCHK(c, launch_face<double>(face_args_buf<double>(c, d, 2, c->qs, qpre, c->qa, nullptr), 2, S));
         HIPCHK(c, launch_alm_points_only(field<double>(qpre), c->alm, S));
         // actuator line: lam_pre = lam + (sampling path); gradient in s
         for (int v = 0; v < 4; ++v) HIPCHK(c, launch_axpby(B.lam_pre[v], B.lam[v], 1.0, nullptr, 0.0, np, S));
