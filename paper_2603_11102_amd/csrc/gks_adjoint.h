@@ -25,7 +25,7 @@ struct AdjFaceArgs {
     const double* mu0[4];   // seed of L (interior, local order), stage 1 only
     const double* mu1[4];   // seed of L_t
     double* gpbar;          // [80][nface]
-    double* w_t2;           // [32 NW][nface], NW = 3 frozen weights or 5 Jacobian entries per evaluation
+    double* w_t2;           // [32 NW][nface], NW = 2 frozen weights (w0, w2) or 5 Jacobian entries per evaluation
     double* w_t1;           // [16 NW][nt1pos]
     double* w_n;            // [8 NW][nnpos]
     double* t1bar;          // [40][nt1pos]

@@ -27,13 +27,15 @@ __device__ __forceinline__ long long n_ix(const AdjFaceArgs& a, int f, int jx, i
 }
 
 // Coefficient of stencil cell r in a WENO evaluation on `side` from its stored coefficients: the frozen
-// weights expanded over the sub-stencils, or (EXACT) the stored Jacobian entry.
+// weights (stored as w0 and w2; w1 = 1 - w0 - w2) expanded over the sub-stencils, or (EXACT) the stored
+// Jacobian entry.
 template <bool EXACT>
 __device__ __forceinline__ double wcoef(int side, const double* c, int r) {
     if constexpr (EXACT) {
         return c[r];
     } else {
-        return weno_eff(side, c, r);
+        const double w[3] = {c[0], 1.0 - c[0] - c[1], c[1]};
+        return weno_eff(side, w, r);
     }
 }
 
@@ -50,7 +52,7 @@ template <int STAGE, bool EXACT>
 __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(const AdjFaceArgs a) {
     constexpr bool NEED_F0 = (STAGE == 1);
     constexpr int T2 = FaceTile<double>::T2, X2 = T2 + 4, NTH = FaceTile<double>::THREADS;
-    constexpr int NW = EXACT ? 5 : 3;
+    constexpr int NW = EXACT ? 5 : 2;
     static_assert(EXT1 * X2 <= NTH && 2 * TILE1 * T2 == NTH && TILE1 * X2 <= NTH, "thread roles");
     __shared__ double s_nrm[4][X2][EXT1];
     __shared__ double s_t1[5][X2][TILE1][2];
@@ -88,7 +90,9 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
         if constexpr (EXACT) {
             weno_jacobian(side, q, eps, w, v, out);
         } else {
-            for (int kk = 0; kk < 3; ++kk) out[kk] = w[kk];
+            // the weights sum to one: w1 is rebuilt from w0 and w2 where they are used
+            out[0] = w[0];
+            out[1] = w[2];
         }
     };
 
@@ -272,68 +276,74 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
 // ------------------------------------------------------------------------------------------------
 // pass B: transpose of the t2 sweep -> adjoints of the t1 line values (q^L_m, q^R_m, D_m, Ct1_m, C_m)
 // ------------------------------------------------------------------------------------------------
-constexpr int T2_STRIP = 4;  // consecutive t2 outputs per thread in pass B
+constexpr int T2_CHUNK = 32;  // consecutive t2 outputs per thread in pass B
 
 template <bool EXACT>
 __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
-    constexpr int NW = EXACT ? 5 : 3;
-    // one thread per (t1 line position, variable, Gauss line m, strip of T2_STRIP consecutive t2
+    constexpr int NW = EXACT ? 5 : 2;
+    // one thread per (t1 line position, variable, Gauss line m, chunk of T2_CHUNK consecutive t2
     // positions incl. halo, face); the t1 position is the fastest index so that a wave reads
-    // contiguous runs of every plane. Each face value loaded serves every output of the strip whose
-    // 5-point stencil holds it; every output sums its faces in ascending t2 order, Gauss point n inner.
-    const int nstrip = (a.n_t2 + 4 + T2_STRIP - 1) / T2_STRIP;
-    const long long total = (long long)(a.n_n + 1) * nstrip * 8 * a.n_t1;
+    // contiguous runs of every plane. The thread walks the faces of its chunk in ascending t2 order and
+    // loads each once: face k adds its terms to the five outputs kx = k-2 .. k+2 it reaches (slot r =
+    // kx - k + 2 of a ring), and output k-2 is stored after face k. Every output sums its faces in
+    // ascending t2 order, Gauss point n inner.
+    const int nout = a.n_t2 + 4;  // outputs kx = -2 .. n_t2 + 1
+    const int nchunk = (nout + T2_CHUNK - 1) / T2_CHUNK;
+    const long long total = (long long)(a.n_n + 1) * nchunk * 8 * a.n_t1;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int j = (int)(t % a.n_t1);
     long long r_ = t / a.n_t1;
     const int vm = (int)(r_ % 8);  // v * 2 + m
     r_ /= 8;
-    const int kx0 = (int)(r_ % nstrip) * T2_STRIP - 2;
-    const int f = (int)(r_ / nstrip);
-    double bar[T2_STRIP][5];
+    const int kx_lo = (int)(r_ % nchunk) * T2_CHUNK - 2;
+    const int kx_hi = min(kx_lo + T2_CHUNK, a.n_t2 + 2);
+    const int f = (int)(r_ / nchunk);
+    double acc[5][5];
 #pragma unroll
-    for (int o = 0; o < T2_STRIP; ++o)
+    for (int r = 0; r < 5; ++r)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) bar[o][q] = 0.0;
+        for (int q = 0; q < 5; ++q) acc[r][q] = 0.0;
+    for (int k = kx_lo - 2; k < kx_hi + 2; ++k) {
+        if (k >= 0 && k < a.n_t2) {
+            const long long fi = face_ix(a, f, j, k);
 #pragma unroll
-    for (int dk = 0; dk < T2_STRIP + 4; ++dk) {  // faces k = kx0 - 2 .. kx0 + T2_STRIP + 1
-        const int k = kx0 - 2 + dk;
-        if (k < 0 || k >= a.n_t2) continue;
-        const long long fi = face_ix(a, f, j, k);
+            for (int n = 0; n < 2; ++n) {
+                const int side = n == 0 ? 2 : 3;
+                const int sg = n == 0 ? -1 : 1;
+                const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
+                double wL[NW], wR[NW], gv[5];
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
-            const int side = n == 0 ? 2 : 3;
-            const int s = n == 0 ? -1 : 1;
-            const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
-            double wL[NW], wR[NW], gv[5];
+                for (int kk = 0; kk < NW; ++kk) {
+                    wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * NW + kk) * a.nface + fi];
+                    wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * NW + kk) * a.nface + fi];
+                }
 #pragma unroll
-            for (int kk = 0; kk < NW; ++kk) {
-                wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * NW + kk) * a.nface + fi];
-                wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * NW + kk) * a.nface + fi];
-            }
+                for (int q = 0; q < 5; ++q) gv[q] = a.gpbar[gbase + q * a.nface];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) gv[q] = a.gpbar[gbase + q * a.nface];
-#pragma unroll
-            for (int o = 0; o < T2_STRIP; ++o) {
-                const int r = o - dk + 4;  // stencil slot of face k for output kx0 + o (compile time)
-                if (r < 0 || r > 4) continue;
-                const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h2;
-                bar[o][0] += wcoef<EXACT>(side, wL, r) * gv[0];
-                bar[o][1] += wcoef<EXACT>(side, wR, r) * gv[1];
-                bar[o][2] += cv * gv[2];
-                bar[o][3] += cv * gv[3];
-                bar[o][4] += cd * gv[4];
+                for (int r = 0; r < 5; ++r) {
+                    const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h2;
+                    acc[r][0] += wcoef<EXACT>(side, wL, r) * gv[0];
+                    acc[r][1] += wcoef<EXACT>(side, wR, r) * gv[1];
+                    acc[r][2] += cv * gv[2];
+                    acc[r][3] += cv * gv[3];
+                    acc[r][4] += cd * gv[4];
+                }
             }
         }
-    }
+        // output kx = k - 2 has all its faces now
+        const int kx = k - 2;
+        if (kx >= kx_lo && kx < kx_hi) {
+            const long long p = t1_ix(a, f, j, kx);
 #pragma unroll
-    for (int o = 0; o < T2_STRIP; ++o) {
-        const int kx = kx0 + o;
-        if (kx > a.n_t2 + 1) break;
-        const long long p = t1_ix(a, f, j, kx);
+            for (int q = 0; q < 5; ++q) a.t1bar[(long long)(vm * 5 + q) * a.nt1pos + p] = acc[0][q];
+        }
 #pragma unroll
-        for (int q = 0; q < 5; ++q) a.t1bar[(long long)(vm * 5 + q) * a.nt1pos + p] = bar[o][q];
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[r][q] = acc[r + 1][q];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[4][q] = 0.0;
     }
 }
 
@@ -341,11 +351,91 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
 // pass C: transpose of the t1 sweep and of C = (q^L + q^R)/2 -> adjoints of q^L, q^R, D per face
 // position (tangential halo included)
 // ------------------------------------------------------------------------------------------------
+constexpr int C_THREADS = 128;  // threads per workgroup of pass C
+constexpr int C_SEG = 132;      // outputs of one workgroup along t1 (a whole row when n_t1 = 128)
+
 template <bool EXACT>
-__global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
-    constexpr int NW = EXACT ? 5 : 3;
-    // one thread per (t1 position incl. halo, variable, t2 position incl. halo, face)
-    const long long total = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 4 * (a.n_t1 + 4);
+__global__ void __launch_bounds__(C_THREADS) adj_t1_kernel(const AdjFaceArgs a) {
+    constexpr int NW = EXACT ? 5 : 2;
+    constexpr int NV = 10 + 4 * NW;  // per t1 position: t1bar[m][q] and the weights [side][m][kk]
+    constexpr int NP = C_SEG + 4;    // t1 positions a segment reads
+    // one workgroup per (segment of C_SEG t1 outputs incl. halo, variable, t2 position incl. halo, face):
+    // the t1 line values and weights of the segment's positions are staged in LDS, each loaded once,
+    // and every output gathers its five positions from there (ascending t1, Gauss line m inner)
+    __shared__ double s_v[NV][NP];
+    const int nseg = (a.n_t1 + 4 + C_SEG - 1) / C_SEG;
+    long long r_ = blockIdx.x;
+    const int seg = (int)(r_ % nseg);
+    r_ /= nseg;
+    const int v = (int)(r_ % 4);
+    r_ /= 4;
+    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
+    const int f = (int)(r_ / (a.n_t2 + 4));
+    const int seg0 = -2 + seg * C_SEG;
+    for (int l = threadIdx.x; l < NP; l += C_THREADS) {
+        const int j = seg0 - 2 + l;
+        const bool in = j >= 0 && j < a.n_t1;
+        const long long p = in ? t1_ix(a, f, j, kx) : 0;
+        for (int m = 0; m < 2; ++m) {
+            for (int q = 0; q < 5; ++q)
+                s_v[m * 5 + q][l] = in ? a.t1bar[(long long)((v * 2 + m) * 5 + q) * a.nt1pos + p] : 0.0;
+            for (int side = 0; side < 2; ++side)
+                for (int kk = 0; kk < NW; ++kk)
+                    s_v[10 + (side * 2 + m) * NW + kk][l] =
+                        in ? a.w_t1[(((v * 2 + side) * 2 + m) * NW + kk) * a.nt1pos + p] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < C_SEG; o += C_THREADS) {
+        const int jx = seg0 + o;
+        if (jx >= a.n_t1 + 2) break;
+        double bar[3] = {0.0, 0.0, 0.0}, Cb = 0.0;
+        // positions j = jx - 2 .. jx + 2 in ascending order (stencil slot r = jx - j + 2 descending)
+#pragma unroll
+        for (int r = 4; r >= 0; --r) {
+            const int j = jx - r + 2;
+            if (j < 0 || j >= a.n_t1) continue;
+            const int l = j - seg0 + 2;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int side = m == 0 ? 2 : 3;
+                const int sg = m == 0 ? -1 : 1;
+                const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h1;
+                double wL[NW], wR[NW];
+#pragma unroll
+                for (int kk = 0; kk < NW; ++kk) {
+                    wL[kk] = s_v[10 + (0 * 2 + m) * NW + kk][l];
+                    wR[kk] = s_v[10 + (1 * 2 + m) * NW + kk][l];
+                }
+                bar[0] += wcoef<EXACT>(side, wL, r) * s_v[m * 5 + 0][l];
+                bar[1] += wcoef<EXACT>(side, wR, r) * s_v[m * 5 + 1][l];
+                bar[2] += cv * s_v[m * 5 + 2][l];
+                Cb += cd * s_v[m * 5 + 3][l];
+                Cb += cv * s_v[m * 5 + 4][l];
+            }
+        }
+        const long long p = n_ix(a, f, jx, kx);
+        a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[0] + 0.5 * Cb;
+        a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[1] + 0.5 * Cb;
+        a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[2];
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// pass D: transpose of the normal reconstruction -> padded cell adjoint (accumulated)
+// ------------------------------------------------------------------------------------------------
+constexpr int N_CHUNK = 32;  // consecutive cells along the normal per thread in pass D
+
+template <bool EXACT>
+__global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
+    constexpr int NW = EXACT ? 5 : 2;
+    // one thread per (tangential position incl. halo, variable, chunk of N_CHUNK cells along the
+    // normal); the t1 position is the fastest index. The thread walks its cells in order with the six
+    // faces f = i-2 .. i+3 that reach cell i in registers (slot s holds face i-2+s), loading each face
+    // once, and sums per cell the q^L terms, then the q^R terms, then the D terms, each in ascending f.
+    const int ncell = a.n_n + 6;  // padded cells i = -3 .. n_n + 2
+    const int nchunk = (ncell + N_CHUNK - 1) / N_CHUNK;
+    const long long total = (long long)nchunk * 4 * (a.n_t2 + 4) * (a.n_t1 + 4);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int jx = (int)(t % (a.n_t1 + 4)) - 2;
@@ -353,77 +443,54 @@ __global__ void __launch_bounds__(256) adj_t1_kernel(const AdjFaceArgs a) {
     const int v = (int)(r_ % 4);
     r_ /= 4;
     const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
-    const int f = (int)(r_ / (a.n_t2 + 4));
-    double bar[3] = {0.0, 0.0, 0.0}, Cb = 0.0;
-    for (int j = max(0, jx - 2); j <= min(a.n_t1 - 1, jx + 2); ++j) {
-        const int r = jx - j + 2;
-        const long long p = t1_ix(a, f, j, kx);
-        for (int m = 0; m < 2; ++m) {
-            const int side = m == 0 ? 2 : 3;
-            const int s = m == 0 ? -1 : 1;
-            const double cv = quartic_coef(0, s, r), cd = quartic_coef(1, s, r) * a.inv_h1;
-            const long long tb = (long long)((v * 2 + m) * 5) * a.nt1pos + p;
-            double wL[NW], wR[NW];
-            for (int kk = 0; kk < NW; ++kk) {
-                wL[kk] = a.w_t1[(((v * 2 + 0) * 2 + m) * NW + kk) * a.nt1pos + p];
-                wR[kk] = a.w_t1[(((v * 2 + 1) * 2 + m) * NW + kk) * a.nt1pos + p];
-            }
-            bar[0] += wcoef<EXACT>(side, wL, r) * a.t1bar[tb];
-            bar[1] += wcoef<EXACT>(side, wR, r) * a.t1bar[tb + a.nt1pos];
-            bar[2] += cv * a.t1bar[tb + 2 * a.nt1pos];
-            Cb += cd * a.t1bar[tb + 3 * a.nt1pos];
-            Cb += cv * a.t1bar[tb + 4 * a.nt1pos];
+    const int c = (int)(r_ / (a.n_t2 + 4));
+    const int i_lo = -3 + c * N_CHUNK, i_hi = min(i_lo + N_CHUNK, a.n_n + 3);
+    double wl[6][NW], wr[6][NW], fb[6][3];
+    bool ok[6];
+    auto load = [&](int s, int f) {
+        ok[s] = f >= 0 && f <= a.n_n;
+        const long long p = ok[s] ? n_ix(a, f, jx, kx) : 0;
+#pragma unroll
+        for (int kk = 0; kk < NW; ++kk) {
+            wl[s][kk] = ok[s] ? a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p] : 0.0;
+            wr[s][kk] = ok[s] ? a.w_n[((v * 2 + 1) * NW + kk) * a.nnpos + p] : 0.0;
         }
-    }
-    const long long p = n_ix(a, f, jx, kx);
-    a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[0] + 0.5 * Cb;
-    a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[1] + 0.5 * Cb;
-    a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[2];
-}
-
-// ------------------------------------------------------------------------------------------------
-// pass D: transpose of the normal reconstruction -> padded cell adjoint (accumulated)
-// ------------------------------------------------------------------------------------------------
-template <bool EXACT>
-__global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
-    constexpr int NW = EXACT ? 5 : 3;
-    const long long total = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int jx = (int)(t % (a.n_t1 + 4)) - 2;
-    long long r_ = t / (a.n_t1 + 4);
-    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
-    const int i = (int)(r_ / (a.n_t2 + 4)) - 3;
-    double bar[4] = {0, 0, 0, 0};
-    // q^L(f) = sum_r W^L_f[r] Q(f-3+r)
-    for (int f = max(0, i - 1); f <= min(a.n_n, i + 3); ++f) {
-        const int r = i - f + 3;
-        const long long p = n_ix(a, f, jx, kx);
-        for (int v = 0; v < 4; ++v) {
-            double w[NW];
-            for (int kk = 0; kk < NW; ++kk) w[kk] = a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p];
-            bar[v] += wcoef<EXACT>(0, w, r) * a.fabar[(long long)(v * 3 + 0) * a.nnpos + p];
-        }
-    }
-    // q^R(f) = sum_r W^R_f[r] Q(f-2+r)
-    for (int f = max(0, i - 2); f <= min(a.n_n, i + 2); ++f) {
-        const int r = i - f + 2;
-        const long long p = n_ix(a, f, jx, kx);
-        for (int v = 0; v < 4; ++v) {
-            double w[NW];
-            for (int kk = 0; kk < NW; ++kk) w[kk] = a.w_n[((v * 2 + 1) * NW + kk) * a.nnpos + p];
-            bar[v] += wcoef<EXACT>(1, w, r) * a.fabar[(long long)(v * 3 + 1) * a.nnpos + p];
-        }
-    }
-    // D(f) = (Q(f-2) - 15 Q(f-1) + 15 Q(f) - Q(f+1)) / (12 h)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) fb[s][q] = ok[s] ? a.fabar[(long long)(v * 3 + q) * a.nnpos + p] : 0.0;
+    };
+#pragma unroll
+    for (int s = 0; s < 6; ++s) load(s, i_lo - 2 + s);
     const double cD[4] = {1.0 / 12.0, -15.0 / 12.0, 15.0 / 12.0, -1.0 / 12.0};
-    for (int f = max(0, i - 1); f <= min(a.n_n, i + 2); ++f) {
-        const int r = i - f + 2;
-        const long long p = n_ix(a, f, jx, kx);
-        for (int v = 0; v < 4; ++v) bar[v] += cD[r] * a.inv_hn * a.fabar[(long long)(v * 3 + 2) * a.nnpos + p];
+    for (int i = i_lo; i < i_hi; ++i) {
+        double bar = 0.0;
+        // q^L(f) = sum_r W^L_f[r] Q(f-3+r): faces i-1 .. i+3 (slots 1..5), r = 5 - s
+#pragma unroll
+        for (int s = 1; s <= 5; ++s)
+            if (ok[s]) bar += wcoef<EXACT>(0, wl[s], 5 - s) * fb[s][0];
+        // q^R(f) = sum_r W^R_f[r] Q(f-2+r): faces i-2 .. i+2 (slots 0..4), r = 4 - s
+#pragma unroll
+        for (int s = 0; s <= 4; ++s)
+            if (ok[s]) bar += wcoef<EXACT>(1, wr[s], 4 - s) * fb[s][1];
+        // D(f) = (Q(f-2) - 15 Q(f-1) + 15 Q(f) - Q(f+1)) / (12 h): faces i-1 .. i+2 (slots 1..4)
+#pragma unroll
+        for (int s = 1; s <= 4; ++s)
+            if (ok[s]) bar += cD[4 - s] * a.inv_hn * fb[s][2];
+        const long long q = a.pad0 + (long long)i * a.st_n + (long long)jx * a.st_t1 + (long long)kx * a.st_t2;
+        a.acc[v][q] += bar;
+        // slide the window: face i + 4 enters
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            ok[s] = ok[s + 1];
+#pragma unroll
+            for (int kk = 0; kk < NW; ++kk) {
+                wl[s][kk] = wl[s + 1][kk];
+                wr[s][kk] = wr[s + 1][kk];
+            }
+#pragma unroll
+            for (int qq = 0; qq < 3; ++qq) fb[s][qq] = fb[s + 1][qq];
+        }
+        if (i + 1 < i_hi) load(5, i + 4);
     }
-    const long long q = a.pad0 + (long long)i * a.st_n + (long long)jx * a.st_t1 + (long long)kx * a.st_t2;
-    for (int v = 0; v < 4; ++v) a.acc[v][q] += bar[v];
 }
 
 template <bool EXACT>
@@ -434,11 +501,11 @@ hipError_t launch_adj_passes(const AdjFaceArgs& a, int stage, hipStream_t s) {
     const dim3 fgrid((unsigned)blocks), fblock(FaceTile<double>::THREADS);
     if (stage == 1) hipLaunchKernelGGL((adj_face_kernel<1, EXACT>), fgrid, fblock, 0, s, a);
     else hipLaunchKernelGGL((adj_face_kernel<2, EXACT>), fgrid, fblock, 0, s, a);
-    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * ((a.n_t2 + 4 + T2_STRIP - 1) / T2_STRIP) * 8;
+    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * ((a.n_t2 + 4 + T2_CHUNK - 1) / T2_CHUNK) * 8;
     hipLaunchKernelGGL((adj_t2_kernel<EXACT>), dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
-    const long long nC = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4) * 4;
-    hipLaunchKernelGGL((adj_t1_kernel<EXACT>), dim3((unsigned)((nC + 255) / 256)), dim3(256), 0, s, a);
-    const long long nD = (long long)(a.n_n + 6) * (a.n_t1 + 4) * (a.n_t2 + 4);
+    const long long nC = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 4 * ((a.n_t1 + 4 + C_SEG - 1) / C_SEG);
+    hipLaunchKernelGGL((adj_t1_kernel<EXACT>), dim3((unsigned)nC), dim3(C_THREADS), 0, s, a);
+    const long long nD = (long long)((a.n_n + 6 + N_CHUNK - 1) / N_CHUNK) * 4 * (a.n_t1 + 4) * (a.n_t2 + 4);
     hipLaunchKernelGGL((adj_normal_kernel<EXACT>), dim3((unsigned)((nD + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -666,10 +733,22 @@ __global__ void alm_adj_points_kernel(AlmAdjArgs A) {
 }
 
 // adjoint of the velocity sampling (trilinear, or the mean of trilinear samples along the direction of
-// motion), points and samples in fixed order (one thread)
-__global__ void alm_adj_scatter_kernel(AlmAdjArgs A) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// motion) in gather form: one thread per cell of the sampling box adds, for the points in ascending
+// order and their samples in ascending order, the terms of every sample whose eight trilinear cells
+// hold it (the order of a serial sweep over points, samples and corners)
+__global__ void __launch_bounds__(256) alm_adj_scatter_kernel(AlmAdjArgs A) {
     const AlmArgs& a = A.fwd;
+    const long long ncell = (long long)a.samp_n[0] * a.samp_n[1] * a.samp_n[2];
+    const long long tcell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tcell >= ncell) return;
+    const int ci = a.samp_lo[0] + (int)(tcell % a.samp_n[0]);
+    const int cj = a.samp_lo[1] + (int)((tcell / a.samp_n[0]) % a.samp_n[1]);
+    const int ck = a.samp_lo[2] + (int)(tcell / ((long long)a.samp_n[0] * a.samp_n[1]));
+    const long long q = pidx_g(a.g, ci, cj, ck);
+    const double rho = a.rho_ref + A.qpre[0][q];
+    const double Uc[3] = {A.qpre[1][q] / rho, A.qpre[2][q] / rho, A.qpre[3][q] / rho};
+    double lam[4] = {A.lam_pre[0][q], A.lam_pre[1][q], A.lam_pre[2][q], A.lam_pre[3][q]};
+    bool touched = false;
     const int ns = a.line_n > 1 ? a.line_n : 1;
     const double t = a.st->t_next;
     for (int p = 0; p < a.n_act; ++p) {
@@ -690,29 +769,28 @@ __global__ void alm_adj_scatter_kernel(AlmAdjArgs A) {
                 i0[d] = (int)fl;
                 w1[d] = fc - fl;
             }
-            for (int dz = 0; dz < 2; ++dz)
-                for (int dy = 0; dy < 2; ++dy)
-                    for (int dx = 0; dx < 2; ++dx) {
-                        const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) * (dz ? w1[2] : 1.0 - w1[2]);
-                        const long long q = pidx_g(a.g, i0[0] + dx, i0[1] + dy, i0[2] + dz);
-                        const double rho = a.rho_ref + A.qpre[0][q];
-                        double dot = 0.0;
-                        for (int c = 0; c < 3; ++c) {
-                            const double Uc = A.qpre[1 + c][q] / rho;
-                            A.lam_pre[1 + c][q] += w * Ub[c] / rho;
-                            dot += Ub[c] * Uc;
-                        }
-                        A.lam_pre[0][q] += -w * dot / rho;
-                    }
+            const int dx = ci - i0[0], dy = cj - i0[1], dz = ck - i0[2];
+            if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;
+            const double w = (dx ? w1[0] : 1.0 - w1[0]) * (dy ? w1[1] : 1.0 - w1[1]) * (dz ? w1[2] : 1.0 - w1[2]);
+            double dot = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                lam[1 + c] += w * Ub[c] / rho;
+                dot += Ub[c] * Uc[c];
+            }
+            lam[0] += -w * dot / rho;
+            touched = true;
         }
     }
+    if (touched)
+        for (int v = 0; v < 4; ++v) A.lam_pre[v][q] = lam[v];
 }
 
 hipError_t launch_alm_adjoint(const AlmAdjArgs& A, hipStream_t s) {
     const int n = A.fwd.n_act;
     hipLaunchKernelGGL(alm_adj_gather_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A);
     hipLaunchKernelGGL(alm_adj_points_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A);
-    hipLaunchKernelGGL(alm_adj_scatter_kernel, dim3(1), dim3(64), 0, s, A);
+    const long long ncell = (long long)A.fwd.samp_n[0] * A.fwd.samp_n[1] * A.fwd.samp_n[2];
+    hipLaunchKernelGGL(alm_adj_scatter_kernel, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 

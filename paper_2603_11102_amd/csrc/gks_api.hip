@@ -804,6 +804,8 @@ int gks_set_actuators(gks_ctx* c, const gks_rotor* r) {
             return fail(c, GKS_E_INVALID_ARG, "rotor (points, sampling cells or 3 eps spheres) leaves the interior cells");
         a.box_lo[d] = i0;
         a.box_n[d] = i1 - i0 + 1;
+        a.samp_lo[d] = s0;
+        a.samp_n[d] = s1 - s0 + 1;
     }
     a.n_act = n;
     a.line_n = line ? r->line_points : 1;

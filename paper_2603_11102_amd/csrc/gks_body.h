@@ -25,6 +25,7 @@ struct AlmArgs {
     double* out_phi;
     double* out_u;        // device, 3 n_act: sampled velocity
     int box_lo[3], box_n[3];
+    int samp_lo[3], samp_n[3];  // cells that the velocity sampling of any point can reach over a revolution
     int line_n;            // line sampling: samples along the direction of motion (<= 1: point sampling)
     double line_half;      // half-length of the sampling segment
     GridDesc g;

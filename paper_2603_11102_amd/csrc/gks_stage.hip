@@ -82,9 +82,11 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     constexpr int T2 = FaceTile<real>::T2, X2 = T2 + 4, NTH = FaceTile<real>::THREADS;
     static_assert(EXT1 * X2 <= NTH && 2 * TILE1 * T2 == NTH, "one thread per column and per face line");
     constexpr bool NEED_F0 = (STAGE == 1);
-    // FP32: the z pass loads its epilogue operands at the top of the step (FP64 has no registers to
-    // spare) and updates the compensated state (high part in the field, low part in lo_in / lo_a / lo_b)
-    constexpr bool EPI_PREFETCH = sizeof(real) == 4;
+    // the z pass loads its epilogue operands at the top of the step, so that their latency overlaps the
+    // step's arithmetic; FP32 also updates the compensated state (high part in the field, low part in
+    // lo_in / lo_a / lo_b)
+    constexpr bool EPI_PREFETCH = true;
+    constexpr bool COMPENSATED = sizeof(real) == 4;
     using real2 = typename Vec2<real>::type;
     constexpr int LOC[4] = {LocalOrder<MODE>::v[0], LocalOrder<MODE>::v[1], LocalOrder<MODE>::v[2],
                             LocalOrder<MODE>::v[3]};
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
             const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
             e_r1 = ld2(a.r1, ridx, m);
             e_x1 = ld2(a.rx1, xidx, m);
-            e_lo = ld2(a.lo_in, ridx, m);
+            if (COMPENSATED) e_lo = ld2(a.lo_in, ridx, m);
             if (NEED_F0) {
                 e_r0 = ld2(a.r0, ridx, m);
                 e_x0 = ld2(a.rx0, xidx, m);
@@ -376,7 +378,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 }
                 const real L1[2] = {r1v.x + (d1.x + x1v.x), r1v.y + (d1.y + x1v.y)};
                 const real L0[2] = {r0v.x + (d0.x + x0v.x), r0v.y + (d0.y + x0v.y)};
-                if constexpr (EPI_PREFETCH) {
+                if constexpr (COMPENSATED) {
                     // FP32: the state is carried as hi + lo; each update is an error-free sum of the
                     // stored high part and (low part + increment)
                     const real lo[2] = {e_lo.x, e_lo.y};
@@ -405,18 +407,19 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                     st2(a.lo_a, ridx, m, la);
                     if (NEED_F0) st2(a.lo_b, ridx, m, lb);
                 } else {
+                    // FP64: the plain stage update from the prefetched Q^n (stage 1) or S (stage 2)
 #pragma unroll
                     for (int vv = 0; vv < 2; ++vv) {
                         real* const outa = pick(hi, a.out_a[LOC[2 + vv]], a.out_a[LOC[vv]]);
                         if (NEED_F0) {
-                            const real Q = pick(hi, a.q_c[LOC[2 + vv]], a.q_c[LOC[vv]])[pidx];
+                            const real Q = e_q[vv];
                             real* const outb = pick(hi, a.out_b[LOC[2 + vv]], a.out_b[LOC[vv]]);
                             outa[pidx] = Q + real(0.5) * dt * L0[vv] + real(0.125) * dt * dt * L1[vv];
                             outb[pidx] = Q + dt * L0[vv] + (dt * dt * real(1.0 / 6.0)) * L1[vv];
                         } else {
                             const real gv = pick(hi, a.g_global[1 + vv], vv == 1 ? a.g_global[0] : real(0));
                             const real add = (dt * dt * real(1.0 / 3.0)) * L1[vv] + dt * gv;
-                            outa[pidx] = pick(hi, a.s_in[LOC[2 + vv]], a.s_in[LOC[vv]])[pidx] + add;
+                            outa[pidx] = e_q[vv] + add;
                         }
                     }
                 }
