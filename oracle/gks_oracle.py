@@ -73,8 +73,10 @@ R17 Stretched meshes (the channel of Section 4.1 is computed on a tanh-clustered
     update divides the flux difference by the normal width w_i; the CFL step takes the smallest
     width. A uniform axis gives exactly the uniform scheme. Periodic axes must be uniform. A rotor or
     an immersed body needs one cell width on the cells around it (the paper keeps its turbines in a
-    uniformly refined block) and works on the uniform grid of that block; a moving body is checked
-    again at every step.
+    uniformly refined block) and works on the uniform grid of that block; a moving body keeps the grid
+    of its initial block and must keep every point's 4-cell support inside the widest run of cells of
+    that width (all cells of a uniform axis); when a support leaves it, the forcing stops for that and
+    every later step and the step reports it.
 R18 Line sampling of the NTNU rotor (Section 3.1 and Section 4.4 name a line sampling method and defer
     its definition to the cited ALM work; PROPOSED, parity unpinned against the paper): the velocity
     of actuator point p is the mean of trilinear samples at N points spaced evenly (midpoints of N
@@ -104,6 +106,7 @@ __all__ = [
     "phi4", "IbmCache", "ibm_setup", "ibm_apply", "conservation_sums", "Oracle", "GAUSS_XI",
     "rotor_objective", "rotor_gradient", "tip_factor", "flow_statistics", "van_leer", "muscl_faces",
     "rotation_matrix", "ibm_motion_state", "axis_metrics", "mesh_faces", "body_grid", "line_sample",
+    "body_run", "support_inside",
 ]
 
 GAUSS_XI = (-1.0 / (2.0 * math.sqrt(3.0)), 1.0 / (2.0 * math.sqrt(3.0)))  # 2-point Gauss-Legendre on a cell
@@ -320,6 +323,41 @@ def body_grid(cfg, lo, hi, pad):
             raise ValueError("a body on a stretched mesh needs one cell width around it (reading R17)")
         org[a], h[a] = float(f[i0] - i0 * w[0]), float(w[0])
     return tuple(org), tuple(h)
+
+
+def body_run(cfg, lo, hi, pad):
+    """Per axis, the widest run of cells of one width that holds the block of body_grid(cfg, lo, hi,
+    pad) (reading R17); all cells of a uniform axis."""
+    runs = []
+    faces = getattr(cfg, "faces", None)
+    for a in range(3):
+        n = (cfg.nx, cfg.ny, cfg.nz)[a]
+        if faces is None or faces[a] is None:
+            runs.append((0, n - 1))
+            continue
+        f = mesh_faces(cfg, a)
+        w = np.diff(f)
+        i0 = max(0, int(np.searchsorted(f, lo[a], side="right")) - 1 - pad)
+        i1 = min(n - 1, int(np.searchsorted(f, hi[a], side="right")) - 1 + pad)
+        r0, r1 = i0, i1
+        while r0 > 0 and abs(w[r0 - 1] - w[i0]) <= 1e-12 * w[i0]:
+            r0 -= 1
+        while r1 < n - 1 and abs(w[r1 + 1] - w[i0]) <= 1e-12 * w[i0]:
+            r1 += 1
+        runs.append((r0, r1))
+    return runs
+
+
+def support_inside(X, grid, runs):
+    """Whether every point's 4-cell delta support (cells b-1 .. b+2, b the cell below the point
+    relative to the cell centres) lies in the run of its axis (reading R17)."""
+    org, h = grid
+    for a in range(3):
+        f = (np.asarray(X)[:, a] - org[a]) / h[a] - 0.5
+        lo, hi = runs[a][0] + 1, runs[a][1] - 2
+        if not bool(np.all((f >= lo) & (f < hi + 1))):
+            return False
+    return True
 
 
 def cfl_dt(Q, cfg):
@@ -798,12 +836,13 @@ class IbmCache:
         self.vol = vol            # cell volume around the body
 
 
-def ibm_setup(cfg, ibm):
+def ibm_setup(cfg, ibm, grid=None):
     """W_{p->ijk} = phi4((x_i-X)/dx) phi4((y_j-Y)/dy) phi4((z_k-Z)/dz); V_p = dx dS_p;
-    V-bar_ijk = sum_p W V_p (Section 3.2); v-bar_ijk = sum_p W V_p v_p / V-bar_ijk (reading R14)."""
+    V-bar_ijk = sum_p W V_p (Section 3.2); v-bar_ijk = sum_p W V_p v_p / V-bar_ijk (reading R14).
+    grid: the (origins, spacings) the body works on (a moving body keeps its initial one, reading R17)."""
     X = np.asarray(ibm.xyz, dtype=np.float64)
     n = X.shape[0]
-    org, h = body_grid(cfg, X.min(0), X.max(0), 2)
+    org, h = body_grid(cfg, X.min(0), X.max(0), 2) if grid is None else grid
     org, h = np.array(org), np.array(h)
     f = (X - org) / h - 0.5
     i0 = np.floor(f).astype(np.int64)
@@ -924,6 +963,13 @@ class Oracle:
         self.chunk = chunk
         moving = cfg.ibm is not None and getattr(cfg.ibm, "motion", None) is not None
         self.ibm_cache = ibm_setup(cfg, cfg.ibm) if cfg.ibm is not None and not moving else None
+        if moving:
+            # a moving body keeps the grid of its initial block and must stay in the run of cells of
+            # that width; once a support leaves it, the forcing stops for good (reading R17)
+            X0 = np.asarray(cfg.ibm.xyz, dtype=np.float64)
+            self.ibm_grid = body_grid(cfg, X0.min(0), X0.max(0), 2)
+            self.ibm_runs = body_run(cfg, X0.min(0), X0.max(0), 2)
+            self.ibm_left = False
         self.history = []
 
     def step(self, dt=None):
@@ -947,8 +993,16 @@ class Oracle:
             cache = self.ibm_cache
             if cache is None:  # moving body: supports of the positions at t^{n+1} (reading R16)
                 X, v = ibm_motion_state(cfg.ibm, t_new)
-                cache = ibm_setup(cfg, IbmPoints(X, cfg.ibm.dS, v))
-            Qn, ib = ibm_apply(Qn, dt, cfg, cache, cfg.ibm_iters)
+                if not self.ibm_left and not support_inside(X, self.ibm_grid, self.ibm_runs):
+                    self.ibm_left = True
+                if not self.ibm_left:
+                    cache = ibm_setup(cfg, IbmPoints(X, cfg.ibm.dS, v), self.ibm_grid)
+            if cache is not None:
+                Qn, ib = ibm_apply(Qn, dt, cfg, cache, cfg.ibm_iters)
+                ib["left"] = False
+            else:
+                ib = {"body_force": torch.zeros(3, dtype=F64), "residual": torch.tensor(0.0, dtype=F64),
+                      "left": True}
             out["ibm"] = ib
         self.Q = Qn
         self.t = t_new

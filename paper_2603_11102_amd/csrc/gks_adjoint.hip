@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
 // ------------------------------------------------------------------------------------------------
 // pass B: transpose of the t2 sweep -> adjoints of the t1 line values (q^L_m, q^R_m, D_m, Ct1_m, C_m)
 // ------------------------------------------------------------------------------------------------
-constexpr int T2_CHUNK = 32;  // consecutive t2 outputs per thread in pass B
+constexpr int T2_CHUNK = 64;  // consecutive t2 outputs per thread in pass B
 
 template <bool EXACT>
 __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {

@@ -497,11 +497,13 @@ __device__ __forceinline__ void gp_flux_adj(const double qL[4], const double qR[
     const double irL = rcp<double>(rL), irR = rcp<double>(rR);
     const double uL = qL[1] * irL, uR = qR[1] * irR;
     const double aL = k.sl * uL, aR = k.sl * uR;
-    const double EaL = erf(aL), EaR = erf(aR);
+    // the forward's evaluation of erf(aL), erf(aR), erf(aL) - erf(aR) and expm1
+    double EaL, EaR, Ead;
+    KinTrans<double>::erfs(aL, aR, EaL, EaR, Ead);
     const double hL = 0.5 * (1.0 + EaL), hR = 0.5 * (1.0 - EaR);
     const double eR = exp(-k.lam * uR * uR), eL = exp(-k.lam * uL * uL);
-    const double dE = eR * expm1(k.lam * (uR - uL) * (uR + uL));
-    const double rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * 0.5 * erf_diff<double>(aL, aR);
+    const double dE = eR * KinTrans<double>::expm1_(k.lam * (uR - uL) * (uR + uL));
+    const double rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * 0.5 * Ead;
     double m0[3];
     m0[0] = qL[1] * hL + qR[1] * hR + k.kk * (qL[0] * eL - qR[0] * eR + k.rho_ref * dE);
     m0[1] = qL[2] * hL + qR[2] * hR;
@@ -610,8 +612,9 @@ __device__ __forceinline__ void gp_flux_adj(const double qL[4], const double qR[
     EaLb += 0.5 * hLb;
     EaRb += -0.5 * hRb;
     const double c2pi = 1.1283791670955126;  // 2 / sqrt(pi)
-    double uLb = k.sl * EaLb * c2pi * exp(-aL * aL) + eLb * eL * (-2.0 * k.lam * uL);
-    double uRb = k.sl * EaRb * c2pi * exp(-aR * aR) + eRb * eR * (-2.0 * k.lam * uR);
+    // d erf(sl u)/du = sl (2/sqrt(pi)) exp(-sl^2 u^2), and sl^2 = lambda: exp(-aL^2) is eL
+    double uLb = k.sl * EaLb * c2pi * eL + eLb * eL * (-2.0 * k.lam * uL);
+    double uRb = k.sl * EaRb * c2pi * eR + eRb * eR * (-2.0 * k.lam * uR);
     qLb[1] += uLb * irL;
     qLb[0] += -uLb * qL[1] * irL * irL;
     qRb[1] += uRb * irR;

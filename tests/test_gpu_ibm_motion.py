@@ -208,3 +208,56 @@ def test_moving_body_leaving_its_uniform_cells_is_reported():
     assert outs[-1]["status"] == GKS_E_BODY_LEFT
     assert outs[-1]["ibm_force"] == [0.0, 0.0, 0.0]
     assert bool(torch.isfinite(s.interior()).all())
+
+
+def _edge_case(velocity_cells_per_step=2.5, steps=4):
+    """A small sphere below the growing cells driven upwards at a fixed dt so that its supports reach
+    the last cell of the run of uniform cells at one step and leave the run at the next."""
+    base = make_case("alm_ibm", grid=GRID).with_(rotor=None)
+    h = base.dz
+    dt = 0.04 * h
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=(40, 3))
+    d *= 1.5 * h / np.linalg.norm(d, axis=1, keepdims=True)
+    c0 = np.array([3.0, 2.0, 24 * h - 6.0 * h])
+    ib = IbmSpec(xyz=c0 + d, dS=np.full(40, 0.005 * h * h),
+                 motion=IbmMotion(center=c0, velocity=(0.0, 0.0, velocity_cells_per_step * h / dt)))
+    return _top_stretched(base.with_(ibm=ib, cfl=0.0, dt_fixed=dt), 24, 8, 1.1)
+
+
+def test_moving_body_at_and_past_the_edge_of_its_run_fp64_vs_oracle():
+    # the oracle applies the same rule as the device: a support may reach the last cell of the run of
+    # the body's width; past it the forcing stops for good and the step reports it
+    from oracle.gks_oracle import body_run, body_grid, ibm_motion_state
+    from paper_2603_11102_amd._lib import GKS_E_BODY_LEFT
+    cfg = _edge_case()
+    steps = 4
+    X0 = np.asarray(cfg.ibm.xyz)
+    org, hh = body_grid(cfg, X0.min(0), X0.max(0), 2)
+    run_hi = body_run(cfg, X0.min(0), X0.max(0), 2)[2][1]
+    top = []
+    for n in range(1, steps + 1):
+        X, _ = ibm_motion_state(cfg.ibm, n * cfg.dt_fixed)
+        top.append(int(np.floor((X[:, 2] - org[2]) / hh[2] - 0.5).max()) + 2)
+    assert run_hi in top and top[-1] > run_hi  # the supports reach the edge cell, then pass it
+    print_case("ibm-motion-edge", grid=GRID, run_hi=run_hi, support_top=top)
+    from paper_2603_11102_amd import GksSolver
+    s = GksSolver(cfg, precision="fp64")
+    gouts = []
+    for _ in range(steps):
+        s.step(1)
+        gouts.append(s.forces(check=False))  # the body-left status is a result here, not an error
+    o, oouts = run_oracle(cfg, steps)
+    err = rel_errors(s.interior(), oracle_dev(o.Q, cfg.rho_ref))
+    assert max(err) < 1e-12, err
+    left = False
+    for g, b, t in zip(gouts, oouts, top):
+        left = left or t > run_hi
+        assert b["ibm"]["left"] == left
+        assert (g["status"] == GKS_E_BODY_LEFT) == left
+        ref_f = b["ibm"]["body_force"].numpy()
+        if left:
+            assert g["ibm_force"] == [0.0, 0.0, 0.0] and not ref_f.any()
+        else:
+            assert any(f != 0.0 for f in g["ibm_force"])
+            assert np.allclose(g["ibm_force"], ref_f, rtol=1e-11, atol=1e-14 * np.abs(ref_f).max())

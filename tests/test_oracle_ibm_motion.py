@@ -142,3 +142,23 @@ def test_body_leaving_the_interior_is_rejected():
     X, v = ibm_motion_state(ib, 0.2)
     with pytest.raises(ValueError):
         ibm_setup(cfg, IbmPoints(X, dS, v))
+
+
+def test_support_rule_at_the_edge_of_the_run():
+    # reading R17: a point's 4-cell support b-1 .. b+2 (b the cell below it relative to the centres)
+    # must lie in the run of cells of the body's width; z is uniform for 24 cells, then grows
+    from oracle.gks_oracle import body_run, support_inside
+    cfg = make_case("alm_ibm", grid=(64, 32, 32)).with_(rotor=None, ibm=None)
+    h = cfg.dz
+    w = np.concatenate([np.full(24, h), h * 1.1 ** np.arange(1, 9)])
+    zf = np.concatenate([[0.0], np.cumsum(w)])
+    cfg = cfg.with_(lz=float(zf[-1]), faces=(None, None, zf))
+    runs = body_run(cfg, np.array([3.0, 2.0, 10 * h]), np.array([3.0, 2.0, 11 * h]), 2)
+    assert runs[2] == (0, 23) and runs[0] == (0, 63)
+    grid = ((0.0, 0.0, 0.0), (cfg.dx, cfg.dy, h))
+    at_edge = np.array([[3.0, 2.0, (21 + 0.5 + 0.99) * h]])     # b = 21: support cells 20 .. 23
+    past = np.array([[3.0, 2.0, (22 + 0.5 + 0.01) * h]])        # b = 22: support reaches cell 24
+    low_edge = np.array([[3.0, 2.0, (1 + 0.5) * h]])            # b = 1: support cells 0 .. 3
+    below = np.array([[3.0, 2.0, (0.5 + 0.99) * h]])            # b = 0: support reaches cell -1
+    assert support_inside(at_edge, grid, runs) and support_inside(low_edge, grid, runs)
+    assert not support_inside(past, grid, runs) and not support_inside(below, grid, runs)
