@@ -47,74 +47,78 @@ template <> __device__ __forceinline__ double rcp<double>(double x) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// WENO-JS smoothness indicators of the three quadratic sub-stencils of five cells q[-2..2].
-// Returns P_k = prod_{j != k} (eps + beta_j)^2: the nonlinear weights gamma_k / (eps + beta_k)^2,
-// normalised, equal gamma_k P_k / sum_j gamma_j P_j, so one reciprocal per evaluation point suffices.
+// WENO-JS on five cells q[-2..2], written in the stencil's first differences
+// d1 = q[-1] - q[-2], d2 = q[0] - q[-1], d3 = q[1] - q[0], d4 = q[2] - q[1]. Sub-stencil k's quadratic
+// (cells k-2..k) has second difference a_k and twice its slope at the cell centre b_k (unit cells):
+//   a0 = d2 - d1, b0 = 3 d2 - d1;   a1 = d3 - d2, b1 = d2 + d3;   a2 = d4 - d3, b2 = 3 d3 - d4,
+// so that its smoothness indicator is 4 beta_k = (13/3) a_k^2 + b_k^2, its values at the faces
+// xi = +-1/2 are q0 + (a_k +- 3 b_k)/12 and at the Gauss points xi = s sqrt3/6 q0 + s (sqrt3/12) b_k
+// (the two-point Gauss rule integrates the quadratic exactly, so its even part there is q0).
+// P_k = prod_{j != k} (4 eps + 4 beta_j)^2: the nonlinear weights gamma_k / (eps + beta_k)^2,
+// normalised, equal gamma_k P_k / sum_j gamma_j P_j (the common factor 4^4 cancels), so one reciprocal
+// per evaluation point suffices.
 // ---------------------------------------------------------------------------------------------
 template <typename real>
-__device__ __forceinline__ void js_weights(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
-                                           real& P0, real& P1, real& P2) {
-    // 4 beta_k = (13/3) a^2 + b^2; with eps scaled by 4 as well every (eps + beta_k)^2 gains the same
-    // factor 16, which cancels in the normalised weights.
-    const real c133 = real(13.0 / 3.0);
-    const real e4 = real(4) * eps;
-    real a = qm2 - real(2) * qm1 + q0, b = qm2 - real(4) * qm1 + real(3) * q0;
-    real e0 = e4 + c133 * a * a + b * b;
-    a = qm1 - real(2) * q0 + qp1;
-    b = qm1 - qp1;
-    real e1 = e4 + c133 * a * a + b * b;
-    a = q0 - real(2) * qp1 + qp2;
-    b = real(3) * q0 - real(4) * qp1 + qp2;
-    real e2 = e4 + c133 * a * a + b * b;
-    e0 *= e0;
-    e1 *= e1;
-    e2 *= e2;
-    P0 = e1 * e2;
-    P1 = e0 * e2;
-    P2 = e0 * e1;
+__device__ __forceinline__ void js_parts(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
+                                         real a[3], real b[3], real P[3]) {
+    const real d1 = qm1 - qm2, d2 = q0 - qm1, d3 = qp1 - q0, d4 = qp2 - qp1;
+    a[0] = d2 - d1;
+    b[0] = real(3) * d2 - d1;
+    a[1] = d3 - d2;
+    b[1] = d2 + d3;
+    a[2] = d4 - d3;
+    b[2] = real(3) * d3 - d4;
+    const real c133 = real(13.0 / 3.0), e4 = real(4) * eps;
+    real e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e[k] = e4 + c133 * a[k] * a[k] + b[k] * b[k];
+        e[k] *= e[k];
+    }
+    P[0] = e[1] * e[2];
+    P[1] = e[0] * e[2];
+    P[2] = e[0] * e[1];
 }
 
 // Face values of cell 0: right face (xi = +1/2, linear weights 1/10, 3/5, 3/10) and left face
-// (xi = -1/2, weights 3/10, 3/5, 1/10). Both share the cell's smoothness indicators.
+// (xi = -1/2, weights 3/10, 3/5, 1/10). Both share the cell's smoothness indicators. The weights are
+// divided by 3/5, and the 1/12 of the sub-stencil values goes into the denominator.
 template <typename real>
 __device__ __forceinline__ void weno_faces(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                            real& right, real& left) {
-    real P0, P1, P2;
-    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
-    const real s6 = real(1.0 / 6.0);
-    real r0 = s6 * (real(2) * qm2 - real(7) * qm1 + real(11) * q0);
-    real r1 = s6 * (-qm1 + real(5) * q0 + real(2) * qp1);
-    real r2 = s6 * (real(2) * q0 + real(5) * qp1 - qp2);
-    real a0 = real(0.1) * P0, a1 = real(0.6) * P1, a2 = real(0.3) * P2;
-    right = (a0 * r0 + a1 * r1 + a2 * r2) * rcp<real>(a0 + a1 + a2);
-    real l0 = s6 * (-qm2 + real(5) * qm1 + real(2) * q0);
-    real l1 = s6 * (real(2) * qm1 + real(5) * q0 - qp1);
-    real l2 = s6 * (real(11) * q0 - real(7) * qp1 + real(2) * qp2);
-    a0 = real(0.3) * P0;
-    a2 = real(0.1) * P2;
-    left = (a0 * l0 + a1 * l1 + a2 * l2) * rcp<real>(a0 + a1 + a2);
+    real a[3], b[3], P[3];
+    js_parts(qm2, qm1, q0, qp1, qp2, eps, a, b, P);
+    const real P1x = real(12) * P[1];
+    real X0 = P[0] * (a[0] + real(3) * b[0]);
+    real X1 = P[1] * (a[1] + real(3) * b[1]);
+    real X2 = P[2] * (a[2] + real(3) * b[2]);
+    right = q0 + (real(1.0 / 6.0) * X0 + (real(0.5) * X2 + X1)) *
+                     rcp<real>(real(2) * P[0] + (real(6) * P[2] + P1x));
+    X0 = P[0] * (a[0] - real(3) * b[0]);
+    X1 = P[1] * (a[1] - real(3) * b[1]);
+    X2 = P[2] * (a[2] - real(3) * b[2]);
+    left = q0 + (real(0.5) * X0 + (real(1.0 / 6.0) * X2 + X1)) *
+                    rcp<real>(real(6) * P[0] + (real(2) * P[2] + P1x));
 }
 
-// WENO-JS values at the two Gauss points of cell 0. Each sub-stencil quadratic is q0 + s d_k at
-// xi = s sqrt3/6 (the two-point Gauss rule integrates it exactly, so its even part is q0); the linear
-// weights reproducing the quartic are (7/36 - s sqrt3/1080, 11/18, 7/36 + s sqrt3/1080).
+// Linear weights at the Gauss points s = +-1 that reproduce the quartic: (7/36 - s sqrt3/1080, 11/18,
+// 7/36 + s sqrt3/1080), here divided by 11/18 (WGL: the s = +1 outer weight of sub-stencil 0, WGH the
+// other one).
+#define GKS_WGL ((7.0 / 36.0 - GKS_SQRT3 / 1080.0) / (11.0 / 18.0))
+#define GKS_WGH ((7.0 / 36.0 + GKS_SQRT3 / 1080.0) / (11.0 / 18.0))
+
+// WENO-JS values at the two Gauss points of cell 0, vm (s = -1) and vp (s = +1). The sqrt3/12 of the
+// sub-stencil deviations goes into the denominators.
 template <typename real>
 __device__ __forceinline__ void weno_gauss(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                            real& vm, real& vp) {
-    real P0, P1, P2;
-    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
-    const real r12 = real(GKS_SQRT3 / 12.0), r3 = real(GKS_SQRT3 / 3.0), r4 = real(GKS_SQRT3 / 4.0);
-    real d0 = r12 * qm2 - r3 * qm1 + r4 * q0;
-    real d1 = r12 * (qp1 - qm1);
-    real d2 = -r4 * q0 + r3 * qp1 - r12 * qp2;
-    const real gc = real(7.0 / 36.0), gd = real(GKS_SQRT3 / 1080.0), g1 = real(11.0 / 18.0);
-    // s = +1
-    real a0 = (gc - gd) * P0, a1 = g1 * P1, a2 = (gc + gd) * P2;
-    vp = q0 + (a0 * d0 + a1 * d1 + a2 * d2) * rcp<real>(a0 + a1 + a2);
-    // s = -1
-    a0 = (gc + gd) * P0;
-    a2 = (gc - gd) * P2;
-    vm = q0 - (a0 * d0 + a1 * d1 + a2 * d2) * rcp<real>(a0 + a1 + a2);
+    real a[3], b[3], P[3];
+    js_parts(qm2, qm1, q0, qp1, qp2, eps, a, b, P);
+    const real lo = real(GKS_WGL), hi = real(GKS_WGH), k = real(12.0 / GKS_SQRT3);
+    const real X0 = P[0] * b[0], X1 = P[1] * b[1], X2 = P[2] * b[2];
+    const real P1k = k * P[1];
+    vp = q0 + (lo * X0 + (hi * X2 + X1)) * rcp<real>(real(k * lo) * P[0] + (real(k * hi) * P[2] + P1k));
+    vm = q0 - (hi * X0 + (lo * X2 + X1)) * rcp<real>(real(k * hi) * P[0] + (real(k * lo) * P[2] + P1k));
 }
 
 // Quartic through five cell averages: values at the two Gauss points.
@@ -362,53 +366,47 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
 template <typename real>
 __device__ __forceinline__ void weno_faces_w(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                              real& right, real& left, real wr[3], real wl[3]) {
-    real P0, P1, P2;
-    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
-    const real s6 = real(1.0 / 6.0);
-    real r0 = s6 * (real(2) * qm2 - real(7) * qm1 + real(11) * q0);
-    real r1 = s6 * (-qm1 + real(5) * q0 + real(2) * qp1);
-    real r2 = s6 * (real(2) * q0 + real(5) * qp1 - qp2);
-    real a0 = real(0.1) * P0, a1 = real(0.6) * P1, a2 = real(0.3) * P2;
-    real is = rcp<real>(a0 + a1 + a2);
-    wr[0] = a0 * is;
-    wr[1] = a1 * is;
-    wr[2] = a2 * is;
-    right = (a0 * r0 + a1 * r1 + a2 * r2) * is;
-    real l0 = s6 * (-qm2 + real(5) * qm1 + real(2) * q0);
-    real l1 = s6 * (real(2) * qm1 + real(5) * q0 - qp1);
-    real l2 = s6 * (real(11) * q0 - real(7) * qp1 + real(2) * qp2);
-    a0 = real(0.3) * P0;
-    a2 = real(0.1) * P2;
-    is = rcp<real>(a0 + a1 + a2);
-    wl[0] = a0 * is;
-    wl[1] = a1 * is;
-    wl[2] = a2 * is;
-    left = (a0 * l0 + a1 * l1 + a2 * l2) * is;
+    real a[3], b[3], P[3];
+    js_parts(qm2, qm1, q0, qp1, qp2, eps, a, b, P);
+    // weights divided by 3/5 and multiplied by 12 in the denominator, as in weno_faces
+    const real P1x = real(12) * P[1];
+    real c0 = real(2) * P[0], c2 = real(6) * P[2];
+    real is = rcp<real>(c0 + (c2 + P1x));
+    wr[0] = c0 * is;
+    wr[1] = P1x * is;
+    wr[2] = c2 * is;
+    right = q0 + (real(1.0 / 6.0) * P[0] * (a[0] + real(3) * b[0]) +
+                  (real(0.5) * P[2] * (a[2] + real(3) * b[2]) + P[1] * (a[1] + real(3) * b[1]))) * is;
+    c0 = real(6) * P[0];
+    c2 = real(2) * P[2];
+    is = rcp<real>(c0 + (c2 + P1x));
+    wl[0] = c0 * is;
+    wl[1] = P1x * is;
+    wl[2] = c2 * is;
+    left = q0 + (real(0.5) * P[0] * (a[0] - real(3) * b[0]) +
+                 (real(1.0 / 6.0) * P[2] * (a[2] - real(3) * b[2]) + P[1] * (a[1] - real(3) * b[1]))) * is;
 }
 
 template <typename real>
 __device__ __forceinline__ void weno_gauss_w(real qm2, real qm1, real q0, real qp1, real qp2, real eps,
                                              real& vm, real& vp, real wm[3], real wp[3]) {
-    real P0, P1, P2;
-    js_weights(qm2, qm1, q0, qp1, qp2, eps, P0, P1, P2);
-    const real r3 = real(GKS_SQRT3);
-    real d0 = r3 * (real(1.0 / 12.0) * qm2 - real(1.0 / 3.0) * qm1 + real(0.25) * q0);
-    real d1 = r3 * real(1.0 / 12.0) * (qp1 - qm1);
-    real d2 = r3 * (-real(0.25) * q0 + real(1.0 / 3.0) * qp1 - real(1.0 / 12.0) * qp2);
-    const real gc = real(7.0 / 36.0), gd = real(GKS_SQRT3 / 1080.0), g1 = real(11.0 / 18.0);
-    real a0 = (gc - gd) * P0, a1 = g1 * P1, a2 = (gc + gd) * P2;
-    real is = rcp<real>(a0 + a1 + a2);
-    wp[0] = a0 * is;
-    wp[1] = a1 * is;
-    wp[2] = a2 * is;
-    vp = q0 + (a0 * d0 + a1 * d1 + a2 * d2) * is;
-    a0 = (gc + gd) * P0;
-    a2 = (gc - gd) * P2;
-    is = rcp<real>(a0 + a1 + a2);
-    wm[0] = a0 * is;
-    wm[1] = a1 * is;
-    wm[2] = a2 * is;
-    vm = q0 - (a0 * d0 + a1 * d1 + a2 * d2) * is;
+    real a[3], b[3], P[3];
+    js_parts(qm2, qm1, q0, qp1, qp2, eps, a, b, P);
+    const real lo = real(GKS_WGL), hi = real(GKS_WGH), r12 = real(GKS_SQRT3 / 12.0);
+    const real X0 = P[0] * b[0], X1 = P[1] * b[1], X2 = P[2] * b[2];
+    real c0 = lo * P[0], c2 = hi * P[2];
+    real is = rcp<real>(c0 + (c2 + P[1]));
+    wp[0] = c0 * is;
+    wp[1] = P[1] * is;
+    wp[2] = c2 * is;
+    vp = q0 + r12 * (lo * X0 + (hi * X2 + X1)) * is;
+    c0 = hi * P[0];
+    c2 = lo * P[2];
+    is = rcp<real>(c0 + (c2 + P[1]));
+    wm[0] = c0 * is;
+    wm[1] = P[1] * is;
+    wm[2] = c2 * is;
+    vm = q0 - r12 * (hi * X0 + (lo * X2 + X1)) * is;
 }
 
 // Coefficient of cell r (0..4 over the stencil -2..2) in sub-stencil k's value:
