@@ -70,6 +70,7 @@ struct gks_ctx {
     std::vector<double> faces[3];  // host copy of the faces of each stretched axis (empty when uniform)
     double lam, c, hmin, eps;
     int chunk[3];      // faces per workgroup of the face kernels, per direction
+    int seg_len[3], n_wg[3];  // work split of the order-5 face launches (FaceArgs)
     int flags;
     // actuator line model
     int has_rotor;
@@ -401,6 +402,8 @@ FaceArgs<real> face_args_buf(gks_ctx* c, int d, int stage, void* const src[4], v
     a.tiles_t1 = (a.n_t1 + TILE1 - 1) / TILE1;
     a.tiles_t2 = (a.n_t2 + t2 - 1) / t2;
     a.chunk = c->chunk[d];
+    a.seg_len = c->seg_len[d];
+    a.n_wg = c->n_wg[d];
     a.st_n = c->g.st[ax[0]];
     a.st_t1 = c->g.st[ax[1]];
     a.st_t2 = c->g.st[ax[2]];
@@ -736,6 +739,7 @@ int gks_init(const gks_config* cfg, gks_field q, gks_field q_stage, gks_field q_
         const int tiles = ((n[ax[1]] + TILE1 - 1) / TILE1) * ((n[ax[2]] + t2 - 1) / t2);
         c->chunk[d] = cfg->precision == GKS_FP32 ? face_chunk<float>(n[ax[0]], tiles, slots)
                                                  : face_chunk<double>(n[ax[0]], tiles, slots);
+        face_plan(n[ax[0]], tiles, slots, c->chunk[d], &c->seg_len[d], &c->n_wg[d]);
     }
     hipError_t e = cfg->precision == GKS_FP32 ? upload_metrics<float>(c, cfg) : upload_metrics<double>(c, cfg);
     if (e == hipSuccess) e = hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);

@@ -165,10 +165,13 @@ __device__ __forceinline__ float erf_diff<float>(float a, float b) {
 }
 
 // Kinetic-average transcendentals: erf(aL), erf(aR), erf(aL) - erf(aR) and expm1(x).
-// FP64: library functions. FP32, when |aL|, |aR| <= 1/4: the Maclaurin series of erf through x^9
-// (truncation < 1e-9 relative) and, for the difference, (2/sqrt(pi)) d (1 - S3/3 + S5/10 - S7/42 +
-// S9/216) with d = a - b and S_k = (a^k - b^k)/(a - b) from S_k = (a + b) S_{k-1} - ab S_{k-2}, which
-// has no cancellation when a ~ b; expm1 by its series through x^5 when |x| <= 1/16.
+// FP64: library functions. FP32, when |aL|, |aR| <= 1/4: the Maclaurin series of erf through x^9,
+// erf(x) = (2/sqrt(pi)) x P(x^2) with P(y) = 1 - y/3 + y^2/10 - y^3/42 + y^4/216 (truncation < 1e-9
+// relative), and for the difference, with A = a^2, B = b^2,
+//   erf(a) - erf(b) = (2/sqrt(pi)) (a - b) [P(A) + b (a + b) Q(A, B)],  P(A) - P(B) = (A - B) Q(A, B),
+//   Q = -1/3 + (A + B)/10 - (A^2 + AB + B^2)/42 + (A + B)(A^2 + B^2)/216,
+// which has no cancellation when a ~ b (truncation < 1e-8 relative); expm1 by its series through x^5
+// when |x| <= 1/16.
 template <typename real>
 struct KinTrans {
     static __device__ __forceinline__ void erfs(real aL, real aR, real& eL, real& eR, real& ed) {
@@ -180,29 +183,23 @@ struct KinTrans {
 };
 template <>
 struct KinTrans<float> {
-    static __device__ __forceinline__ float erf_small(float x) {
-        const float x2 = x * x;
-        float p = fmaf(x2, 1.0f / 216.0f, -1.0f / 42.0f);
-        p = fmaf(x2, p, 0.1f);
-        p = fmaf(x2, p, -1.0f / 3.0f);
-        p = fmaf(x2, p, 1.0f);
-        return 1.1283791670955126f * x * p;
+    static __device__ __forceinline__ float poly(float y) {
+        float p = fmaf(y, 1.0f / 216.0f, -1.0f / 42.0f);
+        p = fmaf(y, p, 0.1f);
+        p = fmaf(y, p, -1.0f / 3.0f);
+        return fmaf(y, p, 1.0f);
     }
     static __device__ __forceinline__ void erfs(float aL, float aR, float& eL, float& eR, float& ed) {
+        const float k2 = 1.1283791670955126f;  // 2/sqrt(pi)
         if (fabsf(aL) <= 0.25f && fabsf(aR) <= 0.25f) {
-            eL = erf_small(aL);
-            eR = erf_small(aR);
-            const float p = aL + aR, q = aL * aR;
-            float s1 = 1.0f, s2 = p;
-            float s3 = fmaf(p, s2, -q * s1);
-            float s4 = fmaf(p, s3, -q * s2);
-            float s5 = fmaf(p, s4, -q * s3);
-            float s6 = fmaf(p, s5, -q * s4);
-            float s7 = fmaf(p, s6, -q * s5);
-            float s8 = fmaf(p, s7, -q * s6);
-            float s9 = fmaf(p, s8, -q * s7);
-            const float poly = 1.0f - s3 * (1.0f / 3.0f) + s5 * 0.1f - s7 * (1.0f / 42.0f) + s9 * (1.0f / 216.0f);
-            ed = 1.1283791670955126f * (aL - aR) * poly;
+            const float A = aL * aL, B = aR * aR;
+            const float PA = poly(A);
+            eL = k2 * aL * PA;
+            eR = k2 * aR * poly(B);
+            const float sAB = A + B, pAB = A * B;
+            const float u = fmaf(sAB, sAB, -pAB);  // A^2 + AB + B^2
+            const float Q = fmaf(sAB * (u - pAB), 1.0f / 216.0f, fmaf(u, -1.0f / 42.0f, fmaf(sAB, 0.1f, -1.0f / 3.0f)));
+            ed = k2 * (aL - aR) * fmaf(aR * (aL + aR), Q, PA);
         } else {
             eL = erff(aL);
             eR = erff(aR);
@@ -314,8 +311,8 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
     real hL = real(0.5) * (real(1) + eaL);
     real hR = real(0.5) * (real(1) - eaR);
     real eR = Rc<real>::exp_(-k.lam * uR * uR);
-    real eL = Rc<real>::exp_(-k.lam * uL * uL);
     real dE = eR * KinTrans<real>::expm1_(k.lam * (uR - uL) * (uR + uL));  // eL - eR
+    real eL = eR + dE;                                                     // exp(-lambda uL^2)
     real rho0p = qL[0] * hL + qR[0] * hR + k.rho_ref * real(0.5) * ead;
     real m0[3];
     real mass_flux;  // F0 of the density: m0[0], or m0[0] - cm when shifted
@@ -332,27 +329,25 @@ __device__ __forceinline__ void gp_flux(const real qL[4], const real qR[4], cons
     real r0 = k.rho_ref + rho0p;
     real ir = rcp<real>(r0);
     real U[3] = {m0[0] * ir, m0[1] * ir, m0[2] * ir};
-    // velocity gradients dU[d][j] = (dm_j/dx_d - U_j drho/dx_d) / rho0
-    real dU[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) dU[d][j] = (g[d][1 + j] - U[j] * g[d][0]) * ir;
     if (NEED_F0) {
+        // the velocity gradients dU[d][j] = (dm_j/dx_d - U_j drho/dx_d) / rho0 that the stress needs
+        const real u00 = (g[0][1] - U[0] * g[0][0]) * ir;
+        const real u01 = (g[0][2] - U[1] * g[0][0]) * ir, u10 = (g[1][1] - U[0] * g[1][0]) * ir;
+        const real u02 = (g[0][3] - U[2] * g[0][0]) * ir, u20 = (g[2][1] - U[0] * g[2][0]) * ir;
         f0[0] += w * mass_flux;
-        f0[1] += w * (m0[0] * U[0] + k.c2 * rho0p - k.mu * real(2) * dU[0][0]);
-        f0[2] += w * (m0[0] * U[1] - k.mu * (dU[0][1] + dU[1][0]));
-        f0[3] += w * (m0[0] * U[2] - k.mu * (dU[0][2] + dU[2][0]));
+        f0[1] += w * (m0[0] * U[0] + k.c2 * rho0p - k.mu * real(2) * u00);
+        f0[2] += w * (m0[0] * U[1] - k.mu * (u01 + u10));
+        f0[3] += w * (m0[0] * U[2] - k.mu * (u02 + u20));
     }
-    // Euler time derivative of Q0
+    // Euler time derivative of Q0. Its advection term needs no velocity gradient:
+    // rho0 (U . grad) U_j = sum_d U_d dm_j/dx_d - U_j sum_d U_d drho/dx_d.
     real divm = g[0][1] + g[1][2] + g[2][3];
     real qd0 = -divm;
+    const real H = (U[0] * g[0][0] + U[1] * g[1][0] + U[2] * g[2][0]) - divm;
     real qd[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        real adv = U[0] * dU[0][j] + U[1] * dU[1][j] + U[2] * dU[2][j];
-        qd[j] = -U[j] * divm - r0 * adv - k.c2 * g[j][0];
-    }
+    for (int j = 0; j < 3; ++j)
+        qd[j] = U[j] * H - (U[0] * g[0][1 + j] + U[1] * g[1][1 + j] + U[2] * g[2][1 + j]) - k.c2 * g[j][0];
     f1[0] += w * qd[0];
     f1[1] += w * (real(2) * U[0] * qd[0] - U[0] * U[0] * qd0 + k.c2 * qd0);
     f1[2] += w * (U[1] * qd[0] + U[0] * qd[1] - U[0] * U[1] * qd0);

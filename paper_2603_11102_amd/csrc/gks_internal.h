@@ -50,6 +50,10 @@ struct FaceArgs {
     real* lo_b;
     int n_n, n_t1, n_t2;     // interior cells along normal, t1, t2
     int chunk, tiles_t1, tiles_t2;
+    // work split of the order-5 face kernel over its n_wg logical workgroups: seg_len == 0, workgroup b
+    // marches chunk b / (tiles) of tile b % (tiles); seg_len > 0, it marches cells
+    // [b seg_len, (b + 1) seg_len) of the tile-major (tile, cell) order, one segment per tile it meets
+    int seg_len, n_wg;
     long long st_n, st_t1, st_t2;     // padded strides
     long long ist_n, ist_t1, ist_t2;  // interior strides
     long long pad0;                   // padded offset of interior cell (0,0,0)
@@ -113,6 +117,8 @@ template <typename real>
 hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s);
 template <typename real>
 int face_chunk(int n_n, int tiles, int slots);
+// order-5 face launches: the work split (FaceArgs seg_len, n_wg) for chunks of `chunk` cells
+void face_plan(int n_n, int tiles, int slots, int chunk, int* seg_len, int* n_wg);
 template <typename real>
 int face_slots();
 // second-order variant (gks_stage2.hip)

@@ -3,7 +3,9 @@
 // (flux); the two-stage fourth-order combinations).
 //
 // One workgroup owns a tile of faces in the tangential plane (FP32: 16 x 16 faces, 512 threads = 8 wave64;
-// FP64: 16 x 8 faces, 256 threads) and marches along the face normal through a chunk of faces:
+// FP64: 16 x 8 faces, 256 threads) and marches along the face normal through a chunk of faces (or
+// through an equal share of the tile-major (tile, cell) order, one march per tile the share meets, when
+// the tiles do not divide the resident workgroup slots: see face_plan):
 //   * column phase: each of the 20 x 20 (FP64 20 x 12) tangential columns (tile + 2-cell halo per side) keeps a
 //     5-cell window of the field in registers; per cell it evaluates the WENO-JS values at both of its
 //     faces with one set of smoothness indicators, the normal derivative D (cubic through four cells)
@@ -17,6 +19,8 @@
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
 // No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
 // variables (77 KB in FP32, 92 KB in FP64 of the 160 KB per CU).
+#include <algorithm>
+
 #include "gks_internal.h"
 
 namespace gks {
@@ -98,14 +102,26 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
     // the 8 XCDs; the grid is padded to a multiple of 8), so neighbouring tiles share that XCD's L2 for
     // their halo columns
-    int b = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
-    if (b >= a.tiles_t1 * a.tiles_t2 * ((a.n_n + a.chunk - 1) / a.chunk)) return;
-    const int tile1 = b % a.tiles_t1;
-    b /= a.tiles_t1;
-    const int tile2 = b % a.tiles_t2;
-    b /= a.tiles_t2;
-    const int f0 = b * a.chunk;
-    const int f1 = min(f0 + a.chunk, a.n_n);  // residuals of cells [f0, f1); faces f0..f1
+    const int b = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+    if (b >= a.n_wg) return;
+    // this workgroup's cells as a range [lin, lin_end) of the tile-major (tile, cell) order
+    const int tiles = a.tiles_t1 * a.tiles_t2;
+    long long lin, lin_end;
+    if (a.seg_len > 0) {
+        lin = (long long)b * a.seg_len;
+        lin_end = min(lin + a.seg_len, (long long)tiles * a.n_n);
+    } else {
+        const int c0 = (b / tiles) * a.chunk;
+        lin = (long long)(b % tiles) * a.n_n + c0;
+        lin_end = lin + min(a.chunk, a.n_n - c0);
+    }
+    // one march per tile the range meets (the shift cm, the window and the face fluxes restart)
+    while (lin < lin_end) {
+    const int tile = (int)(lin / a.n_n);
+    const int f0 = (int)(lin - (long long)tile * a.n_n);
+    const int f1 = (int)min((long long)a.n_n, f0 + (lin_end - lin));  // residuals of cells [f0, f1); faces f0..f1
+    lin += f1 - f0;
+    const int tile1 = tile % a.tiles_t1, tile2 = tile / a.tiles_t1;
     const int j0 = tile1 * TILE1, k0 = tile2 * T2;
     const real eps = a.eps;
 
@@ -431,6 +447,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
             if (NEED_F0) fprev0[v] = fa0[v];
         }
     }
+    }  // segments
 }
 
 template <typename real>
@@ -465,11 +482,41 @@ int face_chunk(int n_n, int tiles, int slots) {
     return best_chunk;
 }
 
+void face_plan(int n_n, int tiles, int slots, int chunk, int* seg_len, int* n_wg) {
+    // Worst workgroup of each split, in face steps (a march over L cells costs about L + 2), times the
+    // rounds of `slots` workgroups: aligned chunks of `chunk` cells, or equal runs of the tile-major
+    // (tile, cell) order, whose workgroups fill the slots when the tiles do not divide them but pay a
+    // second march where a run crosses into the next tile. The cheaper wins; ties go to the chunks.
+    if (slots <= 0) slots = 512;
+    const long long nch = (n_n + chunk - 1) / chunk;
+    const long long wg_c = (long long)tiles * nch;
+    long long best = ((wg_c + slots - 1) / slots) * (chunk + 2);
+    *seg_len = 0;
+    *n_wg = (int)wg_c;
+    const long long total = (long long)tiles * n_n;
+    for (long long rounds = 1; rounds <= 8; ++rounds) {
+        const long long len = (total + rounds * slots - 1) / (rounds * slots);
+        const long long wgs = (total + len - 1) / len;
+        long long worst = 0;
+        for (long long w = 0; w < wgs; ++w) {
+            const long long c0 = w * len, c1 = std::min(c0 + len, total);
+            const long long segs = (c1 - 1) / n_n - c0 / n_n + 1;
+            worst = std::max(worst, (c1 - c0) + 2 * segs);
+        }
+        const long long cost = ((wgs + slots - 1) / slots) * worst;
+        if (cost < best && wgs <= 0x7ffffff8LL) {
+            best = cost;
+            *seg_len = (int)len;
+            *n_wg = (int)wgs;
+        }
+        if (len == 1) break;
+    }
+}
+
 template <typename real>
 hipError_t launch_face(const FaceArgs<real>& a, int stage, hipStream_t s) {
-    const int nchunks = (a.n_n + a.chunk - 1) / a.chunk;
-    const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
-    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const long long blocks = ((long long)a.n_wg + 7) / 8 * 8;
+    if (a.n_wg <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(FaceTile<real>::THREADS);
 #define GKS_FACE_LAUNCH(ST, MD)                                                                     \
     do {                                                                                            \

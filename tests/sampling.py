@@ -62,20 +62,71 @@ def face_chunk(n_n, tiles, slots=256):
     return best_chunk
 
 
+def face_plan(n_n, tiles, chunk, slots=256):
+    """Work split of an order-5 face launch: (seg_len, n_wg). seg_len 0 is one aligned chunk per
+    workgroup; seg_len > 0 gives workgroup w the cells [w seg_len, (w + 1) seg_len) of the tile-major
+    (tile, cell) order, when its worst workgroup (cells + 2 per tile it meets, times the rounds of
+    `slots`) beats the chunks'."""
+    best = (-(-tiles * (-(-n_n // chunk)) // slots)) * (chunk + 2)
+    plan = (0, tiles * (-(-n_n // chunk)))
+    total = tiles * n_n
+    for rounds in range(1, 9):
+        ln = -(-total // (rounds * slots))
+        wgs = -(-total // ln)
+        w = np.arange(wgs)
+        c0, c1 = w * ln, np.minimum(w * ln + ln, total)
+        worst = int(((c1 - c0) + 2 * ((c1 - 1) // n_n - c0 // n_n + 1)).max())
+        cost = (-(-wgs // slots)) * worst
+        if cost < best:
+            best, plan = cost, (ln, wgs)
+        if ln == 1:
+            break
+    return plan
+
+
 def seams(cfg, precision):
-    """Per axis, the cells on both sides of a seam of the face kernels: tile edges across the faces
-    (16 x 16 faces in FP32, 16 x 8 in FP64) and the ends of the march chunks along the normal."""
+    """Per axis, a (nz, ny, nx) mask of the cells on either side of a seam of the face kernels along that
+    axis: the first and last cell of each march of the pass normal to it (aligned chunks, or the runs of
+    the tile-major split, which start and end at different cells in different tiles), and the tile edges
+    across the faces of the other passes (16 x 16 faces in FP32, 16 x 8 in FP64)."""
     n = (cfg.nx, cfg.ny, cfg.nz)
     t2 = 16 if precision == "fp32" else 8
     axes = ((0, 1, 2), (1, 0, 2), (2, 0, 1))  # (normal, t1, t2) of the x, y and z faces
-    seam = [np.zeros(n[a], bool) for a in range(3)]
+    seam = [np.zeros((cfg.nz, cfg.ny, cfg.nx), bool) for _ in range(3)]
+
+    def along(a, mask1d):  # broadcast a 1-D mask over axis a of the (z, y, x) array
+        shape = [1, 1, 1]
+        shape[2 - a] = n[a]
+        return mask1d.reshape(shape)
+
     for an, a1, a2 in axes:
-        tiles = (-(-n[a1] // 16)) * (-(-n[a2] // t2))
+        nt1, nt2 = -(-n[a1] // 16), -(-n[a2] // t2)
+        tiles = nt1 * nt2
         chunk = face_chunk(n[an], tiles)
-        i = np.arange(n[an])
-        seam[an] |= (i % chunk == 0) | (i % chunk == chunk - 1)
-        seam[a1] |= (np.arange(n[a1]) % 16 == 0) | (np.arange(n[a1]) % 16 == 15)
-        seam[a2] |= (np.arange(n[a2]) % t2 == 0) | (np.arange(n[a2]) % t2 == t2 - 1)
+        seg_len, n_wg = face_plan(n[an], tiles, chunk)
+        # march ends per tile: ends[t] marks the normal cells that start or end a march in tile t
+        ends = np.zeros((tiles, n[an]), bool)
+        if seg_len == 0:
+            i = np.arange(n[an])
+            ends[:] = (i % chunk == 0) | (i % chunk == chunk - 1) | (i == n[an] - 1)
+        else:
+            for w in range(n_wg):
+                lin, end = w * seg_len, min(w * seg_len + seg_len, tiles * n[an])
+                while lin < end:
+                    t, f0 = divmod(lin, n[an])
+                    f1 = min(n[an], f0 + end - lin)
+                    ends[t, f0] = ends[t, f1 - 1] = True
+                    lin += f1 - f0
+        # spread over the cells: tile t covers t1 cells [16 (t % nt1), ...) and t2 cells [t2 (t // nt1), ...)
+        i1 = np.arange(n[a1]) // 16
+        i2 = np.arange(n[a2]) // t2
+        tile_of = i2[:, None] * nt1 + i1[None, :]            # [t2 cell, t1 cell]
+        m = ends[tile_of]                                     # [t2 cell, t1 cell, normal cell]
+        # to (z, y, x): axes (a2, a1, an) -> (2, 1, 0) order
+        order = {a2: 0, a1: 1, an: 2}
+        seam[an] |= np.transpose(m, (order[2], order[1], order[0]))
+        seam[a1] |= along(a1, (np.arange(n[a1]) % 16 == 0) | (np.arange(n[a1]) % 16 == 15))
+        seam[a2] |= along(a2, (np.arange(n[a2]) % t2 == 0) | (np.arange(n[a2]) % t2 == t2 - 1))
     return seam
 
 

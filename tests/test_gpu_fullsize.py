@@ -46,7 +46,7 @@ def test_full_size_sampled_cells(case, precision, tol):
     ex = excluded(cfg)
     nb = near_boundary(cfg)
     seam = seams(cfg, precision)
-    on_seam = seam[2][:, None, None] & seam[1][None, :, None] & seam[0][None, None, :]
+    on_seam = seam[0] & seam[1] & seam[2]
     groups = {"random": np.argwhere(~ex & ~nb), "seam": np.argwhere(~ex & ~nb & on_seam),
               "boundary": np.argwhere(~ex & nb)}
     counts = {"random": 6, "seam": 8, "boundary": 6}
