@@ -74,6 +74,10 @@ hipError_t launch_pad_to_int(double* dst, const double* src, double a, const dou
                              const GridDesc& g, hipStream_t s);
 hipError_t launch_zero(double* y, long long n, hipStream_t s);
 
+// immersed-body adjoint (a body at rest): lam (padded, adjoint of the field after the forcing) becomes
+// the adjoint of the field before it, in place
+hipError_t launch_ibm_adjoint(double* lam[4], const IbmArgs& a, hipStream_t s);
+
 // actuator-line adjoint
 struct AlmAdjArgs {
     AlmArgs fwd;             // forward arguments (positions and per-point data of this step)

@@ -615,6 +615,43 @@ hipError_t launch_zero(double* y, long long n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// immersed-body adjoint (body at rest). Per forced cell the S direct-forcing iterations are affine in
+// (rho, m): m^{s+1} = m^s + r (rho v-bar - m^s), r = V-bar / |Omega|, with V-bar and v-bar fixed by the
+// body. Their transpose, taken through the iterations in reverse order, scales the momentum adjoint by
+// (1 - r) per iteration and adds r v-bar . lambda_m to the density adjoint (the density is not forced).
+// Every forced cell appears once in the body's cell list, so the cells are independent.
+// ------------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) ibm_adj_kernel(Field4<double> lam, IbmArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    const long long q = a.g.pad0 + (long long)a.cell[3 * c] * a.g.st[0] + (long long)a.cell[3 * c + 1] * a.g.st[1] +
+                        (long long)a.cell[3 * c + 2] * a.g.st[2];
+    const double r = a.vbar[c] / (a.g.h[0] * a.g.h[1] * a.g.h[2]);
+    const double vv[3] = {a.vbar_vel[3 * c], a.vbar_vel[3 * c + 1], a.vbar_vel[3 * c + 2]};
+    double lm[3] = {lam.v[1][q], lam.v[2][q], lam.v[3][q]};
+    double lr = lam.v[0][q];
+    for (int s = 0; s < a.iters; ++s) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lr += r * vv[d] * lm[d];
+            lm[d] *= 1.0 - r;
+        }
+    }
+    lam.v[0][q] = lr;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lam.v[1 + d][q] = lm[d];
+}
+
+hipError_t launch_ibm_adjoint(double* lam[4], const IbmArgs& a, hipStream_t s) {
+    if (a.moving || a.ncell_dev) return hipErrorInvalidValue;
+    if (a.ncell <= 0 || a.iters <= 0) return hipSuccess;
+    Field4<double> f;
+    for (int v = 0; v < 4; ++v) f.v[v] = lam[v];
+    hipLaunchKernelGGL(ibm_adj_kernel, dim3((unsigned)((a.ncell + 255) / 256)), dim3(256), 0, s, f, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
 // actuator-line adjoint
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ long long pidx_g(const GridDesc& g, int i, int j, int k) {

@@ -1106,7 +1106,7 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
     if (c->cfg.order == 2) return fail(c, GKS_E_UNSUPPORTED, "the adjoint covers the high-order scheme only");
     if (c->cfg.cfl > 0) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a fixed dt (cfl <= 0)");
     if (!c->has_rotor) return fail(c, GKS_E_STATE, "the adjoint needs a rotor (gks_set_actuators)");
-    if (c->has_ibm) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover immersed bodies");
+    if (c->has_ibm && c->ibm_moving) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover moving bodies");
     for (int sd = 0; sd < 6; ++sd)
         if (c->cfg.bc[sd] == GKS_BC_INFLOW) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover inflow boundaries");
     if (!c->ckpt || nsteps < 1 || nsteps > c->ckpt_n)
@@ -1147,6 +1147,8 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
         rc = ghost_all<double>(c, c->qs);
         if (rc) return rc;
         HIPCHK(c, launch_alm_points_only(field<double>(qpre), c->alm, S));
+        // immersed body (at rest): lam becomes the adjoint of the field before the forcing
+        if (c->has_ibm) HIPCHK(c, launch_ibm_adjoint(B.lam, c->ibm, S));
         // actuator line: lam_pre = lam + (sampling path); gradient in s
         for (int v = 0; v < 4; ++v) HIPCHK(c, launch_axpby(B.lam_pre[v], B.lam[v], 1.0, nullptr, 0.0, np, S));
         AlmAdjArgs A;

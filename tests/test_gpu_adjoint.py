@@ -155,3 +155,58 @@ def test_adjoint_full_size_vs_finite_differences():
         assert abs(fd - fz) < 5e-4 * max(fds[lab]), (name, lab, rf)
     print(f"128^3 adjoint frozen {t_adj:.3f} s, exact {t_exact:.3f} s; worst relative difference to finite "
           f"differences: exact {worst_exact:.3e}, frozen {worst_frozen:.3e} of the largest derivative")
+
+
+def _body_case(grid=(20, 20, 20)):
+    """The rotor box with the tower and nacelle behind the rotor: points at rest with a prescribed
+    velocity (a moving surface), so the forcing's density path (v-bar != 0) is exercised too."""
+    from dataclasses import replace
+    from synth.cases import tower_and_nacelle
+    cfg = make_case("adjoint", grid=grid)
+    ib = tower_and_nacelle(cfg.rotor.hub, 1.0, cfg.dx, spacing=0.5 * cfg.dx, z_ground=2.0 * cfg.dx)
+    rng = np.random.default_rng(7)
+    return cfg.with_(ibm=replace(ib, vel=0.2 * rng.standard_normal((ib.n, 3))))
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_adjoint_with_a_body_at_rest_matches_oracle_reference(exact):
+    # the direct forcing of a body at rest is affine in the field; the window gradient through it, in
+    # the scalings and in the initial field, against the oracle's reverse mode
+    cfg = _body_case()
+    n = cfg.rotor.n_act
+    rng = np.random.default_rng(0)
+    s0 = 1.0 + 0.1 * rng.standard_normal(n)
+    nsteps = 2
+    print_case("adjoint-body-vs-oracle", grid=(20, 20, 20), n_ibm=cfg.ibm.n, nsteps=nsteps, exact=exact)
+    s, J, _ = _gpu_window(cfg, s0, nsteps)
+    g, gq = s.adjoint(nsteps, W, want_field=True, exact=exact)
+    Jo, go = rotor_gradient(cfg, s0, nsteps, W, frozen=not exact)
+    # the body changes the objective and its gradient by tens of per cent at this size
+    J_free, g_free = rotor_gradient(make_case("adjoint", grid=(20, 20, 20)), s0, nsteps, W, frozen=not exact)
+    assert float((go - g_free).abs().max() / go.abs().max()) > 0.05
+    assert abs(J - Jo) < 1e-12 * abs(Jo)
+    rel = float((g.cpu() - go).abs().max() / go.abs().max())
+    assert rel < 1e-10, rel
+    q0 = torch.tensor(cfg.q0).clone().requires_grad_(True)
+    Jt, _ = rotor_objective(cfg, torch.tensor(s0), nsteps, W, None if exact else WenoControl("detach"), q0=q0)
+    Jt.backward()
+    ref = q0.grad.detach()
+    gq = gq.cpu()
+    for v in range(4):
+        e = float((gq[v] - ref[v]).abs().max() / ref[v].abs().max())
+        assert e < 1e-9, (v, e)
+
+
+def test_adjoint_refuses_a_moving_body():
+    from dataclasses import replace
+    from paper_2603_11102_amd._lib import GKS_E_UNSUPPORTED, GksError
+    from synth.cases import IbmMotion
+    cfg = _body_case()
+    ib = replace(cfg.ibm, vel=None, motion=IbmMotion(center=cfg.rotor.hub, velocity=(0.0, 0.0, 0.0),
+                                                     omega=(0.0, 0.0, 0.1)))
+    cfg = cfg.with_(ibm=ib)
+    print_case("adjoint-moving-body-refused", grid=(20, 20, 20))
+    s, _, _ = _gpu_window(cfg, np.ones(cfg.rotor.n_act), 1)
+    with pytest.raises(GksError) as e:
+        s.adjoint(1, W)
+    assert e.value.code == GKS_E_UNSUPPORTED

@@ -66,3 +66,59 @@ def test_frozen_weights_close_to_true_derivative(case):
     rel = float((gf - gt).norm() / gt.norm())
     print(f"frozen-weight gradient error (relative L2): {rel:.3e}")
     assert rel < 1e-2
+
+
+def _body_case(case):
+    """The 20^3 rotor box with the tower and nacelle behind the rotor, its points at rest but given a
+    prescribed velocity (a moving surface), so that the forcing targets a non-zero v-bar."""
+    from dataclasses import replace
+    from synth.cases import tower_and_nacelle
+    ib = tower_and_nacelle(case.rotor.hub, 1.0, case.dx, spacing=0.5 * case.dx, z_ground=2.0 * case.dx)
+    rng = np.random.default_rng(7)
+    ib = replace(ib, vel=0.2 * rng.standard_normal((ib.n, 3)))
+    return case.with_(ibm=ib)
+
+
+def test_forcing_transpose_is_the_closed_form(case):
+    # the S direct-forcing iterations are affine per cell: m_S = c m + (1 - c) rho v-bar with
+    # c = (1 - V-bar/|Omega|)^S, so the reverse mode through ibm_apply must give lambda_m c and
+    # lambda_rho + (1 - c) v-bar . lambda_m at the forced cells and leave the rest unchanged
+    from oracle.gks_oracle import ibm_apply, ibm_setup
+    cfg = _body_case(case)
+    cache = ibm_setup(cfg, cfg.ibm)
+    rng = np.random.default_rng(3)
+    Q = torch.tensor(cfg.q0).clone().requires_grad_(True)
+    lam = torch.tensor(rng.standard_normal(cfg.q0.shape))
+    iters, dt = 3, 1e-3
+    Qn, _ = ibm_apply(Q, dt, cfg, cache, iters)
+    (g,) = torch.autograd.grad(Qn, Q, lam)
+    ref = lam.clone()
+    i, j, k = (cache.vbar_index[:, a] for a in range(3))
+    c = (1.0 - cache.vbar / cache.vol) ** iters
+    lm = lam[1:, k, j, i]
+    ref[1:, k, j, i] = lm * torch.tensor(c)
+    ref[0, k, j, i] = lam[0, k, j, i] + torch.tensor(1.0 - c) * (torch.tensor(cache.vbar_vel.T) * lm).sum(0)
+    assert len(cache.vbar) > 50 and np.abs(cache.vbar_vel).max() > 0.01
+    assert torch.allclose(g, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_body_at_rest_field_gradient_matches_frozen_finite_differences(case):
+    # the whole window with the forced body: reverse mode against central differences of the forward
+    # that replays the recorded WENO weights, along a random direction of the initial field
+    cfg = _body_case(case)
+    rng = np.random.default_rng(4)
+    n = cfg.rotor.n_act
+    s0 = 1.0 + 0.1 * rng.standard_normal(n)
+    q0 = torch.tensor(cfg.q0).clone().requires_grad_(True)
+    J, _ = rotor_objective(cfg, torch.tensor(s0), NSTEPS, W, WenoControl("detach"), q0=q0)
+    J.backward()
+    dq = torch.tensor(rng.standard_normal(cfg.q0.shape))
+    dq[0] *= 0.01
+    fd = _frozen_fd(cfg, s0, np.zeros(n), 1e-4, q0=torch.tensor(cfg.q0), dq=dq)
+    ad = float((q0.grad * dq).sum())
+    assert abs(fd - ad) < 1e-7 * abs(ad), (fd, ad)
+    # and in the force scalings
+    _, g = rotor_gradient(cfg, s0, NSTEPS, W, frozen=True)
+    v = rng.standard_normal(n)
+    fd = _frozen_fd(cfg, s0, v, 1e-3)
+    assert abs(fd - float(g.numpy() @ v)) < 1e-8 * abs(fd)
