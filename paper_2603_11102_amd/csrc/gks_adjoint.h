@@ -4,12 +4,15 @@
 // forward values (frozen, the default) or differentiated too (exact). Per face direction and stage
 // operator the transpose is computed in gather form, without atomics, in four passes over buffers in
 // the adjoint workspace:
-//   A  recompute the forward face pipeline, store the coefficients of every WENO evaluation (frozen:
-//      its weights; exact: its Jacobian row) and the adjoints of the Gauss-point inputs (q^L, q^R,
-//      dQ/dn, dQ/dt1, dQ/dt2) from the flux seeds;
+//   A  recompute the forward face pipeline, store the inputs of the tangential WENO evaluations (the
+//      normal face values q^L, q^R and the t1 line values q^L_m, q^R_m) and the adjoints of the
+//      Gauss-point inputs (q^L, q^R, dQ/dn, dQ/dt1, dQ/dt2) from the flux seeds;
 //   B  transpose of the t2 sweep (gather over the five faces whose stencils hold a t1 line value);
 //   C  transpose of the t1 sweep (gather over five positions) and of C = (q^L + q^R)/2;
 //   D  transpose of the normal reconstruction into the padded cell adjoint;
+// B, C and D rebuild the coefficients of the WENO evaluations they transpose (frozen: the weights;
+// exact: the Jacobian row) from those stored inputs, or from the field for the normal evaluations, with
+// the recompute's own routine on the same values, so the coefficients are bitwise the recompute's;
 // then the transpose of the ghost-cell fill folds ghost adjoints into interior cells.
 #pragma once
 
@@ -25,9 +28,8 @@ struct AdjFaceArgs {
     const double* mu0[4];   // seed of L (interior, local order), stage 1 only
     const double* mu1[4];   // seed of L_t
     double* gpbar;          // [80][nface]
-    double* w_t2;           // [32 NW][nface], NW = 2 frozen weights (w0, w2) or 5 Jacobian entries per evaluation
-    double* w_t1;           // [16 NW][nt1pos]
-    double* w_n;            // [8 NW][nnpos]
+    double* t1v;            // [16][nt1pos]: t1 line values q^L_m, q^R_m, index (v * 2 + side) * 2 + m
+    double* fv;             // [8][nnpos]: normal face values q^L, q^R, index v * 2 + side
     double* t1bar;          // [40][nt1pos]
     double* fabar;          // [12][nnpos]
     double* acc[4];         // padded cell adjoint accumulator (LOCAL order)
@@ -55,9 +57,8 @@ struct AdjBuffers {
     double* mu0[4];      // interior seeds
     double* mu1[4];
     double* gpbar;
-    double* w_t2;
-    double* w_t1;
-    double* w_n;
+    double* t1v;
+    double* fv;
     double* t1bar;
     double* fabar;
     double* pt;          // per-point scratch of the ALM adjoint: [16][n_act]

@@ -26,9 +26,21 @@ __device__ __forceinline__ long long n_ix(const AdjFaceArgs& a, int f, int jx, i
     return ((long long)f * (a.n_t2 + 4) + (kx + 2)) * (a.n_t1 + 4) + (jx + 2);
 }
 
-// Coefficient of stencil cell r in a WENO evaluation on `side` from its stored coefficients: the frozen
-// weights (stored as w0 and w2; w1 = 1 - w0 - w2) expanded over the sub-stencils, or (EXACT) the stored
-// Jacobian entry.
+// Coefficients of one WENO evaluation on `side` (stencil q, nonlinear weights w, value v): the frozen
+// weights w0 and w2 (w1 = 1 - w0 - w2 is rebuilt where they are used) or (EXACT) the Jacobian row.
+template <bool EXACT>
+__device__ __forceinline__ void weno_coefs(int side, const double q[5], double eps, const double w[3], double v,
+                                           double* out) {
+    if constexpr (EXACT) {
+        weno_jacobian(side, q, eps, w, v, out);
+    } else {
+        out[0] = w[0];
+        out[1] = w[2];
+    }
+}
+
+// Coefficient of stencil cell r in a WENO evaluation on `side` from its coefficients: the frozen weights
+// expanded over the sub-stencils, or (EXACT) the Jacobian entry.
 template <bool EXACT>
 __device__ __forceinline__ double wcoef(int side, const double* c, int r) {
     if constexpr (EXACT) {
@@ -43,16 +55,14 @@ __device__ __forceinline__ double wcoef(int side, const double* c, int r) {
 
 // ------------------------------------------------------------------------------------------------
 // pass A: recompute the face pipeline of one direction (the forward's 16 x 8 face tiles of 256 threads,
-// one wave per SIMD so that the FP64 state fits the unified register file), store the coefficients of
-// every WENO evaluation (frozen: its three nonlinear weights; EXACT: its Jacobian row over the five
-// stencil cells, the weights differentiated too) and, per face and Gauss point, the adjoints of the
-// Gauss-point inputs from the reverse of the flux (seeds Fbar(f) = (mu(f) - mu(f-1)) / h)
+// one wave per SIMD so that the FP64 state fits the unified register file), store the inputs of the
+// tangential WENO evaluations (normal face values, t1 line values) and, per face and Gauss point, the
+// adjoints of the Gauss-point inputs from the reverse of the flux (seeds Fbar(f) = (mu(f) - mu(f-1)) / h)
 // ------------------------------------------------------------------------------------------------
-template <int STAGE, bool EXACT>
+template <int STAGE>
 __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(const AdjFaceArgs a) {
     constexpr bool NEED_F0 = (STAGE == 1);
     constexpr int T2 = FaceTile<double>::T2, X2 = T2 + 4, NTH = FaceTile<double>::THREADS;
-    constexpr int NW = EXACT ? 5 : 2;
     static_assert(EXT1 * X2 <= NTH && 2 * TILE1 * T2 == NTH && TILE1 * X2 <= NTH, "thread roles");
     __shared__ double s_nrm[4][X2][EXT1];
     __shared__ double s_t1[5][X2][TILE1][2];
@@ -85,17 +95,6 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
     const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
     const bool face_ok = (j0 + fj < a.n_t1) && (k0 + fk < a.n_t2);
 
-    // coefficients of one WENO evaluation: the weights, or the Jacobian row
-    auto coefs = [&](int side, const double q[5], const double w[3], double v, double out[NW]) {
-        if constexpr (EXACT) {
-            weno_jacobian(side, q, eps, w, v, out);
-        } else {
-            // the weights sum to one: w1 is rebuilt from w0 and w2 where they are used
-            out[0] = w[0];
-            out[1] = w[2];
-        }
-    };
-
     double ring[4][5];
     double carry[4];
     for (int v = 0; v < 4; ++v) {
@@ -111,12 +110,6 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
             double right, left, wr[3], wl[3];
             weno_faces_w<double>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left, wr, wl);
             carry[v] = right;
-            if (col_st) {
-                double cf[NW];
-                coefs(0, ring[v], wr, right, cf);
-                const long long p = n_ix(a, f0, jc, kc);
-                for (int kk = 0; kk < NW; ++kk) a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p] = cf[kk];
-            }
         }
     }
 
@@ -143,15 +136,10 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                 s_nrm[3][c2][c1] = 0.5 * (qL + left);
                 carry[v] = right;
                 if (col_st) {
-                    double cf[NW];
+                    // the inputs of the t1 WENO evaluations (pass C rebuilds their coefficients)
                     const long long p = n_ix(a, f, jc, kc);
-                    coefs(1, ring[v], wl, left, cf);
-                    for (int kk = 0; kk < NW; ++kk) a.w_n[((v * 2 + 1) * NW + kk) * a.nnpos + p] = cf[kk];
-                    if (f + 1 <= f1) {
-                        const long long p1 = n_ix(a, f + 1, jc, kc);
-                        coefs(0, ring[v], wr, right, cf);
-                        for (int kk = 0; kk < NW; ++kk) a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p1] = cf[kk];
-                    }
+                    a.fv[(v * 2 + 0) * a.nnpos + p] = qL;
+                    a.fv[(v * 2 + 1) * a.nnpos + p] = left;
                 }
             }
         };
@@ -171,13 +159,9 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                     s_t1[side][tk][tj][0] = vm;
                     s_t1[side][tk][tj][1] = vp;
                     if (t1_st) {
-                        double cm_[NW], cp_[NW];
-                        coefs(2, x[side], wm, vm, cm_);
-                        coefs(3, x[side], wp, vp, cp_);
-                        for (int kk = 0; kk < NW; ++kk) {
-                            a.w_t1[(((v * 2 + side) * 2 + 0) * NW + kk) * a.nt1pos + p] = cm_[kk];
-                            a.w_t1[(((v * 2 + side) * 2 + 1) * NW + kk) * a.nt1pos + p] = cp_[kk];
-                        }
+                        // the inputs of the t2 WENO evaluations (pass B rebuilds their coefficients)
+                        a.t1v[((v * 2 + side) * 2 + 0) * a.nt1pos + p] = vm;
+                        a.t1v[((v * 2 + side) * 2 + 1) * a.nt1pos + p] = vp;
                     }
                 }
                 quartic_gauss_value<double>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
@@ -196,20 +180,10 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                 for (int q = 0; q < 5; ++q)
                     for (int r = 0; r < 5; ++r) y[q][r] = s_t1[q][fk + r][fj][m];
                 double vm, vp, wm[3], wp[3];
-                const long long fi = face_ok ? face_ix(a, f, j0 + fj, k0 + fk) : 0;
                 for (int side = 0; side < 2; ++side) {
                     weno_gauss_w<double>(y[side][0], y[side][1], y[side][2], y[side][3], y[side][4], eps, vm, vp, wm, wp);
                     put(v, 0, side, vm);
                     put(v, 1, side, vp);
-                    if (face_ok) {
-                        double cm_[NW], cp_[NW];
-                        coefs(2, y[side], wm, vm, cm_);
-                        coefs(3, y[side], wp, vp, cp_);
-                        for (int kk = 0; kk < NW; ++kk) {
-                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 0) * NW + kk) * a.nface + fi] = cm_[kk];
-                            a.w_t2[((((v * 2 + m) * 2 + side) * 2 + 1) * NW + kk) * a.nface + fi] = cp_[kk];
-                        }
-                    }
                 }
                 quartic_gauss_value<double>(y[2][0], y[2][1], y[2][2], y[2][3], y[2][4], vm, vp);
                 put(v, 0, 2, vm);
@@ -286,7 +260,8 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
     // contiguous runs of every plane. The thread walks the faces of its chunk in ascending t2 order and
     // loads each once: face k adds its terms to the five outputs kx = k-2 .. k+2 it reaches (slot r =
     // kx - k + 2 of a ring), and output k-2 is stored after face k. Every output sums its faces in
-    // ascending t2 order, Gauss point n inner.
+    // ascending t2 order, Gauss point n inner. The coefficients of face k's two t2 WENO evaluations
+    // (of q^L_m and q^R_m) are rebuilt from the t1 line values at kx = k-2 .. k+2, kept in a second ring.
     const int nout = a.n_t2 + 4;  // outputs kx = -2 .. n_t2 + 1
     const int nchunk = (nout + T2_CHUNK - 1) / T2_CHUNK;
     const long long total = (long long)(a.n_n + 1) * nchunk * 8 * a.n_t1;
@@ -299,32 +274,54 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
     const int kx_lo = (int)(r_ % nchunk) * T2_CHUNK - 2;
     const int kx_hi = min(kx_lo + T2_CHUNK, a.n_t2 + 2);
     const int f = (int)(r_ / nchunk);
+    const int v = vm >> 1, m = vm & 1;
+    auto t1val = [&](int side, int kx) -> double {
+        return (kx >= -2 && kx < a.n_t2 + 2) ? a.t1v[((v * 2 + side) * 2 + m) * a.nt1pos + t1_ix(a, f, j, kx)] : 0.0;
+    };
+    // y[side][r]: t1 line value at kx = k - 2 + r for the face k of the current step
+    double y[2][5];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        y[side][0] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[side][r + 1] = t1val(side, kx_lo - 4 + r);
+    }
     double acc[5][5];
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[r][q] = 0.0;
     for (int k = kx_lo - 2; k < kx_hi + 2; ++k) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[side][r] = y[side][r + 1];
+            y[side][4] = t1val(side, k + 2);
+        }
         if (k >= 0 && k < a.n_t2) {
             const long long fi = face_ix(a, f, j, k);
+            // coefficients [side][Gauss point n] of the face's evaluations, as the recompute formed them
+            double cw[2][2][NW];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                double gm, gp, wm[3], wp[3];
+                weno_gauss_w<double>(y[side][0], y[side][1], y[side][2], y[side][3], y[side][4], a.eps, gm, gp, wm, wp);
+                weno_coefs<EXACT>(2, y[side], a.eps, wm, gm, cw[side][0]);
+                weno_coefs<EXACT>(3, y[side], a.eps, wp, gp, cw[side][1]);
+            }
 #pragma unroll
             for (int n = 0; n < 2; ++n) {
                 const int side = n == 0 ? 2 : 3;
                 const int sg = n == 0 ? -1 : 1;
                 const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
-                double wL[NW], wR[NW], gv[5];
-#pragma unroll
-                for (int kk = 0; kk < NW; ++kk) {
-                    wL[kk] = a.w_t2[(((vm * 2 + 0) * 2 + n) * NW + kk) * a.nface + fi];
-                    wR[kk] = a.w_t2[(((vm * 2 + 1) * 2 + n) * NW + kk) * a.nface + fi];
-                }
+                double gv[5];
 #pragma unroll
                 for (int q = 0; q < 5; ++q) gv[q] = a.gpbar[gbase + q * a.nface];
 #pragma unroll
                 for (int r = 0; r < 5; ++r) {
                     const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h2;
-                    acc[r][0] += wcoef<EXACT>(side, wL, r) * gv[0];
-                    acc[r][1] += wcoef<EXACT>(side, wR, r) * gv[1];
+                    acc[r][0] += wcoef<EXACT>(side, cw[0][n], r) * gv[0];
+                    acc[r][1] += wcoef<EXACT>(side, cw[1][n], r) * gv[1];
                     acc[r][2] += cv * gv[2];
                     acc[r][3] += cv * gv[3];
                     acc[r][4] += cd * gv[4];
@@ -357,12 +354,15 @@ constexpr int C_SEG = 132;      // outputs of one workgroup along t1 (a whole ro
 template <bool EXACT>
 __global__ void __launch_bounds__(C_THREADS) adj_t1_kernel(const AdjFaceArgs a) {
     constexpr int NW = EXACT ? 5 : 2;
-    constexpr int NV = 10 + 4 * NW;  // per t1 position: t1bar[m][q] and the weights [side][m][kk]
+    constexpr int NV = 10 + 4 * NW;  // per t1 position: t1bar[m][q] and the coefficients [side][m][kk]
     constexpr int NP = C_SEG + 4;    // t1 positions a segment reads
     // one workgroup per (segment of C_SEG t1 outputs incl. halo, variable, t2 position incl. halo, face):
-    // the t1 line values and weights of the segment's positions are staged in LDS, each loaded once,
-    // and every output gathers its five positions from there (ascending t1, Gauss line m inner)
+    // the t1 line adjoints of the segment's positions and the normal face values around them are
+    // staged in LDS, each loaded once; the coefficients of every position's t1 WENO evaluations are
+    // rebuilt from the five face values of its stencil, and every output gathers its five positions
+    // from there (ascending t1, Gauss line m inner)
     __shared__ double s_v[NV][NP];
+    __shared__ double s_f[2][NP + 4];  // normal face values q^L, q^R at t1 cells seg0 - 4 + l
     const int nseg = (a.n_t1 + 4 + C_SEG - 1) / C_SEG;
     long long r_ = blockIdx.x;
     const int seg = (int)(r_ % nseg);
@@ -372,17 +372,45 @@ __global__ void __launch_bounds__(C_THREADS) adj_t1_kernel(const AdjFaceArgs a) 
     const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
     const int f = (int)(r_ / (a.n_t2 + 4));
     const int seg0 = -2 + seg * C_SEG;
+    for (int l = threadIdx.x; l < NP + 4; l += C_THREADS) {
+        const int jx = seg0 - 4 + l;
+        const bool in = jx >= -2 && jx < a.n_t1 + 2;
+        const long long p = in ? n_ix(a, f, jx, kx) : 0;
+        s_f[0][l] = in ? a.fv[(v * 2 + 0) * a.nnpos + p] : 0.0;
+        s_f[1][l] = in ? a.fv[(v * 2 + 1) * a.nnpos + p] : 0.0;
+    }
     for (int l = threadIdx.x; l < NP; l += C_THREADS) {
         const int j = seg0 - 2 + l;
         const bool in = j >= 0 && j < a.n_t1;
         const long long p = in ? t1_ix(a, f, j, kx) : 0;
-        for (int m = 0; m < 2; ++m) {
+        for (int m = 0; m < 2; ++m)
             for (int q = 0; q < 5; ++q)
                 s_v[m * 5 + q][l] = in ? a.t1bar[(long long)((v * 2 + m) * 5 + q) * a.nt1pos + p] : 0.0;
-            for (int side = 0; side < 2; ++side)
-                for (int kk = 0; kk < NW; ++kk)
-                    s_v[10 + (side * 2 + m) * NW + kk][l] =
-                        in ? a.w_t1[(((v * 2 + side) * 2 + m) * NW + kk) * a.nt1pos + p] : 0.0;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < NP; l += C_THREADS) {
+        const int j = seg0 - 2 + l;
+        const bool in = j >= 0 && j < a.n_t1;
+        for (int side = 0; side < 2; ++side) {
+            // stencil of position j: face values at t1 cells j - 2 .. j + 2
+            double x[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r) x[r] = s_f[side][l + r];
+            double cm[NW], cp[NW];
+            if (in) {
+                double gm, gp, wm[3], wp[3];
+                weno_gauss_w<double>(x[0], x[1], x[2], x[3], x[4], a.eps, gm, gp, wm, wp);
+                weno_coefs<EXACT>(2, x, a.eps, wm, gm, cm);
+                weno_coefs<EXACT>(3, x, a.eps, wp, gp, cp);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < NW; ++kk) cm[kk] = cp[kk] = 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < NW; ++kk) {
+                s_v[10 + (side * 2 + 0) * NW + kk][l] = cm[kk];
+                s_v[10 + (side * 2 + 1) * NW + kk][l] = cp[kk];
+            }
         }
     }
     __syncthreads();
@@ -433,6 +461,9 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
     // normal); the t1 position is the fastest index. The thread walks its cells in order with the six
     // faces f = i-2 .. i+3 that reach cell i in registers (slot s holds face i-2+s), loading each face
     // once, and sums per cell the q^L terms, then the q^R terms, then the D terms, each in ascending f.
+    // The coefficients of the normal WENO evaluations are rebuilt from the field as the recompute's
+    // column march formed them: the evaluation on cell c (stencil c-2 .. c+2) gives q^R of face c and
+    // q^L of face c+1, so a five-cell window and the carried q^L coefficients suffice.
     const int ncell = a.n_n + 6;  // padded cells i = -3 .. n_n + 2
     const int nchunk = (ncell + N_CHUNK - 1) / N_CHUNK;
     const long long total = (long long)nchunk * 4 * (a.n_t2 + 4) * (a.n_t1 + 4);
@@ -445,21 +476,42 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
     const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
     const int c = (int)(r_ / (a.n_t2 + 4));
     const int i_lo = -3 + c * N_CHUNK, i_hi = min(i_lo + N_CHUNK, a.n_n + 3);
+    const long long colq = a.pad0 + (long long)jx * a.st_t1 + (long long)kx * a.st_t2;
+    auto cell = [&](int i) -> double { return (i >= -3 && i < a.n_n + 3) ? a.q[v][colq + (long long)i * a.st_n] : 0.0; };
     double wl[6][NW], wr[6][NW], fb[6][3];
     bool ok[6];
-    auto load = [&](int s, int f) {
-        ok[s] = f >= 0 && f <= a.n_n;
-        const long long p = ok[s] ? n_ix(a, f, jx, kx) : 0;
+    // the next face to enter the window, the field cells fn-2 .. fn+2 and the q^L coefficients of face fn
+    int fn = i_lo - 2;
+    double win[5], carryL[NW];
+    {
+        double s5[5];
 #pragma unroll
-        for (int kk = 0; kk < NW; ++kk) {
-            wl[s][kk] = ok[s] ? a.w_n[((v * 2 + 0) * NW + kk) * a.nnpos + p] : 0.0;
-            wr[s][kk] = ok[s] ? a.w_n[((v * 2 + 1) * NW + kk) * a.nnpos + p] : 0.0;
-        }
+        for (int r = 0; r < 5; ++r) s5[r] = cell(fn - 3 + r);
+        double right, left, w_r[3], w_l[3];
+        weno_faces_w<double>(s5[0], s5[1], s5[2], s5[3], s5[4], a.eps, right, left, w_r, w_l);
+        weno_coefs<EXACT>(0, s5, a.eps, w_r, right, carryL);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) win[r] = s5[r + 1];
+        win[4] = cell(fn + 2);
+    }
+    auto enter = [&](int s) {
+        ok[s] = fn >= 0 && fn <= a.n_n;
+        double right, left, w_r[3], w_l[3];
+        weno_faces_w<double>(win[0], win[1], win[2], win[3], win[4], a.eps, right, left, w_r, w_l);
+#pragma unroll
+        for (int kk = 0; kk < NW; ++kk) wl[s][kk] = carryL[kk];
+        weno_coefs<EXACT>(1, win, a.eps, w_l, left, wr[s]);
+        weno_coefs<EXACT>(0, win, a.eps, w_r, right, carryL);
+        const long long p = ok[s] ? n_ix(a, fn, jx, kx) : 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) fb[s][q] = ok[s] ? a.fabar[(long long)(v * 3 + q) * a.nnpos + p] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) win[r] = win[r + 1];
+        win[4] = cell(fn + 3);
+        ++fn;
     };
 #pragma unroll
-    for (int s = 0; s < 6; ++s) load(s, i_lo - 2 + s);
+    for (int s = 0; s < 6; ++s) enter(s);
     const double cD[4] = {1.0 / 12.0, -15.0 / 12.0, 15.0 / 12.0, -1.0 / 12.0};
     for (int i = i_lo; i < i_hi; ++i) {
         double bar = 0.0;
@@ -478,18 +530,20 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
         const long long q = a.pad0 + (long long)i * a.st_n + (long long)jx * a.st_t1 + (long long)kx * a.st_t2;
         a.acc[v][q] += bar;
         // slide the window: face i + 4 enters
+        if (i + 1 < i_hi) {
 #pragma unroll
-        for (int s = 0; s < 5; ++s) {
-            ok[s] = ok[s + 1];
+            for (int s = 0; s < 5; ++s) {
+                ok[s] = ok[s + 1];
 #pragma unroll
-            for (int kk = 0; kk < NW; ++kk) {
-                wl[s][kk] = wl[s + 1][kk];
-                wr[s][kk] = wr[s + 1][kk];
+                for (int kk = 0; kk < NW; ++kk) {
+                    wl[s][kk] = wl[s + 1][kk];
+                    wr[s][kk] = wr[s + 1][kk];
+                }
+#pragma unroll
+                for (int qq = 0; qq < 3; ++qq) fb[s][qq] = fb[s + 1][qq];
             }
-#pragma unroll
-            for (int qq = 0; qq < 3; ++qq) fb[s][qq] = fb[s + 1][qq];
+            enter(5);
         }
-        if (i + 1 < i_hi) load(5, i + 4);
     }
 }
 
@@ -499,8 +553,8 @@ hipError_t launch_adj_passes(const AdjFaceArgs& a, int stage, hipStream_t s) {
     const long long blocks = ((long long)a.tiles_t1 * a.tiles_t2 * nchunks + 7) / 8 * 8;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 fgrid((unsigned)blocks), fblock(FaceTile<double>::THREADS);
-    if (stage == 1) hipLaunchKernelGGL((adj_face_kernel<1, EXACT>), fgrid, fblock, 0, s, a);
-    else hipLaunchKernelGGL((adj_face_kernel<2, EXACT>), fgrid, fblock, 0, s, a);
+    if (stage == 1) hipLaunchKernelGGL((adj_face_kernel<1>), fgrid, fblock, 0, s, a);
+    else hipLaunchKernelGGL((adj_face_kernel<2>), fgrid, fblock, 0, s, a);
     const long long nB = (long long)(a.n_n + 1) * a.n_t1 * ((a.n_t2 + 4 + T2_CHUNK - 1) / T2_CHUNK) * 8;
     hipLaunchKernelGGL((adj_t2_kernel<EXACT>), dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
     const long long nC = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 4 * ((a.n_t1 + 4 + C_SEG - 1) / C_SEG);
@@ -858,11 +912,9 @@ void adjoint_carve(char* base, int nx, int ny, int nz, int n_act, AdjBuffers* b,
         nn = std::max(nn, a0 * (a1 + 4) * (a2 + 4));
     }
     b->gpbar = reinterpret_cast<double*>(take(80 * nface * 8));
-    // WENO coefficients: 5 per evaluation (the Jacobian rows of the exact mode; the frozen weights use 3)
-    b->w_t2 = reinterpret_cast<double*>(take(160 * nface * 8));
-    b->w_t1 = reinterpret_cast<double*>(take(80 * nt1 * 8));
+    b->t1v = reinterpret_cast<double*>(take(16 * nt1 * 8));
     b->t1bar = reinterpret_cast<double*>(take(40 * nt1 * 8));
-    b->w_n = reinterpret_cast<double*>(take(40 * nn * 8));
+    b->fv = reinterpret_cast<double*>(take(8 * nn * 8));
     b->fabar = reinterpret_cast<double*>(take(12 * nn * 8));
     b->pt = reinterpret_cast<double*>(take(16 * (size_t)std::max(n_act, 1) * 8));
     *total = off;

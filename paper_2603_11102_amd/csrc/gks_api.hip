@@ -466,9 +466,8 @@ AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4],
         a.acc[v] = B.acc[gv];
     }
     a.gpbar = B.gpbar;
-    a.w_t2 = B.w_t2;
-    a.w_t1 = B.w_t1;
-    a.w_n = B.w_n;
+    a.t1v = B.t1v;
+    a.fv = B.fv;
     a.t1bar = B.t1bar;
     a.fabar = B.fabar;
     a.n_n = c->g.n[ax[0]];
