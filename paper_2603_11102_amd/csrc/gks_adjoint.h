@@ -7,8 +7,9 @@
 //   A  recompute the forward face pipeline, store the inputs of the tangential WENO evaluations (the
 //      normal face values q^L, q^R and the t1 line values q^L_m, q^R_m) and the adjoints of the
 //      Gauss-point inputs (q^L, q^R, dQ/dn, dQ/dt1, dQ/dt2) from the flux seeds;
-//   B  transpose of the t2 sweep (gather over the five faces whose stencils hold a t1 line value);
-//   C  transpose of the t1 sweep (gather over five positions) and of C = (q^L + q^R)/2;
+//   B  transpose of the t2 sweep (gather over the five faces whose stencils hold a t1 line value),
+//   C  then, row by row in the same kernel with the t1 line adjoints in LDS, transpose of the t1 sweep
+//      (gather over five positions) and of C = (q^L + q^R)/2;
 //   D  transpose of the normal reconstruction into the padded cell adjoint;
 // B, C and D rebuild the coefficients of the WENO evaluations they transpose (frozen: the weights;
 // exact: the Jacobian row) from those stored inputs, or from the field for the normal evaluations, with
@@ -30,7 +31,6 @@ struct AdjFaceArgs {
     double* gpbar;          // [80][nface]
     double* t1v;            // [16][nt1pos]: t1 line values q^L_m, q^R_m, index (v * 2 + side) * 2 + m
     double* fv;             // [8][nnpos]: normal face values q^L, q^R, index v * 2 + side
-    double* t1bar;          // [40][nt1pos]
     double* fabar;          // [12][nnpos]
     double* acc[4];         // padded cell adjoint accumulator (LOCAL order)
     int n_n, n_t1, n_t2;
@@ -59,7 +59,6 @@ struct AdjBuffers {
     double* gpbar;
     double* t1v;
     double* fv;
-    double* t1bar;
     double* fabar;
     double* pt;          // per-point scratch of the ALM adjoint: [16][n_act]
 };

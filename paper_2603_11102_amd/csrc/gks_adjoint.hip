@@ -248,59 +248,110 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
 }
 
 // ------------------------------------------------------------------------------------------------
-// pass B: transpose of the t2 sweep -> adjoints of the t1 line values (q^L_m, q^R_m, D_m, Ct1_m, C_m)
+// passes B and C fused: the transpose of the t2 sweep produces one row (fixed t2 position) of t1 line
+// adjoints at a time into LDS, and the transpose of the t1 sweep and of C = (q^L + q^R)/2 consumes it
+// there, so the t1 line adjoints never reach HBM
 // ------------------------------------------------------------------------------------------------
-constexpr int T2_CHUNK = 64;  // consecutive t2 outputs per thread in pass B
+constexpr int BC_ROWS = 64;  // t2 rows (outputs kx) per workgroup
+
+// Work split of the fused pass along t1 for n_t1 cells: outputs jx per segment, t1 positions per
+// segment at most (the threads are two per position: Gauss lines m = 0, 1), segments per row.
+struct BcSplit {
+    int seg, npt, nseg;
+};
+inline BcSplit bc_split(int n_t1) {
+    BcSplit b;
+    // at most 128 positions (LDS of the exact mode: 33 KB)
+    if (n_t1 <= 128) {  // one segment: all outputs -2 .. n_t1 + 1 from all positions 0 .. n_t1 - 1
+        b.seg = n_t1 + 4;
+        b.npt = (n_t1 + 31) / 32 * 32;
+    } else {  // segments of 124 outputs read 128 positions
+        b.seg = 124;
+        b.npt = 128;
+    }
+    b.nseg = (n_t1 + 4 + b.seg - 1) / b.seg;
+    return b;
+}
 
 template <bool EXACT>
-__global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
+__global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int seg_len, int npt) {
     constexpr int NW = EXACT ? 5 : 2;
-    // one thread per (t1 line position, variable, Gauss line m, chunk of T2_CHUNK consecutive t2
-    // positions incl. halo, face); the t1 position is the fastest index so that a wave reads
-    // contiguous runs of every plane. The thread walks the faces of its chunk in ascending t2 order and
-    // loads each once: face k adds its terms to the five outputs kx = k-2 .. k+2 it reaches (slot r =
-    // kx - k + 2 of a ring), and output k-2 is stored after face k. Every output sums its faces in
-    // ascending t2 order, Gauss point n inner. The coefficients of face k's two t2 WENO evaluations
-    // (of q^L_m and q^R_m) are rebuilt from the t1 line values at kx = k-2 .. k+2, kept in a second ring.
-    const int nout = a.n_t2 + 4;  // outputs kx = -2 .. n_t2 + 1
-    const int nchunk = (nout + T2_CHUNK - 1) / T2_CHUNK;
-    const long long total = (long long)(a.n_n + 1) * nchunk * 8 * a.n_t1;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int j = (int)(t % a.n_t1);
-    long long r_ = t / a.n_t1;
-    const int vm = (int)(r_ % 8);  // v * 2 + m
-    r_ /= 8;
-    const int kx_lo = (int)(r_ % nchunk) * T2_CHUNK - 2;
-    const int kx_hi = min(kx_lo + T2_CHUNK, a.n_t2 + 2);
-    const int f = (int)(r_ / nchunk);
-    const int v = vm >> 1, m = vm & 1;
+    // one workgroup per (row chunk of BC_ROWS t2 positions incl. halo, t1 segment, variable, face) of
+    // 2 npt threads. Thread (jl, m), jl = tid % npt, m = tid / npt, runs the t2 transpose of t1 position
+    // j = jlo + jl, Gauss line m: it walks the faces of the chunk in ascending t2 order, each face adding
+    // its terms to the five rows kx = k-2 .. k+2 it reaches (a ring), the face's two t2 WENO
+    // coefficients rebuilt from the t1 line values of its stencil (a second ring). When row kx = k-2 is
+    // complete it goes to LDS, and the workgroup transposes the t1 sweep of that row: the coefficients
+    // of every position's t1 WENO evaluations are rebuilt from the normal face values of its stencil,
+    // and every output jx gathers its five positions (ascending t1, Gauss line m inner). Sums are in
+    // the same fixed orders as the separate passes.
+    extern __shared__ double lds[];
+    double* const s_tb = lds;                        // [10][npt]: t1 line adjoints [m * 5 + q][position]
+    double* const s_w = s_tb + 10 * npt;             // [4 NW][npt]: coefficients [(side * 2 + m) * NW + kk]
+    double* const s_f = s_w + 4 * NW * npt;          // [2][npt + 4]: normal face values q^L, q^R
+    const int tid = threadIdx.x;
+    const int nrc = (a.n_t2 + 4 + BC_ROWS - 1) / BC_ROWS;
+    const int nseg = (a.n_t1 + 4 + seg_len - 1) / seg_len;
+    long long r_ = blockIdx.x;
+    const int rc = (int)(r_ % nrc);
+    r_ /= nrc;
+    const int seg = (int)(r_ % nseg);
+    r_ /= nseg;
+    const int v = (int)(r_ % 4);
+    const int f = (int)(r_ / 4);
+    const int kx_lo = -2 + rc * BC_ROWS, kx_hi = min(kx_lo + BC_ROWS, a.n_t2 + 2);
+    const int seg0 = -2 + seg * seg_len, seg1 = min(seg0 + seg_len, a.n_t1 + 2);  // outputs jx
+    const int jlo = max(0, seg0 - 2), jhi = min(a.n_t1, seg1 + 2);                 // positions j
+    const int npos = jhi - jlo;
+    const int jl = tid % npt, m = tid / npt;
+    const bool tb = jl < npos;
+    const int j = jlo + jl;
+    const int vm = v * 2 + m;
     auto t1val = [&](int side, int kx) -> double {
-        return (kx >= -2 && kx < a.n_t2 + 2) ? a.t1v[((v * 2 + side) * 2 + m) * a.nt1pos + t1_ix(a, f, j, kx)] : 0.0;
+        return (tb && kx >= -2 && kx < a.n_t2 + 2) ? a.t1v[((v * 2 + side) * 2 + m) * a.nt1pos + t1_ix(a, f, j, kx)]
+                                                   : 0.0;
     };
-    // y[side][r]: t1 line value at kx = k - 2 + r for the face k of the current step
-    double y[2][5];
+    // the adjoints of face k's Gauss-point inputs, [Gauss point n][quantity]
+    auto gp_in = [&](int k, double g[2][5]) {
+        const bool ok = tb && k >= 0 && k < a.n_t2;
+        const long long fi = ok ? face_ix(a, f, j, k) : 0;
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) g[n][q] = ok ? a.gpbar[(long long)((vm * 2 + n) * 5 + q) * a.nface + fi] : 0.0;
+    };
+    // software pipelining: the next face's inputs and the t1 line value two positions ahead are loaded
+    // one step before they are used
+    double y[2][5], ynext[2], gnext[2][5];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         y[side][0] = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) y[side][r + 1] = t1val(side, kx_lo - 4 + r);
+        ynext[side] = t1val(side, kx_lo);
     }
+    gp_in(kx_lo - 2, gnext);
     double acc[5][5];
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[r][q] = 0.0;
     for (int k = kx_lo - 2; k < kx_hi + 2; ++k) {
+        // ---- t2 transpose: face k of this thread's position
+        double gcur[2][5];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) gcur[n][q] = gnext[n][q];
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) y[side][r] = y[side][r + 1];
-            y[side][4] = t1val(side, k + 2);
+            y[side][4] = ynext[side];
+            ynext[side] = t1val(side, k + 3);
         }
-        if (k >= 0 && k < a.n_t2) {
-            const long long fi = face_ix(a, f, j, k);
-            // coefficients [side][Gauss point n] of the face's evaluations, as the recompute formed them
+        gp_in(k + 1, gnext);
+        if (tb && k >= 0 && k < a.n_t2) {
             double cw[2][2][NW];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
@@ -313,10 +364,7 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
             for (int n = 0; n < 2; ++n) {
                 const int side = n == 0 ? 2 : 3;
                 const int sg = n == 0 ? -1 : 1;
-                const long long gbase = (long long)((vm * 2 + n) * 5) * a.nface + fi;
-                double gv[5];
-#pragma unroll
-                for (int q = 0; q < 5; ++q) gv[q] = a.gpbar[gbase + q * a.nface];
+                const double* const gv = gcur[n];
 #pragma unroll
                 for (int r = 0; r < 5; ++r) {
                     const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h2;
@@ -328,12 +376,72 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
                 }
             }
         }
-        // output kx = k - 2 has all its faces now
-        const int kx = k - 2;
+        const int kx = k - 2;  // row kx has all its faces now
         if (kx >= kx_lo && kx < kx_hi) {
-            const long long p = t1_ix(a, f, j, kx);
+            // ---- t1 transpose of row kx
+            if (tb)
 #pragma unroll
-            for (int q = 0; q < 5; ++q) a.t1bar[(long long)(vm * 5 + q) * a.nt1pos + p] = acc[0][q];
+                for (int q = 0; q < 5; ++q) s_tb[(m * 5 + q) * npt + jl] = acc[0][q];
+            for (int l = tid; l < npos + 4; l += 2 * npt) {
+                const int jx = jlo - 2 + l;
+                const bool in = jx >= -2 && jx < a.n_t1 + 2;
+                const long long p = in ? n_ix(a, f, jx, kx) : 0;
+                s_f[l] = in ? a.fv[(v * 2 + 0) * a.nnpos + p] : 0.0;
+                s_f[(npt + 4) + l] = in ? a.fv[(v * 2 + 1) * a.nnpos + p] : 0.0;
+            }
+            __syncthreads();
+            {
+                // coefficients of position jl (side = the thread's m slot): stencil at t1 cells j-2 .. j+2
+                const int side = m;
+                if (tb) {
+                    double x[5];
+#pragma unroll
+                    for (int r = 0; r < 5; ++r) x[r] = s_f[side * (npt + 4) + jl + r];
+                    double gm, gp, wm[3], wp[3], cm[NW], cp[NW];
+                    weno_gauss_w<double>(x[0], x[1], x[2], x[3], x[4], a.eps, gm, gp, wm, wp);
+                    weno_coefs<EXACT>(2, x, a.eps, wm, gm, cm);
+                    weno_coefs<EXACT>(3, x, a.eps, wp, gp, cp);
+#pragma unroll
+                    for (int kk = 0; kk < NW; ++kk) {
+                        s_w[((side * 2 + 0) * NW + kk) * npt + jl] = cm[kk];
+                        s_w[((side * 2 + 1) * NW + kk) * npt + jl] = cp[kk];
+                    }
+                }
+            }
+            __syncthreads();
+            for (int o = tid; o < seg1 - seg0; o += 2 * npt) {
+                const int jx = seg0 + o;
+                double bar[3] = {0.0, 0.0, 0.0}, Cb = 0.0;
+                // positions jx - 2 .. jx + 2 in ascending order (stencil slot r = jx - jj + 2 descending)
+#pragma unroll
+                for (int r = 4; r >= 0; --r) {
+                    const int jj = jx - r + 2;
+                    if (jj < 0 || jj >= a.n_t1) continue;
+                    const int l = jj - jlo;
+#pragma unroll
+                    for (int mm = 0; mm < 2; ++mm) {
+                        const int side = mm == 0 ? 2 : 3;
+                        const int sg = mm == 0 ? -1 : 1;
+                        const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h1;
+                        double wL[NW], wR[NW];
+#pragma unroll
+                        for (int kk = 0; kk < NW; ++kk) {
+                            wL[kk] = s_w[((0 * 2 + mm) * NW + kk) * npt + l];
+                            wR[kk] = s_w[((1 * 2 + mm) * NW + kk) * npt + l];
+                        }
+                        bar[0] += wcoef<EXACT>(side, wL, r) * s_tb[(mm * 5 + 0) * npt + l];
+                        bar[1] += wcoef<EXACT>(side, wR, r) * s_tb[(mm * 5 + 1) * npt + l];
+                        bar[2] += cv * s_tb[(mm * 5 + 2) * npt + l];
+                        Cb += cd * s_tb[(mm * 5 + 3) * npt + l];
+                        Cb += cv * s_tb[(mm * 5 + 4) * npt + l];
+                    }
+                }
+                const long long p = n_ix(a, f, jx, kx);
+                a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[0] + 0.5 * Cb;
+                a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[1] + 0.5 * Cb;
+                a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[2];
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -341,111 +449,6 @@ __global__ void __launch_bounds__(256) adj_t2_kernel(const AdjFaceArgs a) {
             for (int q = 0; q < 5; ++q) acc[r][q] = acc[r + 1][q];
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[4][q] = 0.0;
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
-// pass C: transpose of the t1 sweep and of C = (q^L + q^R)/2 -> adjoints of q^L, q^R, D per face
-// position (tangential halo included)
-// ------------------------------------------------------------------------------------------------
-constexpr int C_THREADS = 128;  // threads per workgroup of pass C
-constexpr int C_SEG = 132;      // outputs of one workgroup along t1 (a whole row when n_t1 = 128)
-
-template <bool EXACT>
-__global__ void __launch_bounds__(C_THREADS) adj_t1_kernel(const AdjFaceArgs a) {
-    constexpr int NW = EXACT ? 5 : 2;
-    constexpr int NV = 10 + 4 * NW;  // per t1 position: t1bar[m][q] and the coefficients [side][m][kk]
-    constexpr int NP = C_SEG + 4;    // t1 positions a segment reads
-    // one workgroup per (segment of C_SEG t1 outputs incl. halo, variable, t2 position incl. halo, face):
-    // the t1 line adjoints of the segment's positions and the normal face values around them are
-    // staged in LDS, each loaded once; the coefficients of every position's t1 WENO evaluations are
-    // rebuilt from the five face values of its stencil, and every output gathers its five positions
-    // from there (ascending t1, Gauss line m inner)
-    __shared__ double s_v[NV][NP];
-    __shared__ double s_f[2][NP + 4];  // normal face values q^L, q^R at t1 cells seg0 - 4 + l
-    const int nseg = (a.n_t1 + 4 + C_SEG - 1) / C_SEG;
-    long long r_ = blockIdx.x;
-    const int seg = (int)(r_ % nseg);
-    r_ /= nseg;
-    const int v = (int)(r_ % 4);
-    r_ /= 4;
-    const int kx = (int)(r_ % (a.n_t2 + 4)) - 2;
-    const int f = (int)(r_ / (a.n_t2 + 4));
-    const int seg0 = -2 + seg * C_SEG;
-    for (int l = threadIdx.x; l < NP + 4; l += C_THREADS) {
-        const int jx = seg0 - 4 + l;
-        const bool in = jx >= -2 && jx < a.n_t1 + 2;
-        const long long p = in ? n_ix(a, f, jx, kx) : 0;
-        s_f[0][l] = in ? a.fv[(v * 2 + 0) * a.nnpos + p] : 0.0;
-        s_f[1][l] = in ? a.fv[(v * 2 + 1) * a.nnpos + p] : 0.0;
-    }
-    for (int l = threadIdx.x; l < NP; l += C_THREADS) {
-        const int j = seg0 - 2 + l;
-        const bool in = j >= 0 && j < a.n_t1;
-        const long long p = in ? t1_ix(a, f, j, kx) : 0;
-        for (int m = 0; m < 2; ++m)
-            for (int q = 0; q < 5; ++q)
-                s_v[m * 5 + q][l] = in ? a.t1bar[(long long)((v * 2 + m) * 5 + q) * a.nt1pos + p] : 0.0;
-    }
-    __syncthreads();
-    for (int l = threadIdx.x; l < NP; l += C_THREADS) {
-        const int j = seg0 - 2 + l;
-        const bool in = j >= 0 && j < a.n_t1;
-        for (int side = 0; side < 2; ++side) {
-            // stencil of position j: face values at t1 cells j - 2 .. j + 2
-            double x[5];
-#pragma unroll
-            for (int r = 0; r < 5; ++r) x[r] = s_f[side][l + r];
-            double cm[NW], cp[NW];
-            if (in) {
-                double gm, gp, wm[3], wp[3];
-                weno_gauss_w<double>(x[0], x[1], x[2], x[3], x[4], a.eps, gm, gp, wm, wp);
-                weno_coefs<EXACT>(2, x, a.eps, wm, gm, cm);
-                weno_coefs<EXACT>(3, x, a.eps, wp, gp, cp);
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < NW; ++kk) cm[kk] = cp[kk] = 0.0;
-            }
-#pragma unroll
-            for (int kk = 0; kk < NW; ++kk) {
-                s_v[10 + (side * 2 + 0) * NW + kk][l] = cm[kk];
-                s_v[10 + (side * 2 + 1) * NW + kk][l] = cp[kk];
-            }
-        }
-    }
-    __syncthreads();
-    for (int o = threadIdx.x; o < C_SEG; o += C_THREADS) {
-        const int jx = seg0 + o;
-        if (jx >= a.n_t1 + 2) break;
-        double bar[3] = {0.0, 0.0, 0.0}, Cb = 0.0;
-        // positions j = jx - 2 .. jx + 2 in ascending order (stencil slot r = jx - j + 2 descending)
-#pragma unroll
-        for (int r = 4; r >= 0; --r) {
-            const int j = jx - r + 2;
-            if (j < 0 || j >= a.n_t1) continue;
-            const int l = j - seg0 + 2;
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                const int side = m == 0 ? 2 : 3;
-                const int sg = m == 0 ? -1 : 1;
-                const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h1;
-                double wL[NW], wR[NW];
-#pragma unroll
-                for (int kk = 0; kk < NW; ++kk) {
-                    wL[kk] = s_v[10 + (0 * 2 + m) * NW + kk][l];
-                    wR[kk] = s_v[10 + (1 * 2 + m) * NW + kk][l];
-                }
-                bar[0] += wcoef<EXACT>(side, wL, r) * s_v[m * 5 + 0][l];
-                bar[1] += wcoef<EXACT>(side, wR, r) * s_v[m * 5 + 1][l];
-                bar[2] += cv * s_v[m * 5 + 2][l];
-                Cb += cd * s_v[m * 5 + 3][l];
-                Cb += cv * s_v[m * 5 + 4][l];
-            }
-        }
-        const long long p = n_ix(a, f, jx, kx);
-        a.fabar[(long long)(v * 3 + 0) * a.nnpos + p] = bar[0] + 0.5 * Cb;
-        a.fabar[(long long)(v * 3 + 1) * a.nnpos + p] = bar[1] + 0.5 * Cb;
-        a.fabar[(long long)(v * 3 + 2) * a.nnpos + p] = bar[2];
     }
 }
 
@@ -555,10 +558,11 @@ hipError_t launch_adj_passes(const AdjFaceArgs& a, int stage, hipStream_t s) {
     const dim3 fgrid((unsigned)blocks), fblock(FaceTile<double>::THREADS);
     if (stage == 1) hipLaunchKernelGGL((adj_face_kernel<1>), fgrid, fblock, 0, s, a);
     else hipLaunchKernelGGL((adj_face_kernel<2>), fgrid, fblock, 0, s, a);
-    const long long nB = (long long)(a.n_n + 1) * a.n_t1 * ((a.n_t2 + 4 + T2_CHUNK - 1) / T2_CHUNK) * 8;
-    hipLaunchKernelGGL((adj_t2_kernel<EXACT>), dim3((unsigned)((nB + 255) / 256)), dim3(256), 0, s, a);
-    const long long nC = (long long)(a.n_n + 1) * (a.n_t2 + 4) * 4 * ((a.n_t1 + 4 + C_SEG - 1) / C_SEG);
-    hipLaunchKernelGGL((adj_t1_kernel<EXACT>), dim3((unsigned)nC), dim3(C_THREADS), 0, s, a);
+    const BcSplit bc = bc_split(a.n_t1);
+    const long long nBC = (long long)(a.n_n + 1) * 4 * bc.nseg * ((a.n_t2 + 4 + BC_ROWS - 1) / BC_ROWS);
+    const size_t lds = ((size_t)(10 + 4 * (EXACT ? 5 : 2)) * bc.npt + 2 * (size_t)(bc.npt + 4)) * sizeof(double);
+    if (nBC > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((adj_t21_kernel<EXACT>), dim3((unsigned)nBC), dim3(2 * bc.npt), lds, s, a, bc.seg, bc.npt);
     const long long nD = (long long)((a.n_n + 6 + N_CHUNK - 1) / N_CHUNK) * 4 * (a.n_t1 + 4) * (a.n_t2 + 4);
     hipLaunchKernelGGL((adj_normal_kernel<EXACT>), dim3((unsigned)((nD + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -712,10 +716,11 @@ __device__ __forceinline__ long long pidx_g(const GridDesc& g, int i, int j, int
     return g.pad0 + (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
 }
 
-// per point: fvbar = dt sum_cells G(x - X_p) lambda_m(x) over the projection sphere
-__global__ void alm_adj_gather_kernel(AlmAdjArgs A) {
+// per point: fvbar = dt sum_cells G(x - X_p) lambda_m(x) over the projection sphere; one workgroup per
+// point, its threads striding over the cells of the sphere's bounding box, then a fixed-order tree sum
+__global__ void __launch_bounds__(256) alm_adj_gather_kernel(AlmAdjArgs A) {
     const AlmArgs& a = A.fwd;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x;  // uniform over the workgroup
     if (p >= a.n_act) return;
     const double X[3] = {a.X[3 * p], a.X[3 * p + 1], a.X[3 * p + 2]};
     const double cut = 9.0 * a.eps * a.eps, ie2 = 1.0 / (a.eps * a.eps);
@@ -727,22 +732,34 @@ __global__ void alm_adj_gather_kernel(AlmAdjArgs A) {
         lo[d] = max(lo[d], a.box_lo[d]);
         hi[d] = min(hi[d], a.box_lo[d] + a.box_n[d] - 1);
     }
+    const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+    const int ncell = (nx > 0 && ny > 0 && nz > 0) ? nx * ny * nz : 0;
     double acc[3] = {0, 0, 0};
-    for (int k = lo[2]; k <= hi[2]; ++k)
-        for (int j = lo[1]; j <= hi[1]; ++j)
-            for (int i = lo[0]; i <= hi[0]; ++i) {
-                const double dx = a.g.x0[0] + (i + 0.5) * a.g.h[0] - X[0];
-                const double dy = a.g.x0[1] + (j + 0.5) * a.g.h[1] - X[1];
-                const double dz = a.g.x0[2] + (k + 0.5) * a.g.h[2] - X[2];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 <= cut) {
-                    const double gw = norm * exp(-r2 * ie2);
-                    const long long q = pidx_g(a.g, i, j, k);
-                    for (int c = 0; c < 3; ++c) acc[c] += gw * A.lam_m[c][q];
-                }
-            }
-    const double dt = a.st->dt;
-    for (int c = 0; c < 3; ++c) A.pt[c * a.n_act + p] = dt * acc[c];
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+        const int i = lo[0] + c % nx, r = c / nx;
+        const int j = lo[1] + r % ny, k = lo[2] + r / ny;
+        const double dx = a.g.x0[0] + (i + 0.5) * a.g.h[0] - X[0];
+        const double dy = a.g.x0[1] + (j + 0.5) * a.g.h[1] - X[1];
+        const double dz = a.g.x0[2] + (k + 0.5) * a.g.h[2] - X[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 <= cut) {
+            const double gw = norm * exp(-r2 * ie2);
+            const long long q = pidx_g(a.g, i, j, k);
+            for (int d = 0; d < 3; ++d) acc[d] += gw * A.lam_m[d][q];
+        }
+    }
+    __shared__ double red[3][256];
+    for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = acc[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double dt = a.st->dt;
+        for (int d = 0; d < 3; ++d) A.pt[d * a.n_act + p] = dt * red[d][0];
+    }
 }
 
 // per point: reverse of the blade-element forces; gradient in s and the adjoint of the sampled U
@@ -878,7 +895,8 @@ __global__ void __launch_bounds__(256) alm_adj_scatter_kernel(AlmAdjArgs A) {
 
 hipError_t launch_alm_adjoint(const AlmAdjArgs& A, hipStream_t s) {
     const int n = A.fwd.n_act;
-    hipLaunchKernelGGL(alm_adj_gather_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(alm_adj_gather_kernel, dim3(n), dim3(256), 0, s, A);
     hipLaunchKernelGGL(alm_adj_points_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A);
     const long long ncell = (long long)A.fwd.samp_n[0] * A.fwd.samp_n[1] * A.fwd.samp_n[2];
     hipLaunchKernelGGL(alm_adj_scatter_kernel, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, A);
@@ -913,7 +931,6 @@ void adjoint_carve(char* base, int nx, int ny, int nz, int n_act, AdjBuffers* b,
     }
     b->gpbar = reinterpret_cast<double*>(take(80 * nface * 8));
     b->t1v = reinterpret_cast<double*>(take(16 * nt1 * 8));
-    b->t1bar = reinterpret_cast<double*>(take(40 * nt1 * 8));
     b->fv = reinterpret_cast<double*>(take(8 * nn * 8));
     b->fabar = reinterpret_cast<double*>(take(12 * nn * 8));
     b->pt = reinterpret_cast<double*>(take(16 * (size_t)std::max(n_act, 1) * 8));

@@ -468,7 +468,6 @@ AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4],
     a.gpbar = B.gpbar;
     a.t1v = B.t1v;
     a.fv = B.fv;
-    a.t1bar = B.t1bar;
     a.fabar = B.fabar;
     a.n_n = c->g.n[ax[0]];
     a.n_t1 = c->g.n[ax[1]];
