@@ -131,6 +131,12 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     const int jc = j0 - 2 + c1, kc = k0 - 2 + c2;
     const bool col_ld = col && (jc < a.n_t1 + NG) && (kc < a.n_t2 + NG);
     const long long cbase = a.pad0 + (long long)jc * a.st_t1 + (long long)kc * a.st_t2;
+    // the in-loop prefetch of the column cells is done by every thread, columns outside the padded domain
+    // and threads without a column reading a clamped column (its values are never used): a load on every
+    // path leaves the compiler no merge of a loaded and a kept value, which would make it wait for the
+    // load within the same step, and for the step's stores at the next one
+    const long long cbase_ld = a.pad0 + (long long)min(jc, a.n_t1 + NG - 1) * a.st_t1 +
+                               (long long)min(kc, a.n_t2 + NG - 1) * a.st_t2;
     // face role: face (fj, fk) of the tile, Gauss line m (partner lane tid ^ 1 holds the other line)
     const int m = tid & 1;
     const int fj = (tid >> 1) % TILE1, fk = (tid >> 1) / TILE1;
@@ -224,13 +230,13 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
         // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
         real2 e_r0 = {0, 0}, e_r1 = {0, 0}, e_x0 = {0, 0}, e_x1 = {0, 0}, e_lo = {0, 0};
         real e_q[2] = {0, 0};
-        if (EPI_PREFETCH && MODE == 4 && f > f0 && face_ok) {
-            const int cell = f - 1;
-            const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
-                                   (long long)(k0 + fk) * a.ist_t2;
-            const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)(j0 + fj) * a.st_t1 +
-                                   (long long)(k0 + fk) * a.st_t2;
-            const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
+        if constexpr (EPI_PREFETCH && MODE == 4) {
+            // loaded on every path (for the same reason as the column prefetch): at f = f0 and for faces
+            // outside the domain a clamped cell is read and its values are not used
+            const int cell = max(f - 1, 0), je = min(j0 + fj, a.n_t1 - 1), ke = min(k0 + fk, a.n_t2 - 1);
+            const long long ridx = (long long)cell * a.ist_n + (long long)je * a.ist_t1 + (long long)ke * a.ist_t2;
+            const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)je * a.st_t1 + (long long)ke * a.st_t2;
+            const long long xidx = rx_block_index(je, ke, cell, a.rx_nx, a.rx_nyb);
             e_r1 = ld2(a.r1, ridx, m);
             e_x1 = ld2(a.rx1, xidx, m);
             if (COMPENSATED) e_lo = ld2(a.lo_in, ridx, m);
@@ -254,11 +260,13 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 // the shift is applied here, a step after the load, so that the prefetch stays in flight
                 ring[v][4] = (SHIFT && v == 1) ? nxt[v] - cm : nxt[v];
             }
-            if (col_ld && f < f1) {
-                const long long idx = cbase + (long long)(f + 3) * a.st_n;
+        }
+        {
+            const long long idx = cbase_ld + (long long)min(f + 3, a.n_n + 2) * a.st_n;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
-            }
+            for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
+        }
+        if (col) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 real right, left;
