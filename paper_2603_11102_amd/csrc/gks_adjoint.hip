@@ -113,13 +113,21 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
         }
     }
 
+    // the next cell of the column is loaded one step ahead, by every thread (columns outside the padded
+    // domain and threads without a column read a clamped column whose values only reach faces outside
+    // the domain): a load on every path needs no merge that would wait for it within the step
+    const long long cbase_ld = a.pad0 + (long long)min(jc, a.n_t1 + NG - 1) * a.st_t1 +
+                               (long long)min(kc, a.n_t2 + NG - 1) * a.st_t2;
+    double nxt[4];
+    for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][cbase_ld + (long long)min(f0 + 2, a.n_n + 2) * a.st_n];
     for (int f = f0; f <= f1; ++f) {
-        if (col_ld) {
-            const long long idx = cbase + (long long)(f + 2) * a.st_n;
-            for (int v = 0; v < 4; ++v) {
-                for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
-                ring[v][4] = a.q[v][idx];
-            }
+        for (int v = 0; v < 4; ++v) {
+            for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
+            ring[v][4] = nxt[v];
+        }
+        {
+            const long long idx = cbase_ld + (long long)min(f + 3, a.n_n + 2) * a.st_n;
+            for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
         }
         // column phase of one variable; v is a compile-time constant so that ring stays in registers
         auto column = [&](auto vc) {

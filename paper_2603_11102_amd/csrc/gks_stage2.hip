@@ -107,6 +107,11 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     const int jc = j0 - 1 + c1, kc = k0 - 1 + c2;
     const bool col_ld = col && (jc <= a.n_t1) && (kc <= a.n_t2);
     const long long cbase = a.pad0 + (long long)jc * a.st_t1 + (long long)kc * a.st_t2;
+    // the in-loop column prefetch is done by every thread (threads without a column read a clamped one
+    // whose values are not used): a load on every path keeps the compiler from waiting for it, and for
+    // the step's stores, before the next step
+    const long long cbase_ld = a.pad0 + (long long)min(jc, a.n_t1 + NG - 1) * a.st_t1 +
+                               (long long)min(kc, a.n_t2 + NG - 1) * a.st_t2;
     // face role
     const bool face = tid < TILE1 * TILE2;
     const int fj = tid % TILE1, fk = tid / TILE1;
@@ -182,11 +187,13 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
                 // the shift is applied here, a step after the load, so that the prefetch stays in flight
                 ring[v][3] = (SHIFT && v == 1) ? nxt[v] - cm : nxt[v];
             }
-            if (col_ld && f < f1) {
-                const long long idx = cbase + (long long)(f + 2) * a.st_n;
+        }
+        {
+            const long long idx = cbase_ld + (long long)min(f + 2, a.n_n + 2) * a.st_n;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
-            }
+            for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
+        }
+        if (col) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const real qm2 = ring[v][0], qm1 = ring[v][1], q0 = ring[v][2], qp1 = ring[v][3];
