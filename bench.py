@@ -22,9 +22,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic floating-point operations (add, sub, mul = 1, FMA = 2, div / sqrt / exp / erf = 1) per
-# cell and face direction, counted from the formulation of the face kernel: reconstruction of the four
-# variables (normal 111, t1 215, t2 430 per variable), flux at four Gauss points, divergence. The
-# breakdown is given with the kernel description in the design notes.
+# cell and face direction, counted from the textbook formulation of the scheme (Jiang-Shu closed-form
+# smoothness indicators shared by the two faces of a cell, one normalisation per evaluation point, the
+# closed-form flux): reconstruction of the four variables (normal 111, t1 215, t2 430 per variable),
+# flux at four Gauss points, divergence. It is a fixed unit of work: kernels that evaluate the same
+# quantities with fewer operations do not change it.
 FLOP_STAGE1_PER_CELL_DIR = 3692
 FLOP_STAGE2_PER_CELL_DIR = 3592
 FLOP_PER_CELL_STEP = 3 * (FLOP_STAGE1_PER_CELL_DIR + FLOP_STAGE2_PER_CELL_DIR) + 56
@@ -33,17 +35,17 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per stage-1 face-pass launch (mean over the x, y, z launches) of the FP32 channel workload,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-# "bench.py [--order 2] --steps 2 --warmup 1 --no-fp64 --no-cpu-baseline", each scaled by what the same
-# counter reads for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024": FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0). A figure belongs to the kernel sources it was measured on; bench reports null once
-# they differ.
+# "bench.py [--order 2] --steps 4 --warmup 2 --repeats 1 --no-fp64 --no-cpu-baseline --no-adjoint --no-bodies",
+# each scaled by what the same counter reads for a plain 1 GiB device copy ("bench.py --calibrate-copy 1024":
+# FETCH_SIZE x 2.0, WRITE_SIZE x 1.0). A figure belongs to the kernel sources it was measured on; bench
+# reports null once they differ.
 TRAFFIC = {
     5: {"sources": ("gks_stage.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "b566713947b61edc38f458379709453bd74e764f45af79ce1a31ea16f9df1984",
-         "fetch_bytes": 103_945_421, "write_bytes": 76_419_846},
+         "sources_sha256": "fdeada49f9201c8d8b921410956f879d3fa6ab4e4dab3a3c56197edff415f4d3",
+         "fetch_bytes": 191_445_637, "write_bytes": 85_133_293},
     2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "6d533dd16597edca70dbc7e6042a2d2f2cc8d4f261b8c51855e84ca11998bd75",
-         "fetch_bytes": 97_918_618, "write_bytes": 76_709_743},
+         "sources_sha256": "896e29c2d953450ebfdd919850eeb1b148694f3ff2158b1f2b129a713ca2f4a7",
+         "fetch_bytes": 102_100_143, "write_bytes": 76_769_213},
 }
 
 
