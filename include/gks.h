@@ -244,8 +244,9 @@ size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
  * GKS_ADJ_EXACT_WENO in flags they are differentiated as well, so the gradient is the derivative of the
  * discrete forward itself. Everything else (flux, kinetic average, S2O4 combination, ghost cells,
  * actuator-line sampling, forces and projection, the direct forcing of an immersed body at rest) is
- * linearised exactly. Requires an FP64 context of the high-order scheme (order 5) with a rotor, no moving
- * body, a fixed dt and periodic, wall or outflow boundaries. The stage buffers q_stage and q_acc are overwritten; q is not. adj_ws: device scratch of
+ * linearised exactly, as are the ghost cells of every boundary kind (the inflow's Riemann-invariant
+ * density at the stage's field). Requires an FP64 context of the high-order scheme (order 5) on a uniform
+ * mesh with a rotor, no moving body and a fixed dt. The stage buffers q_stage and q_acc are overwritten; q is not. adj_ws: device scratch of
  * gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
 int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0,
                 void* adj_ws, size_t adj_ws_bytes, int32_t flags);

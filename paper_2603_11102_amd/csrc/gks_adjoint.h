@@ -66,7 +66,10 @@ struct AdjBuffers {
 void adjoint_carve(char* base, int nx, int ny, int nz, int n_act, AdjBuffers* b, size_t* total);
 
 hipError_t launch_adj_direction(const AdjFaceArgs& a, int stage, hipStream_t s);
-hipError_t launch_adj_fold(double* f[4], const GridDesc& g, const int bc[6], hipStream_t s);
+// transpose of the axis-by-axis ghost fill (z, y, x); inflow sides are linearised at the padded field q
+// (global variable order) the fill was applied to
+hipError_t launch_adj_fold(double* f[4], const GridDesc& g, const int bc[6], const double* const q[4],
+                           const double u_in[3], double c, double rho_ref, hipStream_t s);
 // y = a x + b z over n elements (z may be null)
 hipError_t launch_axpby(double* y, const double* x, double a, const double* z, double b, long long n, hipStream_t s);
 // interior extraction / scatter between padded and interior layouts: dst_int = a * src_pad (+ b * src2_pad)

@@ -588,6 +588,10 @@ struct FoldArgs {
     int axis, n, np1, np2;
     long long st_a, st_1, st_2;
     int bc_lo, bc_hi;
+    // inflow sides: the prescribed velocity, the sound speed, rho_ref and the padded field the ghost fill
+    // was applied to (global variable order), at which the fill is linearised
+    double u_in[3], c, rho_ref;
+    Field4<const double> q;
 };
 
 __global__ void adj_fold_kernel(Field4<double> f, FoldArgs g) {
@@ -605,6 +609,20 @@ __global__ void adj_fold_kernel(Field4<double> f, FoldArgs g) {
             else src_i = side == 0 ? 0 : g.n - 1;
             const long long dst = base + (long long)gi * g.st_a;
             const long long src = base + (long long)(src_i + 3) * g.st_a;
+            if (kind == 3) {  // inflow
+                // ghost = (rho_g - rho_ref, rho_g u_in) with rho_g = rho_i e^x, x = s (u_in,n - m_n / rho_i) / C
+                // (s = +1 on the low side, -1 on the high side): only rho' and m_n of the source enter,
+                // d rho_g / d rho' = e^x (1 + s u_n / C), d rho_g / d m_n = -s e^x / C
+                const double sgn = side == 0 ? 1.0 : -1.0;
+                const double rho_i = g.rho_ref + g.q.v[0][src];
+                const double un = g.q.v[1 + g.axis][src] / rho_i;
+                const double ex = exp(sgn * (g.u_in[g.axis] - un) / g.c);
+                const double br = f.v[0][dst] + g.u_in[0] * f.v[1][dst] + g.u_in[1] * f.v[2][dst] + g.u_in[2] * f.v[3][dst];
+                f.v[0][src] += ex * (1.0 + sgn * un / g.c) * br;
+                f.v[1 + g.axis][src] += -sgn * ex / g.c * br;
+                for (int v = 0; v < 4; ++v) f.v[v][dst] = 0.0;
+                continue;
+            }
             for (int v = 0; v < 4; ++v) {
                 double sg = 1.0;
                 if (kind == 1 && v > 0) sg = -1.0;
@@ -616,7 +634,8 @@ __global__ void adj_fold_kernel(Field4<double> f, FoldArgs g) {
     }
 }
 
-hipError_t launch_adj_fold(double* fp[4], const GridDesc& gd, const int bc[6], hipStream_t s) {
+hipError_t launch_adj_fold(double* fp[4], const GridDesc& gd, const int bc[6], const double* const q[4],
+                           const double u_in[3], double c, double rho_ref, hipStream_t s) {
     Field4<double> f;
     for (int v = 0; v < 4; ++v) f.v[v] = fp[v];
     for (int axis = 2; axis >= 0; --axis) {
@@ -631,6 +650,10 @@ hipError_t launch_adj_fold(double* fp[4], const GridDesc& gd, const int bc[6], h
         g.st_2 = gd.st[a2];
         g.bc_lo = bc[2 * axis];
         g.bc_hi = bc[2 * axis + 1];
+        for (int j = 0; j < 3; ++j) g.u_in[j] = u_in[j];
+        g.c = c;
+        g.rho_ref = rho_ref;
+        for (int v = 0; v < 4; ++v) g.q.v[v] = q[v];
         const long long total = (long long)g.np1 * g.np2;
         hipLaunchKernelGGL(adj_fold_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f, g);
     }

@@ -1105,8 +1105,6 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
     if (c->cfg.cfl > 0) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a fixed dt (cfl <= 0)");
     if (!c->has_rotor) return fail(c, GKS_E_STATE, "the adjoint needs a rotor (gks_set_actuators)");
     if (c->has_ibm && c->ibm_moving) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover moving bodies");
-    for (int sd = 0; sd < 6; ++sd)
-        if (c->cfg.bc[sd] == GKS_BC_INFLOW) return fail(c, GKS_E_UNSUPPORTED, "the adjoint does not cover inflow boundaries");
     if (!c->ckpt || nsteps < 1 || nsteps > c->ckpt_n)
         return fail(c, GKS_E_STATE, "need at least nsteps checkpointed steps (gks_set_checkpoints, then gks_step)");
     if (reinterpret_cast<uintptr_t>(adj_ws) % 256) return fail(c, GKS_E_INVALID_ARG, "adj_ws must be 256-byte aligned");
@@ -1169,7 +1167,9 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
             HIPCHK(c, launch_zero(B.acc[v], np, S));
         }
         for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, c->qs, exact), 2, S));
-        HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, S));
+        const double* qs_d[4] = {static_cast<const double*>(c->qs[0]), static_cast<const double*>(c->qs[1]),
+                                 static_cast<const double*>(c->qs[2]), static_cast<const double*>(c->qs[3])};
+        HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, qs_d, c->cfg.u_in, c->c, c->cfg.rho_ref, S));
         for (int v = 0; v < 4; ++v) HIPCHK(c, launch_axpby(B.lam_star[v], B.acc[v], 1.0, nullptr, 0.0, np, S));
         // stage 1: seeds dt lam_pre + dt/2 lam* (of L) and dt^2/6 lam_pre + dt^2/8 lam* (of L_t) at Q^n
         for (int v = 0; v < 4; ++v) {
@@ -1178,7 +1178,8 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
             HIPCHK(c, launch_zero(B.acc[v], np, S));
         }
         for (int d = 0; d < 3; ++d) HIPCHK(c, launch_adj_direction(adj_args(c, B, d, qwork, exact), 1, S));
-        HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, S));
+        const double* qw_d[4] = {B.qwork[0], B.qwork[1], B.qwork[2], B.qwork[3]};
+        HIPCHK(c, launch_adj_fold(B.acc, c->g, c->cfg.bc, qw_d, c->cfg.u_in, c->c, c->cfg.rho_ref, S));
         // lam^n = lam_pre + lam* + J^T(...)
         for (int v = 0; v < 4; ++v) {
             HIPCHK(c, launch_axpby(B.lam[v], B.lam_pre[v], 1.0, B.lam_star[v], 1.0, np, S));

@@ -122,3 +122,32 @@ def test_body_at_rest_field_gradient_matches_frozen_finite_differences(case):
     v = rng.standard_normal(n)
     fd = _frozen_fd(cfg, s0, v, 1e-3)
     assert abs(fd - float(g.numpy() @ v)) < 1e-8 * abs(fd)
+
+
+def _inflow_case():
+    """The rotor workload's boundaries (inflow x-, outflow x+, periodic y, slip z) on 48 x 24 x 24 with a
+    fixed dt, the hub moved to 7.2 cells from the inflow side so that the inflow ghost cells reach the
+    actuator points within the window."""
+    from dataclasses import replace
+    cfg = make_case("alm", grid=(48, 24, 24))
+    return cfg.with_(cfl=0.0, dt_fixed=0.3 * cfg.dx / 11.0, rotor=replace(cfg.rotor, hub=(0.9, 1.5, 1.5)))
+
+
+def test_inflow_window_field_gradient_matches_frozen_finite_differences():
+    # reverse mode through the Riemann-invariant inflow ghost cells, along a perturbation of the cells
+    # next to the inflow side, against central differences of the weight-replaying forward
+    cfg = _inflow_case()
+    assert cfg.bc[0] == "inflow" and cfg.bc[1] == "outflow" and cfg.bc[4] == "slip"
+    rng = np.random.default_rng(6)
+    n = cfg.rotor.n_act
+    s0 = np.ones(n)
+    q0 = torch.tensor(cfg.q0).clone().requires_grad_(True)
+    J, _ = rotor_objective(cfg, torch.tensor(s0), NSTEPS, W, WenoControl("detach"), q0=q0)
+    J.backward()
+    dq = torch.zeros(cfg.q0.shape, dtype=F64)
+    dq[:, :, :, :4] = torch.tensor(rng.standard_normal((4, cfg.nz, cfg.ny, 4)))
+    dq[0] *= 0.01
+    fd = _frozen_fd(cfg, s0, np.zeros(n), 1e-4, q0=torch.tensor(cfg.q0), dq=dq)
+    ad = float((q0.grad * dq).sum())
+    assert abs(ad) > 1e-6
+    assert abs(fd - ad) < 1e-6 * abs(ad), (fd, ad)
