@@ -93,8 +93,7 @@ typedef struct gks_config {
                                     uniform. A rotor (its disc and 3 eps spheres) or an immersed body must
                                     sit in cells of one width (a uniformly refined block, as around the
                                     paper's turbines) and then works on the uniform grid of that block
-                                    (a moving body on the widest run of cells of that width); the
-                                    adjoint needs a uniform mesh. */
+                                    (a moving body on the widest run of cells of that width). */
 } gks_config;
 
 typedef struct gks_field {
@@ -245,8 +244,10 @@ size_t gks_adjoint_workspace_bytes(const gks_config* cfg, int32_t n_act);
  * discrete forward itself. Everything else (flux, kinetic average, S2O4 combination, ghost cells,
  * actuator-line sampling, forces and projection, the direct forcing of an immersed body at rest) is
  * linearised exactly, as are the ghost cells of every boundary kind (the inflow's Riemann-invariant
- * density at the stage's field). Requires an FP64 context of the high-order scheme (order 5) on a uniform
- * mesh with a rotor, no moving body and a fixed dt. The stage buffers q_stage and q_acc are overwritten; q is not. adj_ws: device scratch of
+ * density at the stage's field), on a uniform or a stretched mesh (the chain-rule derivatives and flux
+ * differences carry the local spacings). Requires an FP64 context of the high-order scheme (order 5)
+ * with a rotor, no moving body and a fixed dt. The stage buffers q_stage and q_acc are overwritten; q
+ * is not. adj_ws: device scratch of
  * gks_adjoint_workspace_bytes (256-byte aligned). Synchronises the stream. */
 int gks_adjoint(gks_ctx* ctx, int32_t nsteps, const double w[2], double* grad_s, double* grad_q0,
                 void* adj_ws, size_t adj_ws_bytes, int32_t flags);

@@ -39,7 +39,12 @@ struct AdjFaceArgs {
     long long ist_n, ist_t1, ist_t2;
     long long pad0;
     long long nface, nt1pos, nnpos;
-    double inv_hn, inv_h1, inv_h2;
+    // inverse spacings (device, the forward's arrays; 1/h on a uniform axis): normal face spacings
+    // [n_n + 1], normal widths [n_n], t1 widths [n_t1], t2 widths [n_t2]
+    const double* ihf;
+    const double* ihc;
+    const double* ih1;
+    const double* ih2;
     double eps;
     FluxConst<double> fc;
     int exact;              // 1: the WENO weights are differentiated (Jacobian rows), 0: frozen

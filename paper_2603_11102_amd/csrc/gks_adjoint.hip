@@ -120,11 +120,19 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                                (long long)min(kc, a.n_t2 + NG - 1) * a.st_t2;
     double nxt[4];
     for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][cbase_ld + (long long)min(f0 + 2, a.n_n + 2) * a.st_n];
+    // inverse spacings: t1 width of this thread's tangential-line cell, t2 width of its face cell, and
+    // (per face, fetched one face ahead) the normal face spacing and the widths of the two cells
+    // sharing the face (clamped at the ends, where the terms they scale vanish)
+    const double ih1 = a.ih1[min(j0 + tj, a.n_t1 - 1)], ih2 = a.ih2[min(k0 + fk, a.n_t2 - 1)];
+    double ihf_nxt = a.ihf[f0], ihc_nxt = a.ihc[min(f0, a.n_n - 1)], ihc_lo = a.ihc[max(f0 - 1, 0)];
     for (int f = f0; f <= f1; ++f) {
         for (int v = 0; v < 4; ++v) {
             for (int r = 0; r < 4; ++r) ring[v][r] = ring[v][r + 1];
             ring[v][4] = nxt[v];
         }
+        const double ihf = ihf_nxt, ihc_hi = ihc_nxt;
+        ihf_nxt = a.ihf[min(f + 1, a.n_n)];
+        ihc_nxt = a.ihc[min(f + 1, a.n_n - 1)];
         {
             const long long idx = cbase_ld + (long long)min(f + 3, a.n_n + 2) * a.st_n;
             for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
@@ -137,7 +145,7 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                 weno_faces_w<double>(ring[v][0], ring[v][1], ring[v][2], ring[v][3], ring[v][4], eps, right, left,
                                      wr, wl);
                 const double qL = carry[v];
-                const double D = (ring[v][0] - 15.0 * ring[v][1] + 15.0 * ring[v][2] - ring[v][3]) * (a.inv_hn / 12.0);
+                const double D = (ring[v][0] - 15.0 * ring[v][1] + 15.0 * ring[v][2] - ring[v][3]) * (ihf / 12.0);
                 s_nrm[0][c2][c1] = qL;
                 s_nrm[1][c2][c1] = left;
                 s_nrm[2][c2][c1] = D;
@@ -176,8 +184,8 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                 s_t1[2][tk][tj][0] = vm;
                 s_t1[2][tk][tj][1] = vp;
                 quartic_gauss_deriv<double>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-                s_t1[3][tk][tj][0] = vm * a.inv_h1;
-                s_t1[3][tk][tj][1] = vp * a.inv_h1;
+                s_t1[3][tk][tj][0] = vm * ih1;
+                s_t1[3][tk][tj][1] = vp * ih1;
                 quartic_gauss_value<double>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
                 s_t1[4][tk][tj][0] = vm;
                 s_t1[4][tk][tj][1] = vp;
@@ -200,8 +208,8 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                 put(v, 0, 3, vm);
                 put(v, 1, 3, vp);
                 quartic_gauss_deriv<double>(y[4][0], y[4][1], y[4][2], y[4][3], y[4][4], vm, vp);
-                put(v, 0, 4, vm * a.inv_h2);
-                put(v, 1, 4, vp * a.inv_h2);
+                put(v, 0, 4, vm * ih2);
+                put(v, 1, 4, vp * ih2);
             }
             switch (v) {
                 case 0: column(std::integral_constant<int, 1>{}); break;
@@ -221,11 +229,12 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
             for (int v = 0; v < 4; ++v) {
                 const double hi1 = f < a.n_n ? a.mu1[v][(long long)f * a.ist_n + jk] : 0.0;
                 const double lo1 = f >= 1 ? a.mu1[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
-                b1[v] = (hi1 - lo1) * a.inv_hn;
+                // Fbar(f) = mu(f) / w_f - mu(f-1) / w_{f-1} (cell widths w)
+                b1[v] = hi1 * ihc_hi - lo1 * ihc_lo;
                 if (NEED_F0) {
                     const double hi0 = f < a.n_n ? a.mu0[v][(long long)f * a.ist_n + jk] : 0.0;
                     const double lo0 = f >= 1 ? a.mu0[v][(long long)(f - 1) * a.ist_n + jk] : 0.0;
-                    b0[v] = (hi0 - lo0) * a.inv_hn;
+                    b0[v] = hi0 * ihc_hi - lo0 * ihc_lo;
                 } else {
                     b0[v] = 0.0;
                 }
@@ -252,6 +261,7 @@ __global__ void __launch_bounds__(FaceTile<double>::THREADS) adj_face_kernel(con
                 }
             }
         }
+        ihc_lo = ihc_hi;
     }
 }
 
@@ -297,6 +307,7 @@ __global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int s
     double* const s_tb = lds;                        // [10][npt]: t1 line adjoints [m * 5 + q][position]
     double* const s_w = s_tb + 10 * npt;             // [4 NW][npt]: coefficients [(side * 2 + m) * NW + kk]
     double* const s_f = s_w + 4 * NW * npt;          // [2][npt + 4]: normal face values q^L, q^R
+    double* const s_h1 = s_f + 2 * (npt + 4);        // [npt]: inverse t1 widths of the positions
     const int tid = threadIdx.x;
     const int nrc = (a.n_t2 + 4 + BC_ROWS - 1) / BC_ROWS;
     const int nseg = (a.n_t1 + 4 + seg_len - 1) / seg_len;
@@ -315,6 +326,7 @@ __global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int s
     const bool tb = jl < npos;
     const int j = jlo + jl;
     const int vm = v * 2 + m;
+    if (tid < npos) s_h1[tid] = a.ih1[jlo + tid];  // read after the first row's barrier
     auto t1val = [&](int side, int kx) -> double {
         return (tb && kx >= -2 && kx < a.n_t2 + 2) ? a.t1v[((v * 2 + side) * 2 + m) * a.nt1pos + t1_ix(a, f, j, kx)]
                                                    : 0.0;
@@ -339,6 +351,8 @@ __global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int s
         ynext[side] = t1val(side, kx_lo);
     }
     gp_in(kx_lo - 2, gnext);
+    // inverse t2 width of face k's cell, fetched one face ahead (clamped outside the cells, where unused)
+    double ih2_nxt = a.ih2[min(max(kx_lo - 2, 0), a.n_t2 - 1)];
     double acc[5][5];
 #pragma unroll
     for (int r = 0; r < 5; ++r)
@@ -359,6 +373,8 @@ __global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int s
             ynext[side] = t1val(side, k + 3);
         }
         gp_in(k + 1, gnext);
+        const double ih2 = ih2_nxt;
+        ih2_nxt = a.ih2[min(max(k + 1, 0), a.n_t2 - 1)];
         if (tb && k >= 0 && k < a.n_t2) {
             double cw[2][2][NW];
 #pragma unroll
@@ -375,7 +391,7 @@ __global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int s
                 const double* const gv = gcur[n];
 #pragma unroll
                 for (int r = 0; r < 5; ++r) {
-                    const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h2;
+                    const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * ih2;
                     acc[r][0] += wcoef<EXACT>(side, cw[0][n], r) * gv[0];
                     acc[r][1] += wcoef<EXACT>(side, cw[1][n], r) * gv[1];
                     acc[r][2] += cv * gv[2];
@@ -430,7 +446,7 @@ __global__ void __launch_bounds__(256) adj_t21_kernel(const AdjFaceArgs a, int s
                     for (int mm = 0; mm < 2; ++mm) {
                         const int side = mm == 0 ? 2 : 3;
                         const int sg = mm == 0 ? -1 : 1;
-                        const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * a.inv_h1;
+                        const double cv = quartic_coef(0, sg, r), cd = quartic_coef(1, sg, r) * s_h1[l];
                         double wL[NW], wR[NW];
 #pragma unroll
                         for (int kk = 0; kk < NW; ++kk) {
@@ -516,6 +532,7 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
         const long long p = ok[s] ? n_ix(a, fn, jx, kx) : 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) fb[s][q] = ok[s] ? a.fabar[(long long)(v * 3 + q) * a.nnpos + p] : 0.0;
+        fb[s][2] *= a.ihf[min(max(fn, 0), a.n_n)];  // D's 1/h at face fn
 #pragma unroll
         for (int r = 0; r < 4; ++r) win[r] = win[r + 1];
         win[4] = cell(fn + 3);
@@ -534,10 +551,11 @@ __global__ void __launch_bounds__(256) adj_normal_kernel(const AdjFaceArgs a) {
 #pragma unroll
         for (int s = 0; s <= 4; ++s)
             if (ok[s]) bar += wcoef<EXACT>(1, wr[s], 4 - s) * fb[s][1];
-        // D(f) = (Q(f-2) - 15 Q(f-1) + 15 Q(f) - Q(f+1)) / (12 h): faces i-1 .. i+2 (slots 1..4)
+        // D(f) = (Q(f-2) - 15 Q(f-1) + 15 Q(f) - Q(f+1)) / (12 h_f): faces i-1 .. i+2 (slots 1..4), the
+        // 1/h_f already in fb
 #pragma unroll
         for (int s = 1; s <= 4; ++s)
-            if (ok[s]) bar += cD[4 - s] * a.inv_hn * fb[s][2];
+            if (ok[s]) bar += cD[4 - s] * fb[s][2];
         const long long q = a.pad0 + (long long)i * a.st_n + (long long)jx * a.st_t1 + (long long)kx * a.st_t2;
         a.acc[v][q] += bar;
         // slide the window: face i + 4 enters
@@ -568,7 +586,7 @@ hipError_t launch_adj_passes(const AdjFaceArgs& a, int stage, hipStream_t s) {
     else hipLaunchKernelGGL((adj_face_kernel<2>), fgrid, fblock, 0, s, a);
     const BcSplit bc = bc_split(a.n_t1);
     const long long nBC = (long long)(a.n_n + 1) * 4 * bc.nseg * ((a.n_t2 + 4 + BC_ROWS - 1) / BC_ROWS);
-    const size_t lds = ((size_t)(10 + 4 * (EXACT ? 5 : 2)) * bc.npt + 2 * (size_t)(bc.npt + 4)) * sizeof(double);
+    const size_t lds = ((size_t)(11 + 4 * (EXACT ? 5 : 2)) * bc.npt + 2 * (size_t)(bc.npt + 4)) * sizeof(double);
     if (nBC > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((adj_t21_kernel<EXACT>), dim3((unsigned)nBC), dim3(2 * bc.npt), lds, s, a, bc.seg, bc.npt);
     const long long nD = (long long)((a.n_n + 6 + N_CHUNK - 1) / N_CHUNK) * 4 * (a.n_t1 + 4) * (a.n_t2 + 4);

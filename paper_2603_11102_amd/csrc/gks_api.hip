@@ -486,9 +486,10 @@ AdjFaceArgs adj_args(gks_ctx* c, const AdjBuffers& B, int d, void* const src[4],
     a.nface = (long long)(a.n_n + 1) * a.n_t1 * a.n_t2;
     a.nt1pos = (long long)(a.n_n + 1) * a.n_t1 * (a.n_t2 + 4);
     a.nnpos = (long long)(a.n_n + 1) * (a.n_t1 + 4) * (a.n_t2 + 4);
-    a.inv_hn = 1.0 / c->g.h[ax[0]];
-    a.inv_h1 = 1.0 / c->g.h[ax[1]];
-    a.inv_h2 = 1.0 / c->g.h[ax[2]];
+    a.ihf = static_cast<const double*>(c->ihf[ax[0]]);
+    a.ihc = static_cast<const double*>(c->ihc[ax[0]]);
+    a.ih1 = static_cast<const double*>(c->ihc[ax[1]]);
+    a.ih2 = static_cast<const double*>(c->ihc[ax[2]]);
     a.eps = c->eps;
     a.fc.lam = c->lam;
     a.fc.sl = std::sqrt(c->lam);
@@ -1100,7 +1101,6 @@ int gks_adjoint(gks_ctx* c, int32_t nsteps, const double w[2], double* grad_s, d
     if (flags & ~GKS_ADJ_EXACT_WENO) return fail(c, GKS_E_INVALID_ARG, "unknown adjoint flags");
     const int exact = (flags & GKS_ADJ_EXACT_WENO) ? 1 : 0;
     if (c->cfg.precision != GKS_FP64) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs an FP64 context");
-    if (c->stretched) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a uniform mesh");
     if (c->cfg.order == 2) return fail(c, GKS_E_UNSUPPORTED, "the adjoint covers the high-order scheme only");
     if (c->cfg.cfl > 0) return fail(c, GKS_E_UNSUPPORTED, "the adjoint needs a fixed dt (cfl <= 0)");
     if (!c->has_rotor) return fail(c, GKS_E_STATE, "the adjoint needs a rotor (gks_set_actuators)");

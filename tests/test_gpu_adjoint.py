@@ -240,3 +240,41 @@ def test_adjoint_with_inflow_outflow_and_slip_sides_matches_oracle_reference(exa
     # the inflow cells' sensitivities are held too (they differ from an outflow treatment by ~1e-7)
     e_in = float((gq[:, :, :, :3] - ref[:, :, :, :3]).abs().max() / ref.abs().max())
     assert e_in < 1e-9, e_in
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_adjoint_on_a_stretched_mesh_matches_oracle_reference(exact):
+    # the locally refined grid: the rotor in a uniform block, cells growing outside it along x, y and z;
+    # three steps, so that the stretched cells of every axis reach the actuator points (their
+    # sensitivities are 2e-8 to 1e-4 of the largest)
+    from test_oracle_adjoint import _stretched_case
+    cfg = _stretched_case()
+    n = cfg.rotor.n_act
+    rng = np.random.default_rng(0)
+    s0 = 1.0 + 0.1 * rng.standard_normal(n)
+    nsteps = 3
+    print_case("adjoint-stretched-vs-oracle", grid=(cfg.nx, cfg.ny, cfg.nz), nsteps=nsteps, exact=exact)
+    s, J, _ = _gpu_window(cfg, s0, nsteps)
+    g, gq = s.adjoint(nsteps, W, want_field=True, exact=exact)
+    Jo, go = rotor_gradient(cfg, s0, nsteps, W, frozen=not exact)
+    assert abs(J - Jo) < 1e-12 * abs(Jo)
+    rel = float((g.cpu() - go).abs().max() / go.abs().max())
+    assert rel < 1e-10, rel
+    q0 = torch.tensor(cfg.q0).clone().requires_grad_(True)
+    Jt, _ = rotor_objective(cfg, torch.tensor(s0), nsteps, W, None if exact else WenoControl("detach"), q0=q0)
+    Jt.backward()
+    ref = q0.grad.detach()
+    gq = gq.cpu()
+    scale = ref.abs().max()
+    for v in range(4):
+        e = float((gq[v] - ref[v]).abs().max() / ref[v].abs().max())
+        assert e < 1e-9, (v, e)
+    # the stretched cells of each axis
+    for axis, f in enumerate(cfg.faces):
+        w = np.diff(f)
+        st = torch.tensor(np.abs(w - w.min()) > 1e-12)
+        shape = [1, 1, 1, 1]
+        shape[3 - axis] = len(w)
+        m = st.reshape(shape)
+        assert float((ref * m).abs().max()) > 1e-8 * float(scale), axis
+        assert float(((gq - ref) * m).abs().max()) < 1e-9 * float(scale), axis
