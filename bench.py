@@ -41,8 +41,8 @@ PEAK_HBM_GBS = 8000.0
 # reports null once they differ.
 TRAFFIC = {
     5: {"sources": ("gks_stage.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "fdeada49f9201c8d8b921410956f879d3fa6ab4e4dab3a3c56197edff415f4d3",
-         "fetch_bytes": 191_445_637, "write_bytes": 85_133_293},
+         "sources_sha256": "f23efa760e44bb07a755229ed88967e0086dcfdf8794d5837e4cb00a1787c6b4",
+         "fetch_bytes": 191_411_558, "write_bytes": 85_135_719},
     2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
          "sources_sha256": "896e29c2d953450ebfdd919850eeb1b148694f3ff2158b1f2b129a713ca2f4a7",
          "fetch_bytes": 102_100_143, "write_bytes": 76_769_213},

@@ -18,7 +18,7 @@
 //   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
 // No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
-// variables (77 KB in FP32, 92 KB in FP64 of the 160 KB per CU).
+// variables (113 KB in FP32 with its padded rows, 92 KB in FP64, of the 160 KB per CU).
 #include <algorithm>
 
 #include "gks_internal.h"
@@ -95,7 +95,12 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     constexpr int LOC[4] = {LocalOrder<MODE>::v[0], LocalOrder<MODE>::v[1], LocalOrder<MODE>::v[2],
                             LocalOrder<MODE>::v[3]};
     constexpr int NT1 = TILE1 * X2;               // t1 items per variable (320 FP32, 192 FP64)
-    __shared__ real s_nrm[4][4][X2][EXT1];        // [variable][q^L, q^R, D, C]
+    // FP32 rows of the column values are 48 words apart (EXT1 = 20 used): a wave of the t1 phase reads
+    // rows tk .. tk + 3 at 16 consecutive positions each, and with a stride of 48 the four rows start at
+    // bank offsets 0, 48, 32, 16 (mod 64), so the reads meet no bank twice; a stride of 20 made them
+    // two-way conflicts
+    constexpr int NRM_S = sizeof(real) == 4 ? 48 : EXT1;
+    __shared__ real s_nrm[4][4][X2][NRM_S];       // [variable][q^L, q^R, D, C]
     __shared__ real s_t1[4][5][X2][TILE1][2];     // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
 
     const int tid = threadIdx.x;
