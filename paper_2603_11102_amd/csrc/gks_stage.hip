@@ -18,7 +18,7 @@
 //   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
 // No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
-// variables (113 KB in FP32 with its padded rows, 92 KB in FP64, of the 160 KB per CU).
+// variables (78 KB in FP32, 113 KB in its stage-1 z pass, 93 KB in FP64, of the 160 KB per CU).
 #include <algorithm>
 
 #include "gks_internal.h"
@@ -94,14 +94,28 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     using real2 = typename Vec2<real>::type;
     constexpr int LOC[4] = {LocalOrder<MODE>::v[0], LocalOrder<MODE>::v[1], LocalOrder<MODE>::v[2],
                             LocalOrder<MODE>::v[3]};
-    constexpr int NT1 = TILE1 * X2;               // t1 items per variable (320 FP32, 192 FP64)
-    // FP32 rows of the column values are 48 words apart (EXT1 = 20 used): a wave of the t1 phase reads
-    // rows tk .. tk + 3 at 16 consecutive positions each, and with a stride of 48 the four rows start at
-    // bank offsets 0, 48, 32, 16 (mod 64), so the reads meet no bank twice; a stride of 20 made them
-    // two-way conflicts
-    constexpr int NRM_S = sizeof(real) == 4 ? 48 : EXT1;
-    __shared__ real s_nrm[4][4][X2][NRM_S];       // [variable][q^L, q^R, D, C]
-    __shared__ real s_t1[4][5][X2][TILE1][2];     // [variable][q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][..][m]
+    // LDS: per variable, the column values [q^L, q^R, D, C][t2 row][t1 column] and the t1-phase results
+    // [q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][t2 row][t1 position][Gauss line m].
+    // T1_ROWWAVE: a wave of the t1 phase takes one row of all four variables, 16 consecutive positions
+    // each; the variable blocks are padded to start 16 words apart modulo 64 (FP32; 32 in FP64, whose
+    // elements take two banks), so its reads meet no bank twice. Otherwise (the FP32 stage-1 z pass,
+    // which sits at the register limit: there the thread's fixed LDS bases of the row-wave order cost
+    // spills and 3 % of the launch) a wave takes four rows of one variable, and the rows are 48 words
+    // apart, which puts those four rows in disjoint banks (a stride of 20 made them two-way conflicts).
+    // The t1-phase results of the four variables start 32 words apart modulo 64 (FP32), the least the
+    // wave's 64-bit stores can share banks.
+    constexpr bool T1_ROWWAVE = !(MODE == 4 && STAGE == 1 && sizeof(real) == 4);
+    constexpr int NRM_S = T1_ROWWAVE ? EXT1 : 48;
+    struct NrmV {
+        real a[4][X2][NRM_S];
+        real pad[16];
+    };
+    struct T1V {
+        real a[5][X2][TILE1][2];
+        real pad[sizeof(real) == 4 ? 32 : 2];
+    };
+    __shared__ NrmV s_nrm[4];
+    __shared__ T1V s_t1[4];
 
     const int tid = threadIdx.x;
     // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
@@ -226,8 +240,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     const bool hi = m != 0;
     // tangential inverse widths, loaded once (a vector load inside the march would make the wait for
     // it also wait for the column prefetch): t2 of this thread's face line; t1 of its t1-phase items,
-    // whose t1 position is tid % TILE1 for every item (NT1 and NTH are multiples of TILE1)
-    static_assert(NT1 % TILE1 == 0 && NTH % TILE1 == 0, "t1 position of the t1-phase items");
+    // whose t1 position is tid % TILE1 for every item
     const real ih2 = STR ? a.ih2[min(k0 + fk, a.n_t2 - 1)] : a.inv_h2;
     const real ih1 = STR ? a.ih1[min(j0 + tid % TILE1, a.n_t1 - 1)] : a.inv_h1;
     for (int f = f0; f <= f1; ++f) {
@@ -279,39 +292,56 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 const real qL = carry[v];
                 const real D = (ring[v][0] - real(15) * ring[v][1] + real(15) * ring[v][2] - ring[v][3]) *
                                (real(1.0 / 12.0) * ihf_f);
-                s_nrm[v][0][c2][c1] = qL;
-                s_nrm[v][1][c2][c1] = left;
-                s_nrm[v][2][c2][c1] = D;
-                s_nrm[v][3][c2][c1] = real(0.5) * (qL + left);
+                s_nrm[v].a[0][c2][c1] = qL;
+                s_nrm[v].a[1][c2][c1] = left;
+                s_nrm[v].a[2][c2][c1] = D;
+                s_nrm[v].a[3][c2][c1] = real(0.5) * (qL + left);
                 carry[v] = right;
             }
         }
         __syncthreads();
-        // ---- t1 phase: 4 x 320 (variable, item) pairs spread over all threads
-        for (int it = tid; it < 4 * NT1; it += NTH) {
-            const int v = it / NT1, item = it - v * NT1;
-            const int tj = item % TILE1, tk = item / TILE1;
+        // ---- t1 phase: the 4 x 16 x X2 items (variable v, t2 row tk, t1 position tj) spread over all
+        // threads. Row-wave order: a thread keeps tj = tid % 16 and v = tid / 16 % 4 and takes the rows
+        // tid / 64 + k NTH / 64, so its LDS addresses move by a fixed step (no index arithmetic in the
+        // march); otherwise item it = tid + k NTH in (variable, row, position) order.
+        auto t1_item = [&](int v, int tk, int tj) {
             real x[4][5];
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[v][q][tk][tj + r];
+                for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[v].a[q][tk][tj + r];
             real vm, vp;
             weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
-            s_t1[v][0][tk][tj][0] = vm;
-            s_t1[v][0][tk][tj][1] = vp;
+            s_t1[v].a[0][tk][tj][0] = vm;
+            s_t1[v].a[0][tk][tj][1] = vp;
             weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
-            s_t1[v][1][tk][tj][0] = vm;
-            s_t1[v][1][tk][tj][1] = vp;
+            s_t1[v].a[1][tk][tj][0] = vm;
+            s_t1[v].a[1][tk][tj][1] = vp;
             quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
-            s_t1[v][2][tk][tj][0] = vm;
-            s_t1[v][2][tk][tj][1] = vp;
+            s_t1[v].a[2][tk][tj][0] = vm;
+            s_t1[v].a[2][tk][tj][1] = vp;
             quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-            s_t1[v][3][tk][tj][0] = vm * ih1;
-            s_t1[v][3][tk][tj][1] = vp * ih1;
+            s_t1[v].a[3][tk][tj][0] = vm * ih1;
+            s_t1[v].a[3][tk][tj][1] = vp * ih1;
             quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-            s_t1[v][4][tk][tj][0] = vm;
-            s_t1[v][4][tk][tj][1] = vp;
+            s_t1[v].a[4][tk][tj][0] = vm;
+            s_t1[v].a[4][tk][tj][1] = vp;
+        };
+        static_assert(TILE1 == 16 && NTH % 64 == 0, "t1 items: 16 positions x 4 variables per wave");
+        if constexpr (T1_ROWWAVE) {
+            constexpr int RSTEP = NTH / 64, NK = (X2 + RSTEP - 1) / RSTEP;
+            const int tj = tid & 15, v = (tid >> 4) & 3;
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) {
+                const int tk = (tid >> 6) + kk * RSTEP;
+                if (X2 % RSTEP == 0 || tk < X2) t1_item(v, tk, tj);
+            }
+        } else {
+            constexpr int NT1 = TILE1 * X2;
+            for (int it = tid; it < 4 * NT1; it += NTH) {
+                const int v = it / NT1, item = it - v * NT1;
+                t1_item(v, item / TILE1, item % TILE1);
+            }
         }
         __syncthreads();
         // ---- t2 phase: per thread one face and one Gauss line, all variables
@@ -322,7 +352,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
 #pragma unroll
             for (int q = 0; q < 5; ++q)
 #pragma unroll
-                for (int r = 0; r < 5; ++r) y[q][r] = s_t1[v][q][fk + r][fj][m];
+                for (int r = 0; r < 5; ++r) y[q][r] = s_t1[v].a[q][fk + r][fj][m];
             real vm, vp;
             weno_gauss<real>(y[0][0], y[0][1], y[0][2], y[0][3], y[0][4], eps, vm, vp);
             gp[v][0][0] = vm;
