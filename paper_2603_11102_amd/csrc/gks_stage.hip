@@ -18,7 +18,7 @@
 //   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
 // No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
-// variables (78 KB in FP32, 113 KB in its stage-1 z pass, 93 KB in FP64, of the 160 KB per CU).
+// variables (78 KB in FP32, 93 KB in FP64, of the 160 KB per CU).
 #include <algorithm>
 
 #include "gks_internal.h"
@@ -95,19 +95,16 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     constexpr int LOC[4] = {LocalOrder<MODE>::v[0], LocalOrder<MODE>::v[1], LocalOrder<MODE>::v[2],
                             LocalOrder<MODE>::v[3]};
     // LDS: per variable, the column values [q^L, q^R, D, C][t2 row][t1 column] and the t1-phase results
-    // [q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][t2 row][t1 position][Gauss line m].
-    // T1_ROWWAVE: a wave of the t1 phase takes one row of all four variables, 16 consecutive positions
-    // each; the variable blocks are padded to start 16 words apart modulo 64 (FP32; 32 in FP64, whose
-    // elements take two banks), so its reads meet no bank twice. Otherwise (the FP32 stage-1 z pass,
-    // which sits at the register limit: there the thread's fixed LDS bases of the row-wave order cost
-    // spills and 3 % of the launch) a wave takes four rows of one variable, and the rows are 48 words
-    // apart, which puts those four rows in disjoint banks (a stride of 20 made them two-way conflicts).
-    // The t1-phase results of the four variables start 32 words apart modulo 64 (FP32), the least the
-    // wave's 64-bit stores can share banks.
-    constexpr bool T1_ROWWAVE = !(MODE == 4 && STAGE == 1 && sizeof(real) == 4);
-    constexpr int NRM_S = T1_ROWWAVE ? EXT1 : 48;
+    // [q^L_m, q^R_m, D_m, (dC/dt1)_m, C_m][t2 row][t1 position][Gauss line m]. A wave of the t1 phase takes
+    // one row of all four variables, 16 consecutive positions each; the variable blocks are padded to
+    // start 16 words apart modulo 64 (FP32; 32 in FP64, whose elements take two banks), so its reads
+    // meet no bank twice, and the t1-phase results of the four variables start 32 words apart modulo 64
+    // (FP32), the least the wave's 64-bit stores can share banks.
+    // PAIR_PREV: the FP32 stage-1 z pass, which sits at the register limit, keeps only its lane's two
+    // variables of the previous face's fluxes (the other passes keep all four: fewer selects per step).
+    constexpr bool PAIR_PREV = (MODE == 4 && STAGE == 1 && sizeof(real) == 4);
     struct NrmV {
-        real a[4][X2][NRM_S];
+        real a[4][X2][EXT1];
         real pad[16];
     };
     struct T1V {
@@ -230,12 +227,9 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
         for (int v = 0; v < 4; ++v) nxt[v] = a.q[v][idx];
     }
     const real dt = real(*a.dt_ptr);
-    real fprev0[4], fprev1[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        fprev0[v] = real(0);
-        fprev1[v] = real(0);
-    }
+    // the previous face's fluxes: all four variables, or (PAIR_PREV) only this lane's two
+    real fprev0[4] = {0, 0, 0, 0}, fprev1[4] = {0, 0, 0, 0};
+    real2 pprev0 = {0, 0}, pprev1 = {0, 0};
 
     const bool hi = m != 0;
     // tangential inverse widths, loaded once (a vector load inside the march would make the wait for
@@ -301,46 +295,39 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
         }
         __syncthreads();
         // ---- t1 phase: the 4 x 16 x X2 items (variable v, t2 row tk, t1 position tj) spread over all
-        // threads. Row-wave order: a thread keeps tj = tid % 16 and v = tid / 16 % 4 and takes the rows
+        // threads in row-wave order: a thread keeps tj = tid % 16 and v = tid / 16 % 4 and takes the rows
         // tid / 64 + k NTH / 64, so its LDS addresses move by a fixed step (no index arithmetic in the
-        // march); otherwise item it = tid + k NTH in (variable, row, position) order.
-        auto t1_item = [&](int v, int tk, int tj) {
-            real x[4][5];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[v].a[q][tk][tj + r];
-            real vm, vp;
-            weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
-            s_t1[v].a[0][tk][tj][0] = vm;
-            s_t1[v].a[0][tk][tj][1] = vp;
-            weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
-            s_t1[v].a[1][tk][tj][0] = vm;
-            s_t1[v].a[1][tk][tj][1] = vp;
-            quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
-            s_t1[v].a[2][tk][tj][0] = vm;
-            s_t1[v].a[2][tk][tj][1] = vp;
-            quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-            s_t1[v].a[3][tk][tj][0] = vm * ih1;
-            s_t1[v].a[3][tk][tj][1] = vp * ih1;
-            quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-            s_t1[v].a[4][tk][tj][0] = vm;
-            s_t1[v].a[4][tk][tj][1] = vp;
-        };
+        // march)
         static_assert(TILE1 == 16 && NTH % 64 == 0, "t1 items: 16 positions x 4 variables per wave");
-        if constexpr (T1_ROWWAVE) {
+        {
             constexpr int RSTEP = NTH / 64, NK = (X2 + RSTEP - 1) / RSTEP;
             const int tj = tid & 15, v = (tid >> 4) & 3;
 #pragma unroll
             for (int kk = 0; kk < NK; ++kk) {
                 const int tk = (tid >> 6) + kk * RSTEP;
-                if (X2 % RSTEP == 0 || tk < X2) t1_item(v, tk, tj);
-            }
-        } else {
-            constexpr int NT1 = TILE1 * X2;
-            for (int it = tid; it < 4 * NT1; it += NTH) {
-                const int v = it / NT1, item = it - v * NT1;
-                t1_item(v, item / TILE1, item % TILE1);
+                if (X2 % RSTEP == 0 || tk < X2) {
+                    real x[4][5];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[v].a[q][tk][tj + r];
+                    real vm, vp;
+                    weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
+                    s_t1[v].a[0][tk][tj][0] = vm;
+                    s_t1[v].a[0][tk][tj][1] = vp;
+                    weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
+                    s_t1[v].a[1][tk][tj][0] = vm;
+                    s_t1[v].a[1][tk][tj][1] = vp;
+                    quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
+                    s_t1[v].a[2][tk][tj][0] = vm;
+                    s_t1[v].a[2][tk][tj][1] = vp;
+                    quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+                    s_t1[v].a[3][tk][tj][0] = vm * ih1;
+                    s_t1[v].a[3][tk][tj][1] = vp * ih1;
+                    quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
+                    s_t1[v].a[4][tk][tj][0] = vm;
+                    s_t1[v].a[4][tk][tj][1] = vp;
+                }
             }
         }
         __syncthreads();
@@ -391,6 +378,17 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
             fa1[v] += __shfl_xor(fa1[v], 1);
             if (NEED_F0) fa0[v] += __shfl_xor(fa0[v], 1);
         }
+        // this lane's two variables of the face fluxes: global variables 2m and 2m + 1, local indices
+        // LOC[2m], LOC[2m + 1], picked by value with a per-lane select between compile-time indices
+        // (indexing a register array with the lane-dependent index would move it to scratch)
+        auto lane_pair = [&](const real (&x)[4]) -> real2 {
+            real2 r;
+            r.x = pick(hi, x[LOC[2]], x[LOC[0]]);
+            r.y = pick(hi, x[LOC[3]], x[LOC[1]]);
+            return r;
+        };
+        const real2 fcur1 = lane_pair(fa1);
+        const real2 fcur0 = NEED_F0 ? lane_pair(fa0) : real2{0, 0};
         if (f > f0 && face_ok) {
             const int cell = f - 1;
             const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
@@ -404,11 +402,13 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
             // lane-dependent index would fetch pointers from memory and move the arrays to scratch.
             real2 d1, d0;
             const real ihc = STR ? a.ihc[cell] : a.inv_hn;
-            d1.x = -(pick(hi, fa1[LOC[2]], fa1[LOC[0]]) - pick(hi, fprev1[LOC[2]], fprev1[LOC[0]])) * ihc;
-            d1.y = -(pick(hi, fa1[LOC[3]], fa1[LOC[1]]) - pick(hi, fprev1[LOC[3]], fprev1[LOC[1]])) * ihc;
+            const real2 prev1 = PAIR_PREV ? pprev1 : lane_pair(fprev1);
+            d1.x = -(fcur1.x - prev1.x) * ihc;
+            d1.y = -(fcur1.y - prev1.y) * ihc;
             if (NEED_F0) {
-                d0.x = -(pick(hi, fa0[LOC[2]], fa0[LOC[0]]) - pick(hi, fprev0[LOC[2]], fprev0[LOC[0]])) * ihc;
-                d0.y = -(pick(hi, fa0[LOC[3]], fa0[LOC[1]]) - pick(hi, fprev0[LOC[3]], fprev0[LOC[1]])) * ihc;
+                const real2 prev0 = PAIR_PREV ? pprev0 : lane_pair(fprev0);
+                d0.x = -(fcur0.x - prev0.x) * ihc;
+                d0.y = -(fcur0.y - prev0.y) * ihc;
             } else {
                 d0.x = d0.y = real(0);
             }
@@ -484,10 +484,15 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 }
             }
         }
+        if constexpr (PAIR_PREV) {
+            pprev1 = fcur1;
+            if (NEED_F0) pprev0 = fcur0;
+        } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            fprev1[v] = fa1[v];
-            if (NEED_F0) fprev0[v] = fa0[v];
+            for (int v = 0; v < 4; ++v) {
+                fprev1[v] = fa1[v];
+                if (NEED_F0) fprev0[v] = fa0[v];
+            }
         }
     }
     }  // segments
