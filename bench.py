@@ -41,8 +41,8 @@ PEAK_HBM_GBS = 8000.0
 # reports null once they differ.
 TRAFFIC = {
     5: {"sources": ("gks_stage.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "e04849bc7d4143c90e4cab16f659ab14baa1ae741b2ab51aca73d60918d94b65",
-         "fetch_bytes": 191_357_663, "write_bytes": 84_963_633},
+         "sources_sha256": "231c17131be534ff89f16fca6c5dd7cd445b185a47cac350e12eab1dbd2df8be",
+         "fetch_bytes": 197_497_908, "write_bytes": 84_954_526},
     2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
          "sources_sha256": "896e29c2d953450ebfdd919850eeb1b148694f3ff2158b1f2b129a713ca2f4a7",
          "fetch_bytes": 102_100_143, "write_bytes": 76_769_213},

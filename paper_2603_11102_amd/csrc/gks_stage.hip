@@ -17,8 +17,9 @@
 //     dQ/dt2 in registers (one thread per face and Gauss line);
 //   * flux phase: closed-form flux per Gauss point, quadrature over the face, divergence against the
 //     previous face of the column, and the accumulation (or the S2O4 epilogue in the last direction).
-// No face flux is written to memory. Two workgroup barriers per face step; LDS holds all four
-// variables (78 KB in FP32, 93 KB in FP64, of the 160 KB per CU).
+// No face flux is written to memory. FP32 runs the phases as a software pipeline over two LDS buffers
+// (the face step of f, the t1 phase of f + 1 and the column phase of f + 2 between two barriers; 155 KB of
+// the 160 KB per CU); FP64 runs them in turn with two barriers per face step (93 KB).
 #include <algorithm>
 
 #include "gks_internal.h"
@@ -68,6 +69,18 @@ struct LocalOrder<4> {
     static constexpr int v[4] = {0, 2, 3, 1};
 };
 
+// The value of the partner lane (lane ^ 1; all lanes are active where it is used). FP32, bound by VALU
+// issue, moves it through the LDS crossbar (ds_bpermute), off the VALU; FP64, bound by latency at one
+// wave per SIMD, takes it with a DPP quad permutation [1, 0, 3, 2] on the VALU, without the LDS round trip
+// (with the crossbar the compiler waited for each value in turn).
+__device__ __forceinline__ float pair_swap(float x) { return __shfl_xor(x, 1); }
+__device__ __forceinline__ double pair_swap(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffu), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Error-free sum (Knuth): s + e == a + b exactly, s = fl(a + b).
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     s = a + b;
@@ -111,8 +124,11 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
         real a[5][X2][TILE1][2];
         real pad[sizeof(real) == 4 ? 32 : 2];
     };
-    __shared__ NrmV s_nrm[4];
-    __shared__ T1V s_t1[4];
+    // DB (FP32): two LDS buffers, so that the phases of consecutive faces overlap (FP64 has no room)
+    constexpr bool DB = sizeof(real) == 4;
+    constexpr int NB = DB ? 2 : 1;
+    __shared__ NrmV s_nrm[NB][4];
+    __shared__ T1V s_t1[NB][4];
 
     const int tid = threadIdx.x;
     // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
@@ -237,32 +253,37 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
     // whose t1 position is tid % TILE1 for every item
     const real ih2 = STR ? a.ih2[min(k0 + fk, a.n_t2 - 1)] : a.inv_h2;
     const real ih1 = STR ? a.ih1[min(j0 + tid % TILE1, a.n_t1 - 1)] : a.inv_h1;
-    for (int f = f0; f <= f1; ++f) {
-        const real ihf_f = STR ? a.ihf[f] : a.inv_hn;  // inverse spacing at face f (normal derivative)
-        // epilogue operands of cell f - 1 (z pass), loaded here so that their latency overlaps the step
-        real2 e_r0 = {0, 0}, e_r1 = {0, 0}, e_x0 = {0, 0}, e_x1 = {0, 0}, e_lo = {0, 0};
-        real e_q[2] = {0, 0};
+    // epilogue operands (z pass) of cell f - 1
+    struct Epi {
+        real2 r0, r1, x0, x1, lo;
+        real q[2];
+    };
+    auto epi_load = [&](int f, Epi& ep) {
         if constexpr (EPI_PREFETCH && MODE == 4) {
-            // loaded on every path (for the same reason as the column prefetch): at f = f0 and for faces
-            // outside the domain a clamped cell is read and its values are not used
-            const int cell = max(f - 1, 0), je = min(j0 + fj, a.n_t1 - 1), ke = min(k0 + fk, a.n_t2 - 1);
+            // loaded on every path (for the same reason as the column prefetch): at f = f0, one face past
+            // the march and for faces outside the domain a clamped cell is read and its values are not used
+            const int cell = min(max(f - 1, 0), a.n_n - 1), je = min(j0 + fj, a.n_t1 - 1), ke = min(k0 + fk, a.n_t2 - 1);
             const long long ridx = (long long)cell * a.ist_n + (long long)je * a.ist_t1 + (long long)ke * a.ist_t2;
             const long long pidx = a.pad0 + (long long)cell * a.st_n + (long long)je * a.st_t1 + (long long)ke * a.st_t2;
             const long long xidx = rx_block_index(je, ke, cell, a.rx_nx, a.rx_nyb);
-            e_r1 = ld2(a.r1, ridx, m);
-            e_x1 = ld2(a.rx1, xidx, m);
-            if (COMPENSATED) e_lo = ld2(a.lo_in, ridx, m);
+            ep.r1 = ld2(a.r1, ridx, m);
+            ep.x1 = ld2(a.rx1, xidx, m);
+            if (COMPENSATED) ep.lo = ld2(a.lo_in, ridx, m);
             if (NEED_F0) {
-                e_r0 = ld2(a.r0, ridx, m);
-                e_x0 = ld2(a.rx0, xidx, m);
+                ep.r0 = ld2(a.r0, ridx, m);
+                ep.x0 = ld2(a.rx0, xidx, m);
             }
 #pragma unroll
             for (int vv = 0; vv < 2; ++vv) {
                 const real* const src = NEED_F0 ? pick(hi, a.q_c[LOC[2 + vv]], a.q_c[LOC[vv]])
                                                 : pick(hi, a.s_in[LOC[2 + vv]], a.s_in[LOC[vv]]);
-                e_q[vv] = src[pidx];
+                ep.q[vv] = src[pidx];
             }
         }
+    };
+    // column phase of face f into LDS buffer buf
+    auto column_step = [&](int f, int buf) {
+        const real ihf_f = STR ? a.ihf[f] : a.inv_hn;  // inverse spacing at face f (normal derivative)
         // ---- column phase (all variables): window cells f-2 .. f+2, prefetch cell f+3
         if (col) {
 #pragma unroll
@@ -286,14 +307,16 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 const real qL = carry[v];
                 const real D = (ring[v][0] - real(15) * ring[v][1] + real(15) * ring[v][2] - ring[v][3]) *
                                (real(1.0 / 12.0) * ihf_f);
-                s_nrm[v].a[0][c2][c1] = qL;
-                s_nrm[v].a[1][c2][c1] = left;
-                s_nrm[v].a[2][c2][c1] = D;
-                s_nrm[v].a[3][c2][c1] = real(0.5) * (qL + left);
+                s_nrm[buf][v].a[0][c2][c1] = qL;
+                s_nrm[buf][v].a[1][c2][c1] = left;
+                s_nrm[buf][v].a[2][c2][c1] = D;
+                s_nrm[buf][v].a[3][c2][c1] = real(0.5) * (qL + left);
                 carry[v] = right;
             }
         }
-        __syncthreads();
+    };
+    // t1 phase of LDS buffer buf
+    auto t1_step = [&](int buf) {
         // ---- t1 phase: the 4 x 16 x X2 items (variable v, t2 row tk, t1 position tj) spread over all
         // threads in row-wave order: a thread keeps tj = tid % 16 and v = tid / 16 % 4 and takes the rows
         // tid / 64 + k NTH / 64, so its LDS addresses move by a fixed step (no index arithmetic in the
@@ -310,27 +333,29 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[v].a[q][tk][tj + r];
+                        for (int r = 0; r < 5; ++r) x[q][r] = s_nrm[buf][v].a[q][tk][tj + r];
                     real vm, vp;
                     weno_gauss<real>(x[0][0], x[0][1], x[0][2], x[0][3], x[0][4], eps, vm, vp);
-                    s_t1[v].a[0][tk][tj][0] = vm;
-                    s_t1[v].a[0][tk][tj][1] = vp;
+                    s_t1[buf][v].a[0][tk][tj][0] = vm;
+                    s_t1[buf][v].a[0][tk][tj][1] = vp;
                     weno_gauss<real>(x[1][0], x[1][1], x[1][2], x[1][3], x[1][4], eps, vm, vp);
-                    s_t1[v].a[1][tk][tj][0] = vm;
-                    s_t1[v].a[1][tk][tj][1] = vp;
+                    s_t1[buf][v].a[1][tk][tj][0] = vm;
+                    s_t1[buf][v].a[1][tk][tj][1] = vp;
                     quartic_gauss_value<real>(x[2][0], x[2][1], x[2][2], x[2][3], x[2][4], vm, vp);
-                    s_t1[v].a[2][tk][tj][0] = vm;
-                    s_t1[v].a[2][tk][tj][1] = vp;
+                    s_t1[buf][v].a[2][tk][tj][0] = vm;
+                    s_t1[buf][v].a[2][tk][tj][1] = vp;
                     quartic_gauss_deriv<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-                    s_t1[v].a[3][tk][tj][0] = vm * ih1;
-                    s_t1[v].a[3][tk][tj][1] = vp * ih1;
+                    s_t1[buf][v].a[3][tk][tj][0] = vm * ih1;
+                    s_t1[buf][v].a[3][tk][tj][1] = vp * ih1;
                     quartic_gauss_value<real>(x[3][0], x[3][1], x[3][2], x[3][3], x[3][4], vm, vp);
-                    s_t1[v].a[4][tk][tj][0] = vm;
-                    s_t1[v].a[4][tk][tj][1] = vp;
+                    s_t1[buf][v].a[4][tk][tj][0] = vm;
+                    s_t1[buf][v].a[4][tk][tj][1] = vp;
                 }
             }
         }
-        __syncthreads();
+    };
+    // t2 phase, flux and residual (or stage update) of face f from LDS buffer buf
+    auto face_step = [&](int f, int buf, const Epi& ep) {
         // ---- t2 phase: per thread one face and one Gauss line, all variables
         real gp[4][2][5];  // [variable][Gauss n][q^L, q^R, d/dn, d/dt1, d/dt2]
 #pragma unroll
@@ -339,7 +364,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
 #pragma unroll
             for (int q = 0; q < 5; ++q)
 #pragma unroll
-                for (int r = 0; r < 5; ++r) y[q][r] = s_t1[v].a[q][fk + r][fj][m];
+                for (int r = 0; r < 5; ++r) y[q][r] = s_t1[buf][v].a[q][fk + r][fj][m];
             real vm, vp;
             weno_gauss<real>(y[0][0], y[0][1], y[0][2], y[0][3], y[0][4], eps, vm, vp);
             gp[v][0][0] = vm;
@@ -375,8 +400,8 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            fa1[v] += __shfl_xor(fa1[v], 1);
-            if (NEED_F0) fa0[v] += __shfl_xor(fa0[v], 1);
+            fa1[v] += pair_swap(fa1[v]);
+            if (NEED_F0) fa0[v] += pair_swap(fa0[v]);
         }
         // this lane's two variables of the face fluxes: global variables 2m and 2m + 1, local indices
         // LOC[2m], LOC[2m + 1], picked by value with a per-lane select between compile-time indices
@@ -422,10 +447,10 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
             } else {
                 real2 r1v, x1v, r0v = {0, 0}, x0v = {0, 0};
                 if constexpr (EPI_PREFETCH) {
-                    r1v = e_r1;
-                    x1v = e_x1;
-                    r0v = e_r0;
-                    x0v = e_x0;
+                    r1v = ep.r1;
+                    x1v = ep.x1;
+                    r0v = ep.r0;
+                    x0v = ep.x0;
                 } else {
                     const long long xidx = rx_block_index(j0 + fj, k0 + fk, cell, a.rx_nx, a.rx_nyb);
                     r1v = ld2(a.r1, ridx, m);
@@ -440,7 +465,7 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 if constexpr (COMPENSATED) {
                     // FP32: the state is carried as hi + lo; each update is an error-free sum of the
                     // stored high part and (low part + increment)
-                    const real lo[2] = {e_lo.x, e_lo.y};
+                    const real lo[2] = {ep.lo.x, ep.lo.y};
                     real2 la = {0, 0}, lb = {0, 0};
 #pragma unroll
                     for (int vv = 0; vv < 2; ++vv) {
@@ -448,17 +473,17 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                         float sh, sl;
                         if (NEED_F0) {
                             real* const outb = pick(hi, a.out_b[LOC[2 + vv]], a.out_b[LOC[vv]]);
-                            two_sum(e_q[vv], lo[vv] + (real(0.5) * dt * L0[vv] + real(0.125) * dt * dt * L1[vv]), sh, sl);
+                            two_sum(ep.q[vv], lo[vv] + (real(0.5) * dt * L0[vv] + real(0.125) * dt * dt * L1[vv]), sh, sl);
                             outa[pidx] = sh;
                             if (vv == 0) la.x = sl; else la.y = sl;
-                            two_sum(e_q[vv], lo[vv] + (dt * L0[vv] + (dt * dt * real(1.0 / 6.0)) * L1[vv]), sh, sl);
+                            two_sum(ep.q[vv], lo[vv] + (dt * L0[vv] + (dt * dt * real(1.0 / 6.0)) * L1[vv]), sh, sl);
                             outb[pidx] = sh;
                             if (vv == 0) lb.x = sl; else lb.y = sl;
                         } else {
                             // body force G on the momenta (global variables 1..3)
                             const real gv = pick(hi, a.g_global[1 + vv], vv == 1 ? a.g_global[0] : real(0));
                             const real add = (dt * dt * real(1.0 / 3.0)) * L1[vv] + dt * gv;
-                            two_sum(e_q[vv], lo[vv] + add, sh, sl);
+                            two_sum(ep.q[vv], lo[vv] + add, sh, sl);
                             outa[pidx] = sh;
                             if (vv == 0) la.x = sl; else la.y = sl;
                         }
@@ -471,14 +496,14 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                     for (int vv = 0; vv < 2; ++vv) {
                         real* const outa = pick(hi, a.out_a[LOC[2 + vv]], a.out_a[LOC[vv]]);
                         if (NEED_F0) {
-                            const real Q = e_q[vv];
+                            const real Q = ep.q[vv];
                             real* const outb = pick(hi, a.out_b[LOC[2 + vv]], a.out_b[LOC[vv]]);
                             outa[pidx] = Q + real(0.5) * dt * L0[vv] + real(0.125) * dt * dt * L1[vv];
                             outb[pidx] = Q + dt * L0[vv] + (dt * dt * real(1.0 / 6.0)) * L1[vv];
                         } else {
                             const real gv = pick(hi, a.g_global[1 + vv], vv == 1 ? a.g_global[0] : real(0));
                             const real add = (dt * dt * real(1.0 / 3.0)) * L1[vv] + dt * gv;
-                            outa[pidx] = e_q[vv] + add;
+                            outa[pidx] = ep.q[vv] + add;
                         }
                     }
                 }
@@ -493,6 +518,38 @@ __global__ void __launch_bounds__(FaceTile<real>::THREADS) face_kernel(const Fac
                 fprev1[v] = fa1[v];
                 if (NEED_F0) fprev0[v] = fa0[v];
             }
+        }
+    };
+    if constexpr (DB) {
+        // software pipeline over two LDS buffers with one barrier per face: the face step of f reads
+        // s_t1[buf], the t1 phase of f + 1 reads s_nrm[buf ^ 1] and writes s_t1[buf ^ 1], the column
+        // phase of f + 2 writes s_nrm[buf]; each buffer was last read or written before the previous
+        // barrier. The epilogue operands of the next face step are loaded one step ahead. Waves whose
+        // column phase is light (400 columns on 512 threads) go on to the next face's work.
+        Epi ep = {};
+        epi_load(f0, ep);
+        column_step(f0, 0);
+        __syncthreads();
+        t1_step(0);
+        column_step(f0 + 1, 1);
+        __syncthreads();
+        for (int f = f0; f <= f1; ++f) {
+            const int buf = (f - f0) & 1;
+            face_step(f, buf, ep);
+            epi_load(f + 1, ep);
+            if (f + 1 <= f1) t1_step(buf ^ 1);
+            if (f + 2 <= f1) column_step(f + 2, buf);
+            __syncthreads();
+        }
+    } else {
+        for (int f = f0; f <= f1; ++f) {
+            Epi ep = {};
+            epi_load(f, ep);
+            column_step(f, 0);
+            __syncthreads();
+            t1_step(0);
+            __syncthreads();
+            face_step(f, 0, ep);
         }
     }
     }  // segments
