@@ -44,8 +44,8 @@ TRAFFIC = {
          "sources_sha256": "231c17131be534ff89f16fca6c5dd7cd445b185a47cac350e12eab1dbd2df8be",
          "fetch_bytes": 197_497_908, "write_bytes": 84_954_526},
     2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "896e29c2d953450ebfdd919850eeb1b148694f3ff2158b1f2b129a713ca2f4a7",
-         "fetch_bytes": 102_100_143, "write_bytes": 76_769_213},
+         "sources_sha256": "0f67d09f6fc0c18b338004a48a391491922317fa37a684361a037c156d14a604",
+         "fetch_bytes": 102_163_699, "write_bytes": 77_066_262},
 }
 
 

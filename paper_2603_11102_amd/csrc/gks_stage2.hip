@@ -9,7 +9,9 @@
 // states, the normal derivative and the face average C to LDS. Threads 0..255 own one face each: they
 // read their column's states and the four neighbouring face averages, evaluate the flux and the
 // divergence against the previous face of the column, and run the same epilogue roles as the
-// high-order face pass (x: blocked residual, y: main residual, z: S2O4 stage update).
+// high-order face pass (x: blocked residual, y: main residual, z: S2O4 stage update). FP32 keeps two
+// LDS buffers of face states, so that the face phase of one face and the column phase of the next run
+// between one pair of barriers (one barrier per face); FP64 runs them in turn.
 #include "gks_internal.h"
 
 namespace gks {
@@ -85,7 +87,8 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     constexpr bool COMP = sizeof(real) == 4;  // FP32: compensated state in the z-pass stage update
     constexpr int LOC[4] = {LocalOrder2<MODE>::v[0], LocalOrder2<MODE>::v[1], LocalOrder2<MODE>::v[2],
                             LocalOrder2<MODE>::v[3]};
-    __shared__ real s_face[4][4][T2O_EXT][T2O_EXT];  // [variable][q^L, q^R, D, C][t2][t1]
+    constexpr bool DB2 = sizeof(real) == 4;
+    __shared__ real s_face[DB2 ? 2 : 1][4][4][T2O_EXT][T2O_EXT];  // [buffer][variable][q^L, q^R, D, C][t2][t1]
 
     const int tid = threadIdx.x;
     // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
@@ -176,7 +179,8 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     const real ih1 = STR ? a.ih1[min(j0 + fj, a.n_t1 - 1)] : a.inv_h1;
     const real ih2 = STR ? a.ih2[min(k0 + fk, a.n_t2 - 1)] : a.inv_h2;
 
-    for (int f = f0; f <= f1; ++f) {
+    // column phase of face f into LDS buffer buf
+    auto column_step = [&](int f, int buf) {
         const real ihf_f = STR ? a.ihf[f] : a.inv_hn;  // inverse spacing at face f (normal derivative)
         // ---- column phase: window cells f-2 .. f+1 (prefetch f+2)
         if (col) {
@@ -197,13 +201,25 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const real qm2 = ring[v][0], qm1 = ring[v][1], q0 = ring[v][2], qp1 = ring[v][3];
-                s_face[v][0][c2][c1] = qm1 + real(0.5) * van_leer(qm1 - qm2, q0 - qm1);
-                s_face[v][1][c2][c1] = q0 - real(0.5) * van_leer(q0 - qm1, qp1 - q0);
-                s_face[v][2][c2][c1] = (q0 - qm1) * ihf_f;
-                s_face[v][3][c2][c1] = real(0.5) * (qm1 + q0);
+                s_face[buf][v][0][c2][c1] = qm1 + real(0.5) * van_leer(qm1 - qm2, q0 - qm1);
+                s_face[buf][v][1][c2][c1] = q0 - real(0.5) * van_leer(q0 - qm1, qp1 - q0);
+                s_face[buf][v][2][c2][c1] = (q0 - qm1) * ihf_f;
+                s_face[buf][v][3][c2][c1] = real(0.5) * (qm1 + q0);
             }
         }
+    };
+    // DB2 (FP32): two LDS buffers, one barrier per face: the face phase of f reads buffer f mod 2 while
+    // the column phase of f + 1 fills the other; FP64 keeps one buffer (two would halve its occupancy)
+    if constexpr (DB2) {
+        column_step(f0, 0);
         __syncthreads();
+    }
+    for (int f = f0; f <= f1; ++f) {
+        const int buf = DB2 ? ((f - f0) & 1) : 0;
+        if constexpr (!DB2) {
+            column_step(f, 0);
+            __syncthreads();
+        }
         // ---- face phase: flux at the face centre (weight 1)
         real fa0[4] = {0, 0, 0, 0}, fa1[4] = {0, 0, 0, 0};
         if (face) {
@@ -211,15 +227,19 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             real qL[4], qR[4], g[3][4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                qL[v] = s_face[v][0][ck][cj];
-                qR[v] = s_face[v][1][ck][cj];
-                g[0][v] = s_face[v][2][ck][cj];
-                g[1][v] = (s_face[v][3][ck][cj + 1] - s_face[v][3][ck][cj - 1]) * (real(0.5) * ih1);
-                g[2][v] = (s_face[v][3][ck + 1][cj] - s_face[v][3][ck - 1][cj]) * (real(0.5) * ih2);
+                qL[v] = s_face[buf][v][0][ck][cj];
+                qR[v] = s_face[buf][v][1][ck][cj];
+                g[0][v] = s_face[buf][v][2][ck][cj];
+                g[1][v] = (s_face[buf][v][3][ck][cj + 1] - s_face[buf][v][3][ck][cj - 1]) * (real(0.5) * ih1);
+                g[2][v] = (s_face[buf][v][3][ck + 1][cj] - s_face[buf][v][3][ck - 1][cj]) * (real(0.5) * ih2);
             }
             gp_flux<real, NEED_F0, SHIFT>(qL, qR, g, a.fc, real(1), fa0, fa1, cm);
         }
-        __syncthreads();  // the next column phase overwrites s_face
+        if constexpr (DB2) {
+            if (f + 1 <= f1) column_step(f + 1, buf ^ 1);
+        } else {
+            __syncthreads();  // the next column phase overwrites s_face
+        }
         if (f > f0 && face_ok) {
             const int cell = f - 1;
             const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
@@ -295,6 +315,7 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             fprev1[v] = fa1[v];
             if (NEED_F0) fprev0[v] = fa0[v];
         }
+        if constexpr (DB2) __syncthreads();
     }
 }
 
