@@ -44,7 +44,7 @@ TRAFFIC = {
          "sources_sha256": "231c17131be534ff89f16fca6c5dd7cd445b185a47cac350e12eab1dbd2df8be",
          "fetch_bytes": 197_497_908, "write_bytes": 84_954_526},
     2: {"sources": ("gks_stage2.hip", "gks_device.h", "gks_internal.h"),
-         "sources_sha256": "0f67d09f6fc0c18b338004a48a391491922317fa37a684361a037c156d14a604",
+         "sources_sha256": "8d5906e99bf19247d8bea11a23e4b01fef46cdf6bf5fbb341931ecfb6df876bf",
          "fetch_bytes": 102_163_699, "write_bytes": 77_066_262},
 }
 

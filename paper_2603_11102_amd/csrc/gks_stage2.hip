@@ -9,9 +9,9 @@
 // states, the normal derivative and the face average C to LDS. Threads 0..255 own one face each: they
 // read their column's states and the four neighbouring face averages, evaluate the flux and the
 // divergence against the previous face of the column, and run the same epilogue roles as the
-// high-order face pass (x: blocked residual, y: main residual, z: S2O4 stage update). FP32 keeps two
-// LDS buffers of face states, so that the face phase of one face and the column phase of the next run
-// between one pair of barriers (one barrier per face); FP64 runs them in turn.
+// high-order face pass (x: blocked residual, y: main residual, z: S2O4 stage update). Two LDS buffers of
+// face states let the face phase of one face and the column phase of the next run between one pair of
+// barriers (one barrier per face).
 #include "gks_internal.h"
 
 namespace gks {
@@ -87,8 +87,7 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
     constexpr bool COMP = sizeof(real) == 4;  // FP32: compensated state in the z-pass stage update
     constexpr int LOC[4] = {LocalOrder2<MODE>::v[0], LocalOrder2<MODE>::v[1], LocalOrder2<MODE>::v[2],
                             LocalOrder2<MODE>::v[3]};
-    constexpr bool DB2 = sizeof(real) == 4;
-    __shared__ real s_face[DB2 ? 2 : 1][4][4][T2O_EXT][T2O_EXT];  // [buffer][variable][q^L, q^R, D, C][t2][t1]
+    __shared__ real s_face[2][4][4][T2O_EXT][T2O_EXT];  // [buffer][variable][q^L, q^R, D, C][t2][t1]
 
     const int tid = threadIdx.x;
     // consecutive logical workgroups run on the same XCD (the hardware deals workgroups round-robin to
@@ -208,18 +207,12 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             }
         }
     };
-    // DB2 (FP32): two LDS buffers, one barrier per face: the face phase of f reads buffer f mod 2 while
-    // the column phase of f + 1 fills the other; FP64 keeps one buffer (two would halve its occupancy)
-    if constexpr (DB2) {
-        column_step(f0, 0);
-        __syncthreads();
-    }
+    // two LDS buffers, one barrier per face: the face phase of f reads buffer f mod 2 while the column
+    // phase of f + 1 fills the other
+    column_step(f0, 0);
+    __syncthreads();
     for (int f = f0; f <= f1; ++f) {
-        const int buf = DB2 ? ((f - f0) & 1) : 0;
-        if constexpr (!DB2) {
-            column_step(f, 0);
-            __syncthreads();
-        }
+        const int buf = (f - f0) & 1;
         // ---- face phase: flux at the face centre (weight 1)
         real fa0[4] = {0, 0, 0, 0}, fa1[4] = {0, 0, 0, 0};
         if (face) {
@@ -235,11 +228,7 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             }
             gp_flux<real, NEED_F0, SHIFT>(qL, qR, g, a.fc, real(1), fa0, fa1, cm);
         }
-        if constexpr (DB2) {
-            if (f + 1 <= f1) column_step(f + 1, buf ^ 1);
-        } else {
-            __syncthreads();  // the next column phase overwrites s_face
-        }
+        if (f + 1 <= f1) column_step(f + 1, buf ^ 1);
         if (f > f0 && face_ok) {
             const int cell = f - 1;
             const long long ridx = (long long)cell * a.ist_n + (long long)(j0 + fj) * a.ist_t1 +
@@ -315,7 +304,7 @@ __global__ void __launch_bounds__(T2O_THREADS) face2_kernel(const FaceArgs<real>
             fprev1[v] = fa1[v];
             if (NEED_F0) fprev0[v] = fa0[v];
         }
-        if constexpr (DB2) __syncthreads();
+        __syncthreads();
     }
 }
 
